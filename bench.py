@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the lookup-table stiffness assembly on one MI355X.
+
+A step is one pass of the assembly path over the synthetic workload: the FP64
+macro-field fit, the MFMA contraction of eq. (58) and the deterministic scatter
+into the CSR structure (plan, CSR structure and lookup table are built once,
+outside the timed region, as in the paper's timing convention).  Inputs are
+resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0).  See the design doc for the roofline figures and the
+CPU-baseline protocol.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tile stiffness blocks/s + % MFMA peak; mixed/learned vs plain FP64 @ rel.err"
+PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16x3": 2.5e15, "f16x3": 2.5e15}   # dense MFMA, FLOP/s
+HBM_PEAK = 8.0e12
+WORKLOADS = {
+    "cfg3": "torus sector, 32x32x32 tiles, degree-2 macro map, degree-2 3x3x3-element tile, q=2",
+    "cfg2": "curved cantilever, 16x4x4 tiles, degree-3 macro map, degree-3 4x4x4-element tile, q=3",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def pmc_traffic(kernel_src, config, prec):
+    """HBM bytes per launch of the contraction from a committed rocprofv3 --pmc summary, or None if
+    absent or taken on a different version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", f"contract_{prec}_{config}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != source_hash(kernel_src):
+        return None
+    return float(b.group(1))
+
+
+def time_stages(torch, plan, w, prec, steps, warmup, ws):
+    cb, bb = plan.workspace_bytes(prec)
+    coef = ws
+    blocks = ws.view(torch.uint8)[cb:].view(torch.float64 if prec == "f64" else torch.float32)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    vals = torch.empty(plan.nnz, dtype=dt, device="cuda")
+    for _ in range(warmup):
+        plan.fit(w.E, w.nu, prec, out=coef)
+        plan.contract(coef, prec, out=blocks)
+        plan.scatter(blocks, prec, out=vals)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record()
+        plan.fit(w.E, w.nu, prec, out=coef)
+        ev[s][1].record()
+        plan.contract(coef, prec, out=blocks)
+        ev[s][2].record()
+        plan.scatter(blocks, prec, out=vals)
+        ev[s][3].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.check()
+    st = np.array([[ev[s][i].elapsed_time(ev[s][i + 1]) for i in range(3)] for s in range(steps)])
+    return {"wall_s": wall, "fit_ms": st[:, 0], "contract_ms": st[:, 1], "scatter_ms": st[:, 2],
+            "step_ms": st.sum(axis=1)}, vals, blocks
+
+
+def cpu_baseline(w, n_sample, seed=11):
+    """The CPU oracle on a seeded sample of tiles: fit + table contraction + CSR scatter of the sample."""
+    from oracle import assembly, projection, tables
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    pairs = tables.pair_set(w.tile)
+    table = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)     # prebuilt, not timed
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(w.n_tiles, size=n_sample, replace=False))
+    t0 = time.perf_counter()
+    coefs = projection.all_coefficients(w, sample)
+    blocks = assembly.tile_blocks(table, coefs)
+    rows, cols, vals = assembly.coo_entries(w, pairs, blocks, sample)
+    assembly.csr_from_coo(3 * int(np.prod([w.tiles[k] * (w.tile.n_ctrl[k] - 1) + 1 for k in range(3)])),
+                          rows, cols, vals)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "tile blocks/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_sample} seeded tiles of the same workload (fit + contraction + CSR of the sample), "
+                      f"{dt:.1f} s; host has {os.cpu_count()} logical CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="cfg3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precisions", default="f64,f32,bf16x3,f16x3")
+    ap.add_argument("--cpu-tiles", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2107_09568_amd as P
+
+    w = W.make(args.config)
+    log(f"bench: {args.config} plan")
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    torch.cuda.synchronize()
+    M, K, N = plan.n_pairs, plan.n_cols, 9 * plan.n_tiles
+    flops = 2.0 * M * K * N
+
+    precs = args.precisions.split(",")
+    results = {}
+    ref_blocks = None
+    rng = np.random.default_rng(5)
+    sample = torch.from_numpy(np.sort(rng.choice(plan.n_tiles, size=min(512, plan.n_tiles), replace=False))).cuda()
+    for prec in precs:
+        log(f"bench: {prec}")
+        cb, bb = plan.workspace_bytes(prec)
+        ws = plan._empty_bytes(cb + bb)
+        r, vals, blocks = time_stages(torch, plan, w, prec, args.steps, args.warmup, ws)
+        blk = blocks[: plan.n_tiles * M * 9].view(plan.n_tiles, M, 9)[sample].double()
+        if prec == "f64":
+            ref_blocks = blk
+            err = 0.0
+        else:
+            d = (blk - ref_blocks).reshape(len(sample), -1).norm(dim=1) / ref_blocks.reshape(len(sample), -1).norm(dim=1)
+            err = d.max().item()
+        results[prec] = (r, err)
+        del ws, vals, blocks, blk
+        torch.cuda.empty_cache()
+
+    main_prec = precs[0]
+    r, _ = results[main_prec]
+    step_ms = float(np.median(r["step_ms"]))
+    con_ms = float(np.mean(r["contract_ms"]))
+    achieved = flops / (con_ms * 1e-3)
+    kernel_src = os.path.join(ROOT, "paper_2107_09568_amd", "csrc", "contract.hip")
+    traffic = pmc_traffic(kernel_src, args.config, main_prec)
+    out = {
+        "metric": METRIC,
+        "value": plan.n_tiles / (step_ms * 1e-3),
+        "unit": "tile blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_prec,
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "name": args.config, "n_tiles": plan.n_tiles,
+                   "n_pairs": M, "table_cols": K, "nnz": plan.nnz, "precision": main_prec},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[main_prec] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[main_prec], "traffic": traffic,
+                     "kernel": f"contract_kernel<{main_prec}>", "flops_per_launch": flops,
+                     "avg_launch_ms": con_ms},
+        "stages_ms": {k[:-3]: float(np.median(v)) for k, v in r.items() if k.endswith("_ms")},
+        "blocks_per_s_nonzeros_only": plan.n_tiles / (float(np.median(r["fit_ms"] + r["contract_ms"])) * 1e-3),
+    }
+    variants = {}
+    f64_ms = float(np.median(results["f64"][0]["step_ms"])) if "f64" in results else None
+    for prec, (rr, err) in results.items():
+        sm = float(np.median(rr["step_ms"]))
+        cm = float(np.mean(rr["contract_ms"]))
+        variants[prec] = {"ms_per_step": sm, "tile_blocks_per_s": plan.n_tiles / (sm * 1e-3),
+                          "speedup_vs_f64": f64_ms / sm if f64_ms else None,
+                          "contract_ms": cm, "contract_tflops": flops / (cm * 1e-3) / 1e12,
+                          "mfma_frac": flops / (cm * 1e-3) / PEAK[prec],
+                          "scatter_ms": float(np.median(rr["scatter_ms"])), "fit_ms": float(np.median(rr["fit_ms"])),
+                          "max_block_rel_err_vs_f64": err}
+    out["variants"] = variants
+    if not args.no_cpu:
+        log("bench: cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_tiles)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

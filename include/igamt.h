@@ -1,0 +1,252 @@
+/*
+ * igamt -- interpolation-and-lookup assembly of isogeometric stiffness matrices
+ * for microstructured geometries built by spline composition, on AMD MI355X
+ * (gfx950).  Method: Hirschler, Antolin, Buffa, "Fast and multiscale formation
+ * of isogeometric matrices of microstructured geometric models".
+ *
+ * C ABI.  Plain pointers and sizes only.  Conventions for every entry point:
+ *   - Return value: IGAMT_OK (0) or a negative igamt_status.  No C++ exception
+ *     crosses the boundary.  igamt_last_error() returns a description of the
+ *     last failure on the calling thread.
+ *   - "host" pointers are read during the call only; the plan keeps copies.
+ *   - "device" pointers are caller-owned device memory on the plan's device
+ *     (the device current at the first device call on the plan); the library
+ *     never frees them.
+ *   - stream is a hipStream_t (NULL = the default stream).  Device work is
+ *     queued asynchronously on it unless a function says it synchronises.
+ *   - Index conventions (tile-local and global) are stated in each comment;
+ *     "x fastest" means flat = i + n_x (j + n_y k).
+ */
+#ifndef IGAMT_H
+#define IGAMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t igamt_status;
+#define IGAMT_OK            0
+#define IGAMT_EINVAL       -1  /* invalid argument (knots, sizes, NaN, NULL) */
+#define IGAMT_ENOMEM       -2  /* device or host allocation failed */
+#define IGAMT_EDEGENERATE  -3  /* det J <= 0 (or not finite) at a fit/quadrature point */
+#define IGAMT_EHIP         -4  /* a HIP runtime call failed */
+#define IGAMT_ESHAPE       -5  /* buffer size does not match the plan */
+#define IGAMT_EUNSUPPORTED -6  /* valid input outside what this build implements */
+#define IGAMT_ESTATE       -7  /* call order violated (e.g. assemble before tables exist) */
+
+/* Arithmetic of the contraction (eq. (58)).  The fit is FP64 in every mode.
+ * F64     : FP64 operands, FP64 MFMA, FP64 output.
+ * F32     : FP32 operands, FP32 MFMA, FP32 output.
+ * BF16X3  : x = hi + lo in bfloat16 for table and coefficients, products
+ *           hi*hi + hi*lo + lo*hi, FP32 accumulation and output.
+ * F16X3   : the same in float16 with a power-of-two scale per table row and
+ *           per coefficient column, FP32 accumulation and output.            */
+typedef enum { IGAMT_F64 = 0, IGAMT_F32 = 1, IGAMT_BF16X3 = 2, IGAMT_F16X3 = 3 } igamt_precision;
+
+typedef struct igamt_plan igamt_plan;
+
+/* Trivariate B-spline (eq. (2)-(4)).  host memory.
+ * knots[k]: n_ctrl[k] + degree[k] + 1 values, clamped (first and last
+ * degree+1 values equal), non-decreasing, spanning [0, 1].
+ * ctrl: [n_ctrl[2]][n_ctrl[1]][n_ctrl[0]][3], x fastest.                     */
+typedef struct {
+  int32_t degree[3];
+  int32_t n_ctrl[3];
+  const double *knots[3];
+  const double *ctrl;
+} igamt_spline3d;
+
+/* Tile grid and method parameters.
+ * tiles[k]  : tiles per direction.  box_mode 0: tile i is the i-th non-empty
+ *             knot span of the macro map (eq. (5)-(8)), so tiles[k] must equal
+ *             the number of non-empty spans.  box_mode 1: uniform boxes of
+ *             size 1/tiles[k] in the macro parameter domain.
+ * q         : projection degree p_pi (eq. (21)), 0..6.
+ * n_fit     : Gauss-Legendre samples per direction for the projection,
+ *             >= q + 1 (q + 1 = interpolation at the Gauss nodes, which equals
+ *             the discrete L2 projection of eq. (23)-(24) with that rule).
+ * n_gauss   : Gauss-Legendre points per direction per micro element for the
+ *             lookup table (eq. (52)), 1..8.                                  */
+typedef struct {
+  int32_t tiles[3];
+  int32_t box_mode;
+  int32_t q;
+  int32_t n_fit;
+  int32_t n_gauss;
+} igamt_plan_desc;
+
+/* Sizes derived from a plan. */
+typedef struct {
+  int64_t n_tiles;        /* m_M */
+  int64_t n_tiles_pad;    /* m_M rounded up to a multiple of 16 */
+  int64_t n_pairs;        /* n_nz = |I_coo| (eq. (56)), rows of the table */
+  int64_t n_cols;         /* 9 (q+1)^3, columns of the table (eq. (57)) */
+  int64_t n_cols_pad;     /* n_cols rounded up to a multiple of 64 */
+  int64_t n_tile_ctrl;    /* n_T */
+  int64_t n_macro_ctrl;   /* macro control points */
+  int64_t n_global_ctrl;  /* global control points after gluing tiles */
+  int64_t n_dofs;         /* 3 n_global_ctrl */
+  int64_t nnz;            /* CSR entries, both triangles */
+} igamt_sizes;
+
+const char *igamt_last_error(void);
+
+/* --- plan (host integer setup; no device work) ---------------------------
+ * Validates both splines and the descriptor, computes tile boxes, the pair
+ * set I_coo (eq. (56): A <= B in tile-local x-fastest order, supports sharing
+ * a micro element, sorted by (A, B)), the glued global numbering
+ * G = (t_x (n_x-1) + i, t_y (n_y-1) + j, t_z (n_z-1) + k) x fastest, dof 3 G + a,
+ * and the CSR structure (full symmetric, sorted columns).
+ * Tile knots must have no repeated interior knot (IGAMT_EUNSUPPORTED), tile
+ * boundary control points must sit at the identity (Greville) positions so
+ * that tiles conform (IGAMT_EINVAL otherwise).  *out is owned by the caller
+ * and released with igamt_plan_destroy.                                     */
+igamt_status igamt_plan_create(const igamt_spline3d *macro, const igamt_spline3d *tile,
+                               const igamt_plan_desc *desc, igamt_plan **out);
+void igamt_plan_destroy(igamt_plan *plan);                       /* NULL-safe */
+igamt_status igamt_plan_sizes(const igamt_plan *plan, igamt_sizes *out);
+/* I_coo as host int32 [n_pairs][2]. */
+igamt_status igamt_plan_pairs(const igamt_plan *plan, int32_t *pairs);
+/* CSR structure into host buffers row_ptr int64 [n_dofs + 1], col_idx int32 [nnz]. */
+igamt_status igamt_plan_csr(const igamt_plan *plan, int64_t *row_ptr, int32_t *col_idx);
+/* The same CSR structure generated on the device (bit-identical). */
+igamt_status igamt_plan_csr_device(igamt_plan *plan, int64_t *d_row_ptr, int32_t *d_col_idx, void *stream);
+
+/* --- design updates (same topology) ------------------------------------------
+ * New macro control points [n_ctrl z][y][x][3], from host (on_device = 0) or
+ * device memory (on_device = 1).                                              */
+igamt_status igamt_set_macro_ctrl(igamt_plan *plan, const double *ctrl, int32_t on_device, void *stream);
+/* New reference-tile control points (host), same knots; tables must be rebuilt. */
+igamt_status igamt_set_tile_ctrl(igamt_plan *plan, const double *ctrl);
+
+/* --- lookup tables (eq. (52), (57)) ------------------------------------------
+ * Table layout (row-major): table[p][9 C + 3 i + j], p = pair index, C =
+ * c1 + (q+1)(c2 + (q+1) c3) the Bernstein index, i, j the derivative
+ * directions.  tables_build integrates eq. (52) on the device in FP64 with
+ * n_gauss points per direction per micro element.  tables_set / tables_get
+ * copy a caller device buffer double [n_pairs][n_cols].  After build or set,
+ * the FP32 and split BF16 / F16 copies used by the other precisions are
+ * derived on the device.                                                      */
+igamt_status igamt_tables_build(igamt_plan *plan, void *stream);
+igamt_status igamt_tables_set(igamt_plan *plan, const double *d_table, void *stream);
+igamt_status igamt_tables_get(const igamt_plan *plan, double *d_out, void *stream);
+/* Exact FP64 table rows for the listed pair indices (device int32 [n_rows]) into
+ * d_out double [n_rows][n_cols]; used to estimate the error of a learned table. */
+igamt_status igamt_tables_build_rows(igamt_plan *plan, const int32_t *d_rows, int32_t n_rows,
+                                     double *d_out, void *stream);
+
+/* --- the assembly path -----------------------------------------------------
+ * Workspace sizes (bytes) for the stage buffers of a precision:
+ *   coef  : the fitted coefficients in the contraction layout (below);
+ *   blocks: per-tile stiffness blocks, [n_tiles][n_pairs][9] of double (F64)
+ *           or float (other modes), entry [t][p][3 a + b] = K^(t)[(A,a),(B,b)]
+ *           for (A, B) = pairs[p].                                             */
+igamt_status igamt_workspace_bytes(const igamt_plan *plan, igamt_precision prec,
+                                   int64_t *coef_bytes, int64_t *blocks_bytes);
+
+/* Stage 1, the fit (Section 3.2.2, eq. (37), (42)): for every tile and every
+ * Gauss sample, J = J_M(a + h xi) diag(h), F = J^-1, D = det J and
+ * A_ij,ab = D (lam F_ia F_jb + mu (F_i . F_j) delta_ab + mu F_ib F_ja), then the
+ * Bernstein coefficients <A_ij,ab>_C.  lam, mu from E, nu (3-D isotropic).
+ * d_coef layout (element type by precision): column-major per tile,
+ *   F64 : double [n_tiles_pad][9 (a,b)][n_cols_pad (9C+3i+j)]
+ *   F32 : float  [same]
+ *   BF16X3: hi then lo, each uint16 (bfloat16 bits) [same]
+ *   F16X3 : hi then lo, each uint16 (float16 bits) [same], then float
+ *           inv_scale [n_tiles_pad][9]; hi + lo = coefficient / inv_scale with
+ *           inv_scale a power of two chosen per column.
+ * Padding tiles and columns are written as zeros.  A det J <= 0 raises the
+ * plan's degeneracy flag (reported by igamt_check).                          */
+igamt_status igamt_fit(igamt_plan *plan, double E, double nu, igamt_precision prec,
+                       void *d_coef, void *stream);
+/* Stage 2, the contraction of eq. (58) on MFMA: blocks[t][p][ab] =
+ * sum_k table[p][k] coef[t][ab][k].  Requires tables (ESTATE otherwise).     */
+igamt_status igamt_contract(igamt_plan *plan, igamt_precision prec, const void *d_coef,
+                            void *d_blocks, void *stream);
+/* Stage 3, deterministic scatter into the fixed CSR structure (step 4 of
+ * Section 3.2.4): value(3 G_A + a, 3 G_B + b) = sum over the tiles that hold both
+ * control points, in ascending tile index, of the block entry ((A,B) upper
+ * pair: [p][3a+b]; lower: [p(B,A)][3b+a]).  d_values double (F64) or float. */
+igamt_status igamt_scatter(igamt_plan *plan, igamt_precision prec, const void *d_blocks,
+                           void *d_values, void *stream);
+/* All three stages; d_workspace must hold coef_bytes + blocks_bytes (256-byte
+ * aligned sub-buffers, coef first).                                          */
+igamt_status igamt_assemble(igamt_plan *plan, double E, double nu, igamt_precision prec,
+                            void *d_values, void *d_workspace, void *stream);
+/* Synchronises the stream and reports a degenerate tile seen since the last
+ * check (IGAMT_EDEGENERATE, *bad_tile = smallest tile index) or IGAMT_OK.   */
+igamt_status igamt_check(igamt_plan *plan, void *stream, int64_t *bad_tile);
+
+/* --- sensitivities (Section 4.1.2, eq. (69)-(73)) ----------------------------
+ * d(u^T K^pi u)/d m for every macro control point m (u fixed), FP64 fit and
+ * fit-adjoint, contraction in FP64 (F64) or FP32 (F32).  Per tile the adjoint
+ * field W = table^T U, U[p][ab] = m_p u_(A,a) u_(B,b) (m_p = 2 if A < B else 1),
+ * is paired with dA/dm.  With u = K^-1 f and f independent of m, the
+ * compliance gradient is minus this.  d_u double [n_dofs]; d_grad double
+ * [n_macro_ctrl][3] (z, y, x order as ctrl); d_uKu double [1] (may be NULL).
+ * d_workspace: igamt_grad_workspace_bytes.                                   */
+igamt_status igamt_grad_workspace_bytes(const igamt_plan *plan, igamt_precision prec, int64_t *bytes);
+igamt_status igamt_uKu_grad(igamt_plan *plan, double E, double nu, igamt_precision prec,
+                            const double *d_u, double *d_grad, double *d_uKu,
+                            void *d_workspace, void *stream);
+
+/* Sparse matrix-vector product y = K x for the CSR produced above (support
+ * routine: rigid-mode checks, iterative solves).  F64: double values/x/y;
+ * F32: float.                                                                 */
+igamt_status igamt_spmv(igamt_precision prec, int64_t n_rows, const int64_t *d_row_ptr,
+                        const int32_t *d_col_idx, const void *d_values, const void *d_x,
+                        void *d_y, void *stream);
+
+/* --- learned tables ------------------------------------------------------------
+ * POD basis of a set of tables (not in the paper; replaces one table build per
+ * design of a parameterised tile family).  d_snap double [n_s][n_e] (n_e =
+ * n_pairs * n_cols, row-major tables).  Computes the mean, the Gram matrix of
+ * the centred snapshots (FP64, device), its eigenpairs (host), and the r
+ * leading modes.  Outputs: d_mean float [n_e], d_basis float [r][n_e]
+ * (orthonormal rows), h_sigma double [n_s] singular values (descending).
+ * d_work double: n_s * n_s + n_s * r.  Synchronises the stream.              */
+igamt_status igamt_pod_build(const double *d_snap, int32_t n_s, int64_t n_e, int32_t r,
+                             float *d_mean, float *d_basis, double *h_sigma, double *d_work, void *stream);
+/* Table of a design from POD coefficients: table = mean + basis^T c (FP32
+ * inputs, FP64 table written into the plan, then the precision copies).      */
+igamt_status igamt_table_from_pod(igamt_plan *plan, const float *d_mean, const float *d_basis,
+                                  int32_t r, const float *d_coeffs, void *stream);
+/* Relative Frobenius error of the plan's current table on listed rows against
+ * exact rows (d_exact double [n_rows][n_cols]); result to d_err double [1].   */
+igamt_status igamt_table_rows_error(const igamt_plan *plan, const int32_t *d_rows, int32_t n_rows,
+                                    const double *d_exact, double *d_err, void *stream);
+
+/* Multilayer perceptron x -> GELU(x W1 + b1) -> ... -> x W_L + b_L (no
+ * activation on the last layer), GELU(z) = 0.5 z (1 + erf(z / sqrt 2)).
+ * Parameters are one flat float buffer [W1 (in x out, row-major), b1, W2, b2,
+ * ...].  widths[0..n_layers] are the layer sizes.  Activations buffer d_act
+ * float: batch * (sum of widths[1..n_layers]) pre-activations, written by
+ * forward and read by backward.  All float32.                                 */
+typedef struct {
+  int32_t n_layers;
+  int32_t widths[9];
+  int32_t batch;
+} igamt_mlp_desc;
+int64_t igamt_mlp_n_params(const igamt_mlp_desc *desc);
+igamt_status igamt_mlp_forward(const igamt_mlp_desc *desc, const float *d_params, const float *d_x,
+                               float *d_act, float *d_y, void *stream);
+/* Mean-squared error L = mean((y - t)^2) over batch x outputs; writes dL/dy
+ * (float [batch][out]) and L (float [1]).                                    */
+igamt_status igamt_mse_loss(const igamt_mlp_desc *desc, const float *d_y, const float *d_target,
+                            float *d_dy, float *d_loss, void *stream);
+/* Gradients of all parameters (flat, same layout as d_params) given dL/dy.
+ * d_scratch float: 2 * batch * max(widths).                                  */
+igamt_status igamt_mlp_backward(const igamt_mlp_desc *desc, const float *d_params, const float *d_x,
+                                const float *d_act, const float *d_dy, float *d_grads,
+                                float *d_scratch, void *stream);
+/* Adam with bias correction, in place on d_params, d_m, d_v (float [n]). */
+igamt_status igamt_adam_step(float *d_params, const float *d_grads, float *d_m, float *d_v, int64_t n,
+                             float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGAMT_H */

@@ -1,0 +1,263 @@
+"""igamt: interpolation-and-lookup assembly of isogeometric stiffness matrices of
+microstructured (spline-composed) geometries on AMD MI355X.
+
+Python binding of libigamt (include/igamt.h).  This layer only marshals
+arguments: host arrays become plain pointers, device buffers are torch CUDA
+tensors (HIP memory) and the stream is torch's current HIP stream.  Every step
+of the computation runs in the library's HIP kernels; the binding raises if
+the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import IgamtError, check, lib
+
+F64, F32, BF16X3, F16X3 = 0, 1, 2, 3
+PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "f16x3": F16X3}
+
+__all__ = ["Plan", "F64", "F32", "BF16X3", "F16X3", "PRECISIONS", "IgamtError", "spmv", "lib"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _spline(degree, knots, ctrl, keep):
+    s = _lib.Spline3D()
+    ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+    ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
+    keep.extend([ctrl] + ks)
+    for d in range(3):
+        s.degree[d] = int(degree[d])
+        s.knots[d] = ks[d].ctypes.data_as(_lib.P_f64)
+    s.n_ctrl[0], s.n_ctrl[1], s.n_ctrl[2] = ctrl.shape[2], ctrl.shape[1], ctrl.shape[0]
+    s.ctrl = ctrl.ctypes.data_as(_lib.P_f64)
+    return s
+
+
+class Plan:
+    """A fixed topology: macro map, reference tile, tile grid, projection degree.
+
+    macro, tile: objects with .degree (3 ints), .knots (3 arrays), .ctrl ((nz, ny, nx, 3) array).
+    """
+
+    def __init__(self, macro, tile, tiles, box_mode=0, q=2, n_fit=None, n_gauss=3):
+        keep = []
+        m = _spline(macro.degree, macro.knots, macro.ctrl, keep)
+        t = _spline(tile.degree, tile.knots, tile.ctrl, keep)
+        d = _lib.PlanDesc()
+        for k in range(3):
+            d.tiles[k] = int(tiles[k])
+        d.box_mode = int(box_mode)
+        d.q = int(q)
+        d.n_fit = int(q + 1 if n_fit is None else n_fit)
+        d.n_gauss = int(n_gauss)
+        h = C.c_void_p()
+        check(lib().igamt_plan_create(C.byref(m), C.byref(t), C.byref(d), C.byref(h)))
+        self._h = h
+        self.macro_ctrl_shape = np.asarray(macro.ctrl).shape
+        self.tile_ctrl_shape = np.asarray(tile.ctrl).shape
+        s = _lib.Sizes()
+        check(lib().igamt_plan_sizes(h, C.byref(s)))
+        self.sizes = {f: getattr(s, f) for f, _ in _lib.Sizes._fields_}
+        self.q = int(q)
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.macro, w.tile, w.tiles, w.box_mode, w.q, w.n_fit, w.n_gauss)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().igamt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __getattr__(self, name):
+        sizes = self.__dict__.get("sizes")
+        if sizes is not None and name in sizes:
+            return sizes[name]
+        raise AttributeError(name)
+
+    # ---- host integer set-up ----------------------------------------------------
+    def pairs(self) -> np.ndarray:
+        out = np.empty((self.n_pairs, 2), dtype=np.int32)
+        check(lib().igamt_plan_pairs(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def csr_host(self) -> Tuple[np.ndarray, np.ndarray]:
+        rp = np.empty(self.n_dofs + 1, dtype=np.int64)
+        ci = np.empty(self.nnz, dtype=np.int32)
+        check(lib().igamt_plan_csr(self._h, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p)))
+        return rp, ci
+
+    # ---- device ---------------------------------------------------------------------
+    def csr_device(self):
+        torch = _torch()
+        rp = torch.empty(self.n_dofs + 1, dtype=torch.int64, device="cuda")
+        ci = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        check(lib().igamt_plan_csr_device(self._h, _ptr(rp), _ptr(ci), _stream()))
+        return rp, ci
+
+    def set_macro_ctrl(self, ctrl):
+        torch = _torch()
+        if isinstance(ctrl, torch.Tensor):
+            assert ctrl.is_cuda and ctrl.dtype == torch.float64 and ctrl.is_contiguous()
+            assert ctrl.numel() == 3 * self.n_macro_ctrl
+            check(lib().igamt_set_macro_ctrl(self._h, _ptr(ctrl), 1, _stream()))
+        else:
+            a = np.ascontiguousarray(ctrl, dtype=np.float64)
+            assert a.size == 3 * self.n_macro_ctrl
+            check(lib().igamt_set_macro_ctrl(self._h, a.ctypes.data_as(C.c_void_p), 0, _stream()))
+
+    def set_tile_ctrl(self, ctrl):
+        a = np.ascontiguousarray(ctrl, dtype=np.float64)
+        assert a.size == 3 * self.n_tile_ctrl
+        check(lib().igamt_set_tile_ctrl(self._h, a.ctypes.data_as(C.c_void_p)))
+
+    def tables_build(self):
+        check(lib().igamt_tables_build(self._h, _stream()))
+
+    def tables_set(self, table):
+        torch = _torch()
+        assert table.is_cuda and table.dtype == torch.float64 and table.shape == (self.n_pairs, self.n_cols)
+        table = table.contiguous()
+        check(lib().igamt_tables_set(self._h, _ptr(table), _stream()))
+
+    def tables_get(self):
+        torch = _torch()
+        out = torch.empty((self.n_pairs, self.n_cols), dtype=torch.float64, device="cuda")
+        check(lib().igamt_tables_get(self._h, _ptr(out), _stream()))
+        return out
+
+    def tables_build_rows(self, rows):
+        torch = _torch()
+        rows = rows.to(device="cuda", dtype=torch.int32).contiguous()
+        out = torch.empty((rows.numel(), self.n_cols), dtype=torch.float64, device="cuda")
+        check(lib().igamt_tables_build_rows(self._h, _ptr(rows), int(rows.numel()), _ptr(out), _stream()))
+        return out
+
+    def workspace_bytes(self, prec):
+        cb, bb = C.c_int64(), C.c_int64()
+        check(lib().igamt_workspace_bytes(self._h, _prec(prec), C.byref(cb), C.byref(bb)))
+        return cb.value, bb.value
+
+    def _empty_bytes(self, nbytes):
+        torch = _torch()
+        return torch.empty(max(int(nbytes), 256) // 8 + 1, dtype=torch.float64, device="cuda")
+
+    def fit(self, E, nu, prec="f64", out=None):
+        cb, _ = self.workspace_bytes(prec)
+        out = self._empty_bytes(cb) if out is None else out
+        check(lib().igamt_fit(self._h, float(E), float(nu), _prec(prec), _ptr(out), _stream()))
+        return out
+
+    def coef_view(self, coef, prec="f64"):
+        """Fitted coefficients as (n_tiles, K, 9) float64 for inspection (F64/F32 modes only)."""
+        torch = _torch()
+        p = _prec(prec)
+        npad, Kp, K = self.n_tiles_pad, self.n_cols_pad, self.n_cols
+        if p == F64:
+            v = coef.view(torch.float64)[: npad * 9 * Kp]
+        elif p == F32:
+            v = coef.view(torch.float32)[: npad * 9 * Kp].double()
+        else:
+            raise ValueError("coefficient view only for f64 / f32")
+        return v.view(npad, 9, Kp)[: self.n_tiles, :, :K].transpose(1, 2)
+
+    def contract(self, coef, prec="f64", out=None):
+        torch = _torch()
+        dt = torch.float64 if _prec(prec) == F64 else torch.float32
+        out = torch.empty((self.n_tiles, self.n_pairs, 9), dtype=dt, device="cuda") if out is None else out
+        check(lib().igamt_contract(self._h, _prec(prec), _ptr(coef), _ptr(out), _stream()))
+        return out
+
+    def scatter(self, blocks, prec="f64", out=None):
+        torch = _torch()
+        dt = torch.float64 if _prec(prec) == F64 else torch.float32
+        out = torch.empty(self.nnz, dtype=dt, device="cuda") if out is None else out
+        check(lib().igamt_scatter(self._h, _prec(prec), _ptr(blocks), _ptr(out), _stream()))
+        return out
+
+    def workspace(self, prec):
+        cb, bb = self.workspace_bytes(prec)
+        return self._empty_bytes(cb + bb)
+
+    def assemble(self, E, nu, prec="f64", values=None, workspace=None):
+        torch = _torch()
+        dt = torch.float64 if _prec(prec) == F64 else torch.float32
+        values = torch.empty(self.nnz, dtype=dt, device="cuda") if values is None else values
+        workspace = self.workspace(prec) if workspace is None else workspace
+        check(lib().igamt_assemble(self._h, float(E), float(nu), _prec(prec), _ptr(values), _ptr(workspace),
+                                   _stream()))
+        return values
+
+    def check(self):
+        bad = C.c_int64()
+        code = lib().igamt_check(self._h, _stream(), C.byref(bad))
+        if code != 0:
+            raise IgamtError(code, lib().igamt_last_error().decode())
+
+    # ---- sensitivities ------------------------------------------------------------
+    def grad_workspace(self, prec):
+        b = C.c_int64()
+        check(lib().igamt_grad_workspace_bytes(self._h, _prec(prec), C.byref(b)))
+        return self._empty_bytes(b.value)
+
+    def uKu_grad(self, E, nu, u, prec="f64", workspace=None):
+        """(u^T K u, d(u^T K u)/d macro control points) with u fixed."""
+        torch = _torch()
+        assert u.is_cuda and u.dtype == torch.float64 and u.numel() == self.n_dofs
+        u = u.contiguous()
+        grad = torch.empty(self.macro_ctrl_shape, dtype=torch.float64, device="cuda")
+        val = torch.empty(1, dtype=torch.float64, device="cuda")
+        ws = self.grad_workspace(prec) if workspace is None else workspace
+        check(lib().igamt_uKu_grad(self._h, float(E), float(nu), _prec(prec), _ptr(u), _ptr(grad), _ptr(val),
+                                   _ptr(ws), _stream()))
+        return val, grad
+
+    # ---- learned tables ------------------------------------------------------------------
+    def table_from_pod(self, mean, basis, coeffs):
+        r = basis.shape[0]
+        check(lib().igamt_table_from_pod(self._h, _ptr(mean), _ptr(basis), int(r), _ptr(coeffs.contiguous()),
+                                         _stream()))
+
+    def table_rows_error(self, rows, exact_rows):
+        torch = _torch()
+        err = torch.empty(1, dtype=torch.float64, device="cuda")
+        rows = rows.to(device="cuda", dtype=torch.int32).contiguous()
+        check(lib().igamt_table_rows_error(self._h, _ptr(rows), int(rows.numel()), _ptr(exact_rows), _ptr(err),
+                                           _stream()))
+        return err
+
+
+def spmv(row_ptr, col_idx, values, x, out=None):
+    torch = _torch()
+    prec = F64 if values.dtype == torch.float64 else F32
+    out = torch.empty_like(x) if out is None else out
+    check(lib().igamt_spmv(prec, row_ptr.numel() - 1, _ptr(row_ptr), _ptr(col_idx), _ptr(values), _ptr(x),
+                           _ptr(out), _stream()))
+    return out

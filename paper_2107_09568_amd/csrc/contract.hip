@@ -1,0 +1,304 @@
+// Stage 2 of the assembly: the single matrix product of eq. (58),
+//   blocks[t][p][ab] = sum_k table[p][k] coef[t][ab][k],
+// i.e. C (n_pairs x 9 m_M) = A (n_pairs x K) B (K x 9 m_M), on gfx950 MFMA.
+//
+// Layout: A row-major [Mp][Kp] and B column-major [n_tiles_pad*9][Kp], so both
+// operands are contiguous along k.  A workgroup (4 waves) owns 128 table rows x
+// one group of 16 tiles (144 columns); each wave owns 32 rows x 144 columns
+// (2 x 9 MFMA 16x16 blocks).  B chunks of 256 bytes per column are staged in
+// LDS through registers (next chunk loaded while the current one is consumed);
+// each wave reads its A rows straight from global memory (they are not shared
+// between waves).  Within a lane group the k index is permuted so that every
+// lane loads contiguous k values with one vector load; A and B use the same
+// permutation, so the sum over k is unchanged.
+//
+// Work order is XCD-aware: consecutive workgroups of one XCD take all row
+// blocks of one column group, so a column group is fetched from HBM once and
+// reused from that XCD's L2 while the whole table stays resident in the
+// last-level cache.
+#include "device_common.h"
+
+namespace igamt {
+
+constexpr int BM = 128;                 // table rows per workgroup
+constexpr int BN = 144;                 // columns per workgroup (16 tiles x 9)
+constexpr int CHUNK_BYTES = 256;        // bytes of one B column staged per chunk
+constexpr int LDS_ROW = CHUNK_BYTES + 16;
+
+struct ContractArgs {
+  const void *A;          // table (hi plane for split modes)
+  const void *A2;         // lo plane (split modes)
+  const float *Ascale;    // F16X3 inverse row scales
+  const void *B;          // coefficients (hi plane)
+  const void *B2;         // lo plane
+  const float *Bscale;    // F16X3 inverse column scales [n_tiles_pad][9]
+  void *out;              // [n_tiles][M][9]
+  int64_t M, Kp, n_tiles;
+  int n_mblk, n_groups;
+};
+
+template <int MODE>
+struct Mode;
+template <>
+struct Mode<IGAMT_F64> {
+  using E = double;                      // stored element
+  using O = double;
+  using Acc = d4;
+  static constexpr int KCH = 32;         // k per chunk (256 B of doubles)
+  static constexpr int KSTEP = 16;       // k consumed per lane-load step
+};
+template <>
+struct Mode<IGAMT_F32> {
+  using E = float;
+  using O = float;
+  using Acc = f4;
+  static constexpr int KCH = 64;
+  static constexpr int KSTEP = 16;
+};
+template <>
+struct Mode<IGAMT_BF16X3> {
+  using E = uint16_t;
+  using O = float;
+  using Acc = f4;
+  static constexpr int KCH = 64;         // 128 B hi + 128 B lo per column
+  static constexpr int KSTEP = 32;
+};
+template <>
+struct Mode<IGAMT_F16X3> {
+  using E = uint16_t;
+  using O = float;
+  using Acc = f4;
+  static constexpr int KCH = 64;
+  static constexpr int KSTEP = 32;
+};
+
+template <int MODE>
+__device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64_t k0, int tid, uint4 (&r)[9]) {
+  // 144 columns x 16 pieces of 16 B = 2304 pieces, 9 per thread
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int pc = tid + 256 * i;
+    const int n = pc >> 4, j = pc & 15;
+    const int64_t col = grp * BN + n;
+    if constexpr (MODE == IGAMT_F64 || MODE == IGAMT_F32) {
+      using E = typename Mode<MODE>::E;
+      const char *src = (const char *)((const E *)a.B + col * a.Kp + k0) + 16 * j;
+      r[i] = *(const uint4 *)src;
+    } else {
+      const uint16_t *plane = (j < 8) ? (const uint16_t *)a.B : (const uint16_t *)a.B2;
+      const char *src = (const char *)(plane + col * a.Kp + k0) + 16 * (j & 7);
+      r[i] = *(const uint4 *)src;
+    }
+  }
+}
+
+__device__ inline void store_chunk_lds(char *lds, int tid, const uint4 (&r)[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int pc = tid + 256 * i;
+    const int n = pc >> 4, j = pc & 15;
+    *(uint4 *)(lds + n * LDS_ROW + 16 * j) = r[i];
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
+  using M_ = Mode<MODE>;
+  using Acc = typename M_::Acc;
+  using O = typename M_::O;
+  __shared__ __attribute__((aligned(16))) char lds[BN * LDS_ROW];
+
+  const int wg = blockIdx.x;
+  const int xcd = wg & 7, local = wg >> 3;
+  const int64_t grp = (int64_t)(local / a.n_mblk) * 8 + xcd;
+  const int mb = local % a.n_mblk;
+  if (grp >= a.n_groups) return;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int64_t row0 = (int64_t)mb * BM + wave * 32;
+
+  Acc acc[2][9];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 9; ++ni) acc[mi][ni] = Acc{0, 0, 0, 0};
+
+  uint4 pre[9];
+  load_chunk_regs<MODE>(a, grp, 0, tid, pre);
+
+  for (int64_t k0 = 0; k0 < a.Kp; k0 += M_::KCH) {
+    __syncthreads();
+    store_chunk_lds(lds, tid, pre);
+    __syncthreads();
+    if (k0 + M_::KCH < a.Kp) load_chunk_regs<MODE>(a, grp, k0 + M_::KCH, tid, pre);
+
+#pragma unroll
+    for (int ks = 0; ks < M_::KCH; ks += M_::KSTEP) {
+      if constexpr (MODE == IGAMT_F64) {
+        // lane loads k = ks + 4 kq .. +3 for A rows and B columns; 4 MFMA 16x16x4
+        double av[2][4];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+          const double *src = (const double *)a.A + (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 4 * kq;
+          const double2 x0 = *(const double2 *)src, x1 = *(const double2 *)(src + 2);
+          av[mi][0] = x0.x; av[mi][1] = x0.y; av[mi][2] = x1.x; av[mi][3] = x1.y;
+        }
+#pragma unroll
+        for (int ni = 0; ni < 9; ++ni) {
+          const char *bp = lds + (ni * 16 + l16) * LDS_ROW + (ks + 4 * kq) * 8;
+          const double2 y0 = *(const double2 *)bp, y1 = *(const double2 *)(bp + 16);
+          const double bv[4] = {y0.x, y0.y, y1.x, y1.y};
+#pragma unroll
+          for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], bv[s], acc[mi][ni], 0, 0, 0);
+        }
+      } else if constexpr (MODE == IGAMT_F32) {
+        float av[2][4];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+          const float *src = (const float *)a.A + (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 4 * kq;
+          const float4 x = *(const float4 *)src;
+          av[mi][0] = x.x; av[mi][1] = x.y; av[mi][2] = x.z; av[mi][3] = x.w;
+        }
+#pragma unroll
+        for (int ni = 0; ni < 9; ++ni) {
+          const float4 y = *(const float4 *)(lds + (ni * 16 + l16) * LDS_ROW + (ks + 4 * kq) * 4);
+          const float bv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+          for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], bv[s], acc[mi][ni], 0, 0, 0);
+        }
+      } else {
+        // split modes: lane loads 8 consecutive k (16 B) of hi and lo; 3 MFMA 16x16x32
+        using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
+        V8 ah[2], al[2];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+          const int64_t off = (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 8 * kq;
+          ah[mi] = *(const V8 *)((const uint16_t *)a.A + off);
+          al[mi] = *(const V8 *)((const uint16_t *)a.A2 + off);
+        }
+#pragma unroll
+        for (int ni = 0; ni < 9; ++ni) {
+          const char *bp = lds + (ni * 16 + l16) * LDS_ROW + (ks + 8 * kq) * 2;
+          const V8 bh = *(const V8 *)bp;
+          const V8 bl = *(const V8 *)(bp + 128);
+#pragma unroll
+          for (int mi = 0; mi < 2; ++mi) {
+            if constexpr (MODE == IGAMT_BF16X3) {
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh, acc[mi][ni], 0, 0, 0);
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl, acc[mi][ni], 0, 0, 0);
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh, acc[mi][ni], 0, 0, 0);
+            } else {
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mi], bh, acc[mi][ni], 0, 0, 0);
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mi], bl, acc[mi][ni], 0, 0, 0);
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mi], bh, acc[mi][ni], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // epilogue: lane holds C[row 4 kq + r][col l16] of each 16x16 block
+  O *out = (O *)a.out;
+#pragma unroll
+  for (int ni = 0; ni < 9; ++ni) {
+    const int n = ni * 16 + l16;
+    const int tl = n / 9, ab = n - 9 * tl;
+    const int64_t t = grp * 16 + tl;
+    if (t >= a.n_tiles) continue;
+    float cs = 1.0f;
+    if constexpr (MODE == IGAMT_F16X3) cs = a.Bscale[t * 9 + ab];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = row0 + mi * 16 + 4 * kq + r;
+        if (m >= a.M) continue;
+        O v = (O)acc[mi][ni][r];
+        if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[m] * cs);
+        out[(t * a.M + m) * 9 + ab] = v;
+      }
+  }
+}
+
+igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_coef, void *d_blocks, void *stream) {
+  if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
+  ContractArgs a;
+  const int64_t MK = P->Mp * P->Kp;
+  const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
+  a.M = P->n_pairs;
+  a.Kp = P->Kp;
+  a.n_tiles = P->n_tiles;
+  a.n_mblk = (int)(P->Mp / BM);
+  a.n_groups = (int)P->n_groups;
+  a.out = d_blocks;
+  a.A2 = nullptr;
+  a.B2 = nullptr;
+  a.Ascale = nullptr;
+  a.Bscale = nullptr;
+  a.B = d_coef;
+  switch (prec) {
+    case IGAMT_F64: a.A = P->dev.table; break;
+    case IGAMT_F32: a.A = P->dev.table_f32; break;
+    case IGAMT_BF16X3:
+      a.A = P->dev.table_bf;
+      a.A2 = P->dev.table_bf + MK;
+      a.B2 = (const uint16_t *)d_coef + plane;
+      break;
+    case IGAMT_F16X3:
+      a.A = P->dev.table_h;
+      a.A2 = P->dev.table_h + MK;
+      a.Ascale = P->dev.table_h_scale;
+      a.B2 = (const uint16_t *)d_coef + plane;
+      a.Bscale = (const float *)((const uint16_t *)d_coef + 2 * plane);
+      break;
+    default: set_error("unknown precision"); return IGAMT_EINVAL;
+  }
+  const int64_t groups8 = (P->n_groups + 7) / 8 * 8;
+  const dim3 grid((unsigned)(a.n_mblk * groups8)), block(256);
+  hipStream_t s = (hipStream_t)stream;
+  switch (prec) {
+    case IGAMT_F64: hipLaunchKernelGGL(contract_kernel<IGAMT_F64>, grid, block, 0, s, a); break;
+    case IGAMT_F32: hipLaunchKernelGGL(contract_kernel<IGAMT_F32>, grid, block, 0, s, a); break;
+    case IGAMT_BF16X3: hipLaunchKernelGGL(contract_kernel<IGAMT_BF16X3>, grid, block, 0, s, a); break;
+    case IGAMT_F16X3: hipLaunchKernelGGL(contract_kernel<IGAMT_F16X3>, grid, block, 0, s, a); break;
+  }
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+}  // namespace igamt
+
+using namespace igamt;
+
+extern "C" igamt_status igamt_contract(igamt_plan *P, igamt_precision prec, const void *d_coef, void *d_blocks,
+                                       void *stream) {
+  if (!P || !d_coef || !d_blocks) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (prec < IGAMT_F64 || prec > IGAMT_F16X3) { set_error("unknown precision"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  return launch_contract(P, prec, d_coef, d_blocks, stream);
+}
+
+extern "C" igamt_status igamt_assemble(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_values,
+                                       void *d_workspace, void *stream) {
+  if (!P || !d_values || !d_workspace) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (prec < IGAMT_F64 || prec > IGAMT_F16X3) { set_error("unknown precision"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
+  char *ws = (char *)d_workspace;
+  void *coef = ws;
+  void *blocks = ws + coef_bytes(P, prec);
+  if ((st = launch_fit(P, E, nu, prec, coef, stream))) return st;
+  if ((st = launch_contract(P, prec, coef, blocks, stream))) return st;
+  return launch_scatter(P, prec, blocks, d_values, stream);
+}

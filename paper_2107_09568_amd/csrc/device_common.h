@@ -1,0 +1,169 @@
+// Device helpers for the libigamt kernels: B-spline and Bernstein evaluation,
+// 3x3 algebra, precision conversions and error-checking macros.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <type_traits>
+
+#include "igamt_internal.h"
+
+#define IGAMT_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      igamt::set_error(std::string(#call) + ": " + hipGetErrorString(e_));           \
+      return IGAMT_EHIP;                                                             \
+    }                                                                                \
+  } while (0)
+
+#define IGAMT_LAUNCH_CHECK()                                                         \
+  do {                                                                               \
+    hipError_t e_ = hipGetLastError();                                               \
+    if (e_ != hipSuccess) {                                                          \
+      igamt::set_error(std::string("kernel launch: ") + hipGetErrorString(e_));      \
+      return IGAMT_EHIP;                                                             \
+    }                                                                                \
+  } while (0)
+
+namespace igamt {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// Knot span containing x: the largest i in [p, n-1] with U[i] <= x (x = 1 goes
+// to the last non-empty span).  U has n + p + 1 entries.
+__device__ inline int find_span(const double *__restrict__ U, int n, int p, double x) {
+  if (x >= U[n]) return n - 1;
+  if (x <= U[p]) return p;
+  int lo = p, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (x < U[mid]) hi = mid; else lo = mid;
+  }
+  return lo;
+}
+
+// Values N[r] and first derivatives dN[r] of the P+1 B-splines that are non-zero
+// on span `span` (global index span - P + r), by the triangular Cox-de Boor
+// recursion over the degrees 0..P.
+template <int P>
+__device__ inline void bspline_ders(const double *__restrict__ U, int span, double x,
+                                    double (&N)[P + 1], double (&dN)[P + 1]) {
+  double V[P + 1];
+  double Vp[P + 1];
+#pragma unroll
+  for (int r = 0; r <= P; ++r) { V[r] = 0.0; Vp[r] = 0.0; }
+  V[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= P; ++k) {
+#pragma unroll
+    for (int r = 0; r <= P; ++r) Vp[r] = V[r];
+#pragma unroll
+    for (int r = 0; r <= k; ++r) {
+      double v = 0.0;
+      if (r >= 1) {
+        const double den = U[span + r] - U[span - k + r];
+        if (den > 0.0) v += (x - U[span - k + r]) / den * Vp[r - 1];
+      }
+      if (r <= k - 1) {
+        const double den = U[span + r + 1] - U[span - k + r + 1];
+        if (den > 0.0) v += (U[span + r + 1] - x) / den * Vp[r];
+      }
+      V[r] = v;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    double d = 0.0;
+    if (r >= 1) {
+      const double den = U[span + r] - U[span - P + r];
+      if (den > 0.0) d += Vp[r - 1] / den;
+    }
+    if (r <= P - 1) {
+      const double den = U[span + r + 1] - U[span - P + r + 1];
+      if (den > 0.0) d -= Vp[r] / den;
+    }
+    N[r] = V[r];
+    dN[r] = P * d;
+  }
+}
+
+// Bernstein polynomials of degree q at x (runtime q <= kMaxQ).
+__device__ inline void bernstein(int q, double x, double *B) {
+  // B^q_c = C(q,c) x^c (1-x)^(q-c), built by the de Casteljau-type recursion
+  // B^k_c = (1-x) B^{k-1}_c + x B^{k-1}_{c-1}.
+  B[0] = 1.0;
+  for (int k = 1; k <= q; ++k) {
+    B[k] = x * B[k - 1];
+    for (int c = k - 1; c >= 1; --c) B[c] = (1.0 - x) * B[c] + x * B[c - 1];
+    B[0] = (1.0 - x) * B[0];
+  }
+}
+
+__device__ inline double det3(const double (&J)[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// F = J^-1 by cofactors; returns det J.
+__device__ inline double inv3(const double (&J)[3][3], double (&F)[3][3]) {
+  const double D = det3(J);
+  const double r = 1.0 / D;
+  F[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * r;
+  F[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+  F[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+  F[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * r;
+  F[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+  F[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+  F[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * r;
+  F[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+  F[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+  return D;
+}
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ inline uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_bits_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ inline uint16_t f32_to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;
+  return *reinterpret_cast<uint16_t *>(&h);
+}
+__device__ inline float f16_bits_to_f32(uint16_t b) {
+  _Float16 h = *reinterpret_cast<_Float16 *>(&b);
+  return (float)h;
+}
+
+// x ~ hi + lo with both parts representable in bfloat16.
+__device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
+  hi = f32_to_bf16_bits((float)x);
+  lo = f32_to_bf16_bits((float)(x - (double)bf16_bits_to_f32(hi)));
+}
+__device__ inline void split_f16(double x, uint16_t &hi, uint16_t &lo) {
+  hi = f32_to_f16_bits((float)x);
+  lo = f32_to_f16_bits((float)(x - (double)f16_bits_to_f32(hi)));
+}
+
+// Power-of-two scale that maps a magnitude bound to about 2^14 (float16 range).
+__device__ inline double f16_scale_for(double bound) {
+  if (!(bound > 0.0)) return 1.0;
+  int e;
+  frexp(bound, &e);           // bound = m 2^e, m in [0.5, 1)
+  return ldexp(1.0, 14 - e);  // bound * scale < 2^14
+}
+
+__host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace igamt

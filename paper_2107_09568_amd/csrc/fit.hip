@@ -1,0 +1,295 @@
+// Stage 1 of the assembly: macro-field fit (Section 3.2.2).
+//
+// One 64-thread workgroup per tile.  Every Gauss sample xi_s of the tile gets
+// J = J_M(a + h xi_s) diag(h) (Cox-de Boor derivatives of the macro map),
+// F = J^-1 and D = det J in FP64.  The projection coefficients
+//   <A_ij,ab>_C = sum_s P[C, s] A_ij,ab(xi_s),  P = P1 (x) P1 (x) P1,
+// (eq. (42) with the 1-D operator of eq. (23)-(24)) are applied sum-factorised,
+// one direction at a time, for one (i, j) block of A at a time, with
+//   A_ij,ab = D (lam F_ia F_jb + mu (F_i . F_j) delta_ab + mu F_ib F_ja),
+// the Cartesian form of eq. (37) (F_i is row i of F).  The result is written in
+// the column-major layout the contraction reads: coef[t][3a+b][9C+3i+j].
+#include "device_common.h"
+
+namespace igamt {
+
+struct FitArgs {
+  const double *knots[3];
+  int nM[3];
+  const double *ctrl;
+  const double *box_a[3];
+  const double *box_h[3];
+  int tiles[3];
+  int64_t n_tiles;
+  const double *fx;
+  const double *fP;
+  int q, nf, Kp, prec;
+  double lam, mu;
+  void *out;
+  int64_t plane;        // n_tiles_pad * 9 * Kp elements per stored plane
+  int32_t *flag;
+};
+
+template <typename F>
+__device__ inline void store_coef(const FitArgs &a, int64_t idx, double v, double scale) {
+  if (a.prec == IGAMT_F64) {
+    ((double *)a.out)[idx] = v;
+  } else if (a.prec == IGAMT_F32) {
+    ((float *)a.out)[idx] = (float)v;
+  } else if (a.prec == IGAMT_BF16X3) {
+    uint16_t hi, lo;
+    split_bf16(v, hi, lo);
+    ((uint16_t *)a.out)[idx] = hi;
+    ((uint16_t *)a.out)[a.plane + idx] = lo;
+  } else {
+    uint16_t hi, lo;
+    split_f16(v * scale, hi, lo);
+    ((uint16_t *)a.out)[idx] = hi;
+    ((uint16_t *)a.out)[a.plane + idx] = lo;
+  }
+}
+
+template <int PM>
+__global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
+  extern __shared__ double smem[];
+  const int nf = a.nf, q1 = a.q + 1;
+  const int ns = nf * nf * nf;
+  const int npi = q1 * q1 * q1;
+  double *FD = smem;              // [ns][10]
+  double *buf0 = FD + ns * 10;    // [ns][9]
+  double *buf1 = buf0 + ns * 9;   // [ns][9]
+  __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
+  __shared__ double colmax[64][9];
+  __shared__ double scale[9];
+  const int tid = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int64_t tbase = t * 9 * (int64_t)a.Kp;
+
+  if (t >= a.n_tiles) {  // padding tile: zeros
+    for (int64_t e = tid; e < 9 * (int64_t)a.Kp; e += 64) store_coef<double>(a, tbase + e, 0.0, 1.0);
+    if (a.prec == IGAMT_F16X3 && tid < 9)
+      ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = 1.0f;
+    return;
+  }
+  for (int e = tid; e < q1 * nf; e += 64) Pm[e] = a.fP[e];
+  const int tx = (int)(t % a.tiles[0]);
+  const int ty = (int)((t / a.tiles[0]) % a.tiles[1]);
+  const int tz = (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]));
+  const double ax[3] = {a.box_a[0][tx], a.box_a[1][ty], a.box_a[2][tz]};
+  const double hx[3] = {a.box_h[0][tx], a.box_h[1][ty], a.box_h[2][tz]};
+  double cmax[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cmax[k] = 0.0;
+
+  // Jacobians at the samples
+  for (int s = tid; s < ns; s += 64) {
+    const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
+    double N[3][PM + 1], dN[3][PM + 1];
+    int span[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double x = ax[k] + hx[k] * a.fx[si[k]];
+      span[k] = find_span(a.knots[k], a.nM[k], PM, x);
+      bspline_ders<PM>(a.knots[k], span[k], x, N[k], dN[k]);
+    }
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int rz = 0; rz <= PM; ++rz) {
+      const int iz = span[2] - PM + rz;
+      for (int ry = 0; ry <= PM; ++ry) {
+        const int iy = span[1] - PM + ry;
+        const double wyz = N[1][ry] * N[2][rz];
+        const double dy = dN[1][ry] * N[2][rz];
+        const double dz = N[1][ry] * dN[2][rz];
+#pragma unroll
+        for (int rx = 0; rx <= PM; ++rx) {
+          const int ix = span[0] - PM + rx;
+          const double *c = a.ctrl + 3 * (ix + (int64_t)a.nM[0] * (iy + (int64_t)a.nM[1] * iz));
+          const double g0 = dN[0][rx] * wyz, g1 = N[0][rx] * dy, g2 = N[0][rx] * dz;
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            J[cc][0] += c[cc] * g0;
+            J[cc][1] += c[cc] * g1;
+            J[cc][2] += c[cc] * g2;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) J[cc][k] *= hx[k];
+    double F[3][3];
+    const double D = inv3(J, F);
+    if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag, (int32_t)t);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) FD[s * 10 + 3 * r + c] = F[r][c];
+    FD[s * 10 + 9] = D;
+    if (a.prec == IGAMT_F16X3) {
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const double fij = F[i][0] * F[j][0] + F[i][1] * F[j][1] + F[i][2] * F[j][2];
+          for (int aa = 0; aa < 3; ++aa)
+            for (int bb = 0; bb < 3; ++bb) {
+              const double v = D * (a.lam * F[i][aa] * F[j][bb] + (aa == bb ? a.mu * fij : 0.0) + a.mu * F[i][bb] * F[j][aa]);
+              cmax[3 * aa + bb] = fmax(cmax[3 * aa + bb], fabs(v));
+            }
+        }
+    }
+  }
+  if (a.prec == IGAMT_F16X3) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) colmax[tid][k] = cmax[k];
+  }
+  __syncthreads();
+  if (a.prec == IGAMT_F16X3 && tid < 9) {
+    double m = 0.0;
+    for (int r = 0; r < 64; ++r) m = fmax(m, colmax[r][tid]);
+    double L = 0.0;  // max row sum of |P1|: |coef| <= L^3 max|A|
+    for (int c = 0; c < q1; ++c) {
+      double rs = 0.0;
+      for (int s = 0; s < nf; ++s) rs += fabs(Pm[c * nf + s]);
+      L = fmax(L, rs);
+    }
+    scale[tid] = f16_scale_for(m * L * L * L);
+    ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = (float)(1.0 / scale[tid]);
+  }
+  __syncthreads();
+
+  for (int ij = 0; ij < 9; ++ij) {
+    const int i = ij / 3, j = ij % 3;
+    // A_ij at every sample
+    for (int e = tid; e < ns * 9; e += 64) {
+      const int s = e / 9, ab = e % 9, aa = ab / 3, bb = ab % 3;
+      const double *Fs = FD + s * 10;
+      const double fij = Fs[3 * i] * Fs[3 * j] + Fs[3 * i + 1] * Fs[3 * j + 1] + Fs[3 * i + 2] * Fs[3 * j + 2];
+      buf0[e] = Fs[9] * (a.lam * Fs[3 * i + aa] * Fs[3 * j + bb] + (aa == bb ? a.mu * fij : 0.0) +
+                         a.mu * Fs[3 * i + bb] * Fs[3 * j + aa]);
+    }
+    __syncthreads();
+    // x direction: buf1[(s3, s2, c1)][ab]
+    for (int e = tid; e < q1 * nf * nf * 9; e += 64) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1, s23 = r / q1;
+      double v = 0.0;
+      for (int s1 = 0; s1 < nf; ++s1) v += Pm[c1 * nf + s1] * buf0[(s23 * nf + s1) * 9 + ab];
+      buf1[e] = v;
+    }
+    __syncthreads();
+    // y direction: buf0[(s3, c2, c1)][ab]
+    for (int e = tid; e < q1 * q1 * nf * 9; e += 64) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1, c2 = (r / q1) % q1, s3 = r / (q1 * q1);
+      double v = 0.0;
+      for (int s2 = 0; s2 < nf; ++s2) v += Pm[c2 * nf + s2] * buf1[(((s3 * nf + s2) * q1) + c1) * 9 + ab];
+      buf0[e] = v;
+    }
+    __syncthreads();
+    // z direction and store: C = c1 + q1 (c2 + q1 c3)
+    for (int e = tid; e < npi * 9; e += 64) {
+      const int C = e % npi, ab = e / npi;
+      const int c1 = C % q1, c2 = (C / q1) % q1, c3 = C / (q1 * q1);
+      double v = 0.0;
+      for (int s3 = 0; s3 < nf; ++s3) v += Pm[c3 * nf + s3] * buf0[(((s3 * q1 + c2) * q1) + c1) * 9 + ab];
+      store_coef<double>(a, tbase + (int64_t)ab * a.Kp + 9 * C + ij, v, a.prec == IGAMT_F16X3 ? scale[ab] : 1.0);
+    }
+    __syncthreads();
+  }
+  // zero the padded columns
+  const int K = 9 * npi;
+  for (int e = tid; e < 9 * (a.Kp - K); e += 64) {
+    const int ab = e / (a.Kp - K), k = K + e % (a.Kp - K);
+    store_coef<double>(a, tbase + (int64_t)ab * a.Kp + k, 0.0, 1.0);
+  }
+}
+
+int64_t coef_elem_bytes(igamt_precision prec) {
+  return prec == IGAMT_F64 ? 8 : prec == IGAMT_F32 ? 4 : 4;  // split modes: two 2-byte planes
+}
+
+int64_t coef_bytes(const igamt_plan *P, igamt_precision prec) {
+  const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
+  int64_t b = plane * coef_elem_bytes(prec);
+  if (prec == IGAMT_F16X3) b += P->n_tiles_pad * 9 * 4;
+  return align256(b);
+}
+
+int64_t blocks_bytes(const igamt_plan *P, igamt_precision prec) {
+  return align256(P->n_tiles * P->n_pairs * 9 * (prec == IGAMT_F64 ? 8 : 4));
+}
+
+igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_coef, void *stream) {
+  if (!(E > 0.0) || !std::isfinite(E) || !(nu > -1.0 && nu < 0.5)) {
+    set_error("material constants must satisfy E > 0 and -1 < nu < 0.5");
+    return IGAMT_EINVAL;
+  }
+  FitArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.knots[k] = P->dev.macro_knots[k];
+    a.nM[k] = P->nM[k];
+    a.box_a[k] = P->dev.box_a[k];
+    a.box_h[k] = P->dev.box_h[k];
+    a.tiles[k] = P->tiles[k];
+  }
+  a.ctrl = P->dev.macro_ctrl;
+  a.n_tiles = P->n_tiles;
+  a.fx = P->dev.fit_x;
+  a.fP = P->dev.fit_P;
+  a.q = P->q;
+  a.nf = P->n_fit;
+  a.Kp = P->Kp;
+  a.prec = prec;
+  a.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  a.mu = E / (2.0 * (1.0 + nu));
+  a.out = d_coef;
+  a.plane = P->n_tiles_pad * 9 * (int64_t)P->Kp;
+  a.flag = P->dev.flag;
+  const size_t shm = (size_t)28 * P->n_fit * P->n_fit * P->n_fit * sizeof(double);
+  const dim3 grid((unsigned)P->n_tiles_pad), block(64);
+  hipStream_t s = (hipStream_t)stream;
+  // all macro directions share one degree in the device evaluator
+  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
+    set_error("macro maps with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  switch (P->pM[0]) {
+#define FIT_CASE(p)                                                                                   \
+  case p:                                                                                             \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p>,                       \
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
+    hipLaunchKernelGGL(fit_kernel<p>, grid, block, shm, s, a);                                        \
+    break;
+    FIT_CASE(1)
+    FIT_CASE(2)
+    FIT_CASE(3)
+    FIT_CASE(4)
+    FIT_CASE(5)
+    FIT_CASE(6)
+#undef FIT_CASE
+    default:
+      set_error("unsupported macro degree");
+      return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+}  // namespace igamt
+
+using namespace igamt;
+
+extern "C" igamt_status igamt_workspace_bytes(const igamt_plan *P, igamt_precision prec, int64_t *cb, int64_t *bb) {
+  if (!P || !cb || !bb) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (prec < IGAMT_F64 || prec > IGAMT_F16X3) { set_error("unknown precision"); return IGAMT_EINVAL; }
+  *cb = coef_bytes(P, prec);
+  *bb = blocks_bytes(P, prec);
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_fit(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_coef,
+                                  void *stream) {
+  if (!P || !d_coef) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (prec < IGAMT_F64 || prec > IGAMT_F16X3) { set_error("unknown precision"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  return launch_fit(P, E, nu, prec, d_coef, stream);
+}

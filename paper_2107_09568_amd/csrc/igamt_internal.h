@@ -1,0 +1,125 @@
+// Internal definitions shared by the host plan and the HIP kernels of libigamt.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/igamt.h"
+
+namespace igamt {
+
+constexpr int kMaxDegree = 6;      // spline degrees handled by the device evaluators
+constexpr int kMaxQ = 6;           // projection degree
+constexpr int kMaxFit = 8;         // fit samples per direction
+constexpr int kMaxGauss = 8;       // table quadrature points per direction
+constexpr int kTileGroup = 16;     // tiles per contraction column group (144 columns)
+constexpr int kColPad = 64;        // table columns padded to a multiple of this
+constexpr int kRowPad = 128;       // table rows padded to a multiple of this
+
+void set_error(const std::string &msg);
+
+// One direction of the glued 1-D structure: for every global index g its sorted
+// neighbour list (g2) and, per neighbour, the tiles holding both (1 or 2) with
+// the tile-local indices of g and g2.
+struct Pair1D {
+  int32_t g, g2, rank, ntile;
+  int32_t tile[2], li[2], lj[2];
+  int32_t pad[2];
+};
+static_assert(sizeof(Pair1D) == 48, "Pair1D layout");
+
+struct Direction {
+  int NG = 0;                        // global control points in this direction
+  std::vector<Pair1D> pairs;         // sorted by (g, g2)
+  std::vector<int32_t> off;          // [NG + 1] first entry of g
+  std::vector<int64_t> pre;          // [NG + 1] exclusive prefix of neighbour counts
+};
+
+struct DevicePtrs {
+  bool ready = false;
+  int device = -1;
+  double *macro_knots[3] = {nullptr, nullptr, nullptr};
+  double *macro_ctrl = nullptr;
+  double *box_a[3] = {nullptr, nullptr, nullptr};
+  double *box_h[3] = {nullptr, nullptr, nullptr};
+  double *fit_x = nullptr;           // [n_fit] Gauss nodes on [0,1]
+  double *fit_P = nullptr;           // [(q+1) * n_fit] 1-D projection matrix
+  double *tile_knots[3] = {nullptr, nullptr, nullptr};
+  double *tile_ctrl = nullptr;
+  double *gauss_x = nullptr;         // [n_gauss] nodes on [0,1]
+  double *gauss_w = nullptr;
+  int32_t *pairs = nullptr;          // [n_pairs][2]
+  int32_t *pair_lut = nullptr;       // [n_T][S_z][S_y][S_x] -> pair index or -1
+  Pair1D *dir_pairs[3] = {nullptr, nullptr, nullptr};
+  int32_t *dir_off[3] = {nullptr, nullptr, nullptr};
+  int64_t *dir_pre[3] = {nullptr, nullptr, nullptr};
+  int32_t *ctrl_lo[3] = {nullptr, nullptr, nullptr};     // per tile: first local macro ctrl index
+  int32_t *ctrl_tiles_off[3] = {nullptr, nullptr, nullptr};  // per macro ctrl index: tiles touching it
+  int32_t *ctrl_tiles[3] = {nullptr, nullptr, nullptr};      // (tile, local offset) pairs
+  int32_t *flag = nullptr;           // smallest degenerate tile index (INT32_MAX = none)
+  // tables
+  double *table = nullptr;           // [Mp][Kp] FP64, zero padded
+  double *table_t = nullptr;         // [Kp][Mp] FP64 (transposed, for the adjoint)
+  float *table_f32 = nullptr;        // [Mp][Kp]
+  float *table_t_f32 = nullptr;      // [Kp][Mp]
+  uint16_t *table_bf = nullptr;      // hi [Mp][Kp] then lo [Mp][Kp]
+  uint16_t *table_h = nullptr;       // hi then lo, scaled rows
+  float *table_h_scale = nullptr;    // [Mp] inverse row scale
+  double *point_data = nullptr;      // table builder scratch
+};
+
+}  // namespace igamt
+
+struct igamt_plan {
+  // macro map
+  int pM[3], nM[3];
+  std::vector<double> kM[3];
+  std::vector<double> ctrlM;
+  // reference tile
+  int pT[3], nT[3];
+  std::vector<double> kT[3];
+  std::vector<double> ctrlT;
+  int eT[3];                          // micro elements per direction
+  // descriptor
+  int tiles[3], box_mode, q, n_fit, n_gauss;
+  // derived sizes
+  int64_t n_tiles, n_tiles_pad, n_groups;
+  int npi, K, Kp;
+  int64_t n_pairs, Mp, nTt;
+  int S[3];                           // 2 pT + 1 per direction (pair LUT strides)
+  std::vector<double> box_a[3], box_h[3];
+  std::vector<int32_t> pairs;         // [n_pairs][2]
+  std::vector<int32_t> pair_lut;      // [nTt][S2][S1][S0]
+  igamt::Direction dir[3];
+  int64_t n_global, nnz;
+  // 1-D fit operator
+  std::vector<double> fit_x, fit_w, fit_P;
+  std::vector<double> gauss_x, gauss_w;
+  // macro control points touched by each tile (for the fit adjoint)
+  int Lc[3];                          // local control points per direction (max over tiles)
+  std::vector<int32_t> ctrl_lo[3];
+  std::vector<int32_t> ctrl_tiles_off[3], ctrl_tiles[3];
+  // state
+  bool tables_ready = false;
+  igamt::DevicePtrs dev;
+};
+
+namespace igamt {
+// host helpers (plan.cpp)
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w);
+int find_span_host(const std::vector<double> &U, int n, int p, double x);
+// device helpers (device.hip)
+igamt_status ensure_device(igamt_plan *plan);
+void free_device(igamt_plan *plan);
+igamt_status upload_macro_ctrl(igamt_plan *plan, const double *ctrl, int on_device, void *stream);
+igamt_status derive_table_copies(igamt_plan *plan, void *stream);
+// stage launchers (fit.hip, contract.hip, scatter.hip)
+int64_t coef_bytes(const igamt_plan *plan, igamt_precision prec);
+int64_t blocks_bytes(const igamt_plan *plan, igamt_precision prec);
+igamt_status launch_fit(igamt_plan *plan, double E, double nu, igamt_precision prec, void *d_coef, void *stream);
+igamt_status launch_contract(igamt_plan *plan, igamt_precision prec, const void *d_coef, void *d_blocks,
+                             void *stream);
+igamt_status launch_scatter(igamt_plan *plan, igamt_precision prec, const void *d_blocks, void *d_values,
+                            void *stream);
+}  // namespace igamt

@@ -1,0 +1,258 @@
+// Micro-scale stiffness lookup table (Section 3.2.3, eq. (51)-(52), (57)):
+//   table[p(A,B)][9C + 3i + j] = int_Omega_T d_i(R_A o T^-1) d_j(R_B o T^-1) N_C dxi
+// pulled back to the tile parameter domain,
+//   = sum_e sum_g w_g det J_T (J_T^-T grad R_A)_i (J_T^-T grad R_B)_j N_C(T^r(theta_g)),
+// with n_gauss Gauss-Legendre points per direction on every micro element.
+//
+// Pass 1 (one thread per micro element x Gauss point) evaluates the tile map
+// and stores, per point, w det J_T, the Bernstein values N_C(T^r(theta)) and the
+// mapped gradients of the (p+1)^3 active functions.  Pass 2 (one thread per
+// table row and Bernstein index C) sums the 9 (i, j) integrals over the micro
+// elements shared by A and B, in ascending element and point order, so the
+// table is bitwise reproducible.
+#include "device_common.h"
+
+namespace igamt {
+
+struct TableArgs {
+  const double *knots[3];
+  int nT[3], eT[3];
+  const double *ctrl;
+  const double *gx, *gw;
+  int ng, q, npi;
+  int64_t stride;        // doubles per point record
+  double *pts;
+  int32_t *flag;
+};
+
+template <int PT>
+__global__ __launch_bounds__(64) void table_points_kernel(TableArgs a) {
+  const int G = a.ng * a.ng * a.ng;
+  const int64_t id = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t nE = (int64_t)a.eT[0] * a.eT[1] * a.eT[2];
+  if (id >= nE * G) return;
+  const int64_t e = id / G;
+  const int g = (int)(id % G);
+  const int ei[3] = {(int)(e % a.eT[0]), (int)((e / a.eT[0]) % a.eT[1]), (int)(e / ((int64_t)a.eT[0] * a.eT[1]))};
+  const int gi[3] = {g % a.ng, (g / a.ng) % a.ng, g / (a.ng * a.ng)};
+  double N[3][PT + 1], dN[3][PT + 1];
+  double w = 1.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int span = ei[k] + PT;
+    const double lo = a.knots[k][span], hi = a.knots[k][span + 1];
+    const double th = lo + (hi - lo) * a.gx[gi[k]];
+    w *= (hi - lo) * a.gw[gi[k]];
+    bspline_ders<PT>(a.knots[k], span, th, N[k], dN[k]);
+  }
+  // map value and Jacobian J[c][k] = dT_c / dtheta_k
+  double X[3] = {0, 0, 0};
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int rz = 0; rz <= PT; ++rz)
+    for (int ry = 0; ry <= PT; ++ry)
+#pragma unroll
+      for (int rx = 0; rx <= PT; ++rx) {
+        const int64_t A = (ei[0] + rx) + (int64_t)a.nT[0] * ((ei[1] + ry) + (int64_t)a.nT[1] * (ei[2] + rz));
+        const double *c = a.ctrl + 3 * A;
+        const double R = N[0][rx] * N[1][ry] * N[2][rz];
+        const double d0 = dN[0][rx] * N[1][ry] * N[2][rz];
+        const double d1 = N[0][rx] * dN[1][ry] * N[2][rz];
+        const double d2 = N[0][rx] * N[1][ry] * dN[2][rz];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          X[cc] += R * c[cc];
+          J[cc][0] += c[cc] * d0;
+          J[cc][1] += c[cc] * d1;
+          J[cc][2] += c[cc] * d2;
+        }
+      }
+  double F[3][3];
+  const double D = inv3(J, F);
+  if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag + 1, (int32_t)e);
+  double *out = a.pts + id * a.stride;
+  out[0] = w * D;
+  double B[3][kMaxQ + 1];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) bernstein(a.q, X[k], B[k]);
+  const int q1 = a.q + 1;
+  for (int C = 0; C < a.npi; ++C) out[1 + C] = B[0][C % q1] * B[1][(C / q1) % q1] * B[2][C / (q1 * q1)];
+  double *gout = out + 1 + a.npi;
+  int la = 0;
+  for (int rz = 0; rz <= PT; ++rz)
+    for (int ry = 0; ry <= PT; ++ry)
+#pragma unroll
+      for (int rx = 0; rx <= PT; ++rx, ++la) {
+        const double d[3] = {dN[0][rx] * N[1][ry] * N[2][rz], N[0][rx] * dN[1][ry] * N[2][rz],
+                             N[0][rx] * N[1][ry] * dN[2][rz]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gout[3 * la + c] = F[0][c] * d[0] + F[1][c] * d[1] + F[2][c] * d[2];
+      }
+}
+
+struct TableSumArgs {
+  const int32_t *pairs;
+  const int32_t *rows;   // optional row list
+  int64_t n_rows;
+  int64_t n_pairs;
+  int nT[3], eT[3], pT;
+  int ng, npi;
+  int64_t stride;
+  const double *pts;
+  double *out;
+  int64_t out_stride;    // doubles per output row
+};
+
+__global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= a.n_rows * a.npi) return;
+  const int64_t row = id / a.npi;
+  const int C = (int)(id % a.npi);
+  const int64_t p = a.rows ? a.rows[row] : row;
+  if (p < 0 || p >= a.n_pairs) {  // invalid row index: flag the output instead of reading out of bounds
+    double *o = a.out + row * a.out_stride + 9 * C;
+    for (int k = 0; k < 9; ++k) o[k] = __builtin_nan("");
+    return;
+  }
+  const int A = a.pairs[2 * p], B = a.pairs[2 * p + 1];
+  const int ai[3] = {A % a.nT[0], (A / a.nT[0]) % a.nT[1], A / (a.nT[0] * a.nT[1])};
+  const int bi[3] = {B % a.nT[0], (B / a.nT[0]) % a.nT[1], B / (a.nT[0] * a.nT[1])};
+  int lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = max(max(ai[k], bi[k]) - a.pT, 0);
+    hi[k] = min(min(ai[k], bi[k]), a.eT[k] - 1);
+  }
+  const int G = a.ng * a.ng * a.ng;
+  const int p1 = a.pT + 1;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (int ez = lo[2]; ez <= hi[2]; ++ez)
+    for (int ey = lo[1]; ey <= hi[1]; ++ey)
+      for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+        const int64_t e = ex + (int64_t)a.eT[0] * (ey + (int64_t)a.eT[1] * ez);
+        const int la = (ai[0] - ex) + p1 * ((ai[1] - ey) + p1 * (ai[2] - ez));
+        const int lb = (bi[0] - ex) + p1 * ((bi[1] - ey) + p1 * (bi[2] - ez));
+        const double *pd = a.pts + e * G * a.stride;
+        for (int g = 0; g < G; ++g, pd += a.stride) {
+          const double wn = pd[0] * pd[1 + C];
+          const double *gA = pd + 1 + a.npi + 3 * la;
+          const double *gB = pd + 1 + a.npi + 3 * lb;
+          const double a0 = wn * gA[0], a1 = wn * gA[1], a2 = wn * gA[2];
+          const double b0 = gB[0], b1 = gB[1], b2 = gB[2];
+          acc[0] += a0 * b0; acc[1] += a0 * b1; acc[2] += a0 * b2;
+          acc[3] += a1 * b0; acc[4] += a1 * b1; acc[5] += a1 * b2;
+          acc[6] += a2 * b0; acc[7] += a2 * b1; acc[8] += a2 * b2;
+        }
+      }
+  double *o = a.out + row * a.out_stride + 9 * C;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) o[k] = acc[k];
+}
+
+static __global__ void zero_f64(double *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride) {
+  const int G = P->n_gauss * P->n_gauss * P->n_gauss;
+  const int64_t nE = (int64_t)P->eT[0] * P->eT[1] * P->eT[2];
+  const int nact = (P->pT[0] + 1) * (P->pT[1] + 1) * (P->pT[2] + 1);
+  stride = 1 + P->npi + 3 * nact;
+  if (!P->dev.point_data) IGAMT_HIP(hipMalloc((void **)&P->dev.point_data, nE * G * stride * sizeof(double)));
+  if (P->pT[0] != P->pT[1] || P->pT[0] != P->pT[2]) {
+    set_error("reference tiles with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  // the tile control points may have changed since the last upload
+  IGAMT_HIP(hipMemcpyAsync(P->dev.tile_ctrl, P->ctrlT.data(), P->ctrlT.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+  TableArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.knots[k] = P->dev.tile_knots[k];
+    a.nT[k] = P->nT[k];
+    a.eT[k] = P->eT[k];
+  }
+  a.ctrl = P->dev.tile_ctrl;
+  a.gx = P->dev.gauss_x;
+  a.gw = P->dev.gauss_w;
+  a.ng = P->n_gauss;
+  a.q = P->q;
+  a.npi = P->npi;
+  a.stride = stride;
+  a.pts = P->dev.point_data;
+  a.flag = P->dev.flag;
+  const dim3 grid((unsigned)((nE * G + 63) / 64)), block(64);
+  switch (P->pT[0]) {
+    case 1: hipLaunchKernelGGL(table_points_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(table_points_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(table_points_kernel<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(table_points_kernel<4>, grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(table_points_kernel<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(table_points_kernel<6>, grid, block, 0, s, a); break;
+    default: set_error("unsupported tile degree"); return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+static TableSumArgs sum_args(const igamt_plan *P, int64_t stride) {
+  TableSumArgs b;
+  b.pairs = P->dev.pairs;
+  b.rows = nullptr;
+  b.n_rows = P->n_pairs;
+  b.n_pairs = P->n_pairs;
+  for (int k = 0; k < 3; ++k) {
+    b.nT[k] = P->nT[k];
+    b.eT[k] = P->eT[k];
+  }
+  b.pT = P->pT[0];
+  b.ng = P->n_gauss;
+  b.npi = P->npi;
+  b.stride = stride;
+  b.pts = P->dev.point_data;
+  return b;
+}
+
+}  // namespace igamt
+
+using namespace igamt;
+
+extern "C" igamt_status igamt_tables_build(igamt_plan *P, void *stream) {
+  if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t stride = 0;
+  if ((st = run_points(P, s, stride))) return st;
+  const int64_t MK = P->Mp * P->Kp;
+  hipLaunchKernelGGL(zero_f64, dim3((unsigned)((MK + 255) / 256)), dim3(256), 0, s, P->dev.table, MK);
+  IGAMT_LAUNCH_CHECK();
+  TableSumArgs b = sum_args(P, stride);
+  b.out = P->dev.table;
+  b.out_stride = P->Kp;
+  const int64_t n = P->n_pairs * P->npi;
+  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
+  IGAMT_LAUNCH_CHECK();
+  return derive_table_copies(P, stream);
+}
+
+extern "C" igamt_status igamt_tables_build_rows(igamt_plan *P, const int32_t *d_rows, int32_t n_rows, double *d_out,
+                                                void *stream) {
+  if (!P || !d_rows || !d_out || n_rows <= 0) { set_error("invalid argument"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t stride = 0;
+  if ((st = run_points(P, s, stride))) return st;
+  TableSumArgs b = sum_args(P, stride);
+  b.rows = d_rows;
+  b.n_rows = n_rows;
+  b.out = d_out;
+  b.out_stride = P->K;
+  const int64_t n = (int64_t)n_rows * P->npi;
+  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}

@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and the
+integer plan (pair set, CSR structure) is bit-identical to the oracle's brute force.
+No GPU work is done here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly, geometry, tables
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "igamt.h")
+LIB = os.path.join(ROOT, "paper_2107_09568_amd", "libigamt.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libigamt.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(igamt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_all_declared_symbols_exported():
+    L = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2107_09568_amd as P
+    return P
+
+
+@pytest.mark.parametrize("name,kw", [("cfg1", {}), ("cfg4", {"n_boxes": 3}), ("cfg3", {"n_el": 2}),
+                                     ("cfg2", {})])
+def test_pairs_bit_exact(P, name, kw):
+    w = W.make(name, **kw)
+    plan = P.Plan.from_workload(w)
+    np.testing.assert_array_equal(plan.pairs(), tables.pair_set(w.tile).astype(np.int32))
+
+
+@pytest.mark.parametrize("name,kw", [("cfg1", {}), ("cfg4", {"n_boxes": 3}), ("cfg3", {"n_el": 3})])
+def test_csr_structure_bit_exact(P, name, kw):
+    w = W.make(name, **kw)
+    plan = P.Plan.from_workload(w)
+    rp, ci = plan.csr_host()
+    orp, oci = assembly.csr_pattern(w, tables.pair_set(w.tile))
+    assert plan.nnz == len(oci)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(ci, oci)
+
+
+def test_sizes_cfg3_full(P):
+    w = W.make("cfg3")
+    plan = P.Plan.from_workload(w)
+    assert plan.n_tiles == 32768
+    assert plan.n_pairs == 3492
+    assert plan.n_cols == 243
+    assert plan.n_dofs == 3 * 129 ** 3
+    assert plan.nnz == 9 * 577 ** 3   # 1-D neighbour count 577 = 31*5 + 2*3 + 64*4 + 32*5
+
+
+def test_sampled_rows_cfg2(P):
+    """cfg2 CSR structure on sampled rows against the oracle's one-by-one enumeration."""
+    w = W.make("cfg2")
+    plan = P.Plan.from_workload(w)
+    rp, ci = plan.csr_host()
+    pairs = tables.pair_set(w.tile)
+    zero = np.zeros((len(pairs), 9))
+    rows = [0, 1, 2, 3 * 777 + 1, plan.n_dofs // 2, plan.n_dofs - 1]
+    got = assembly.csr_rows(w, pairs, lambda t: zero, rows)
+    for r in rows:
+        np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], got[r][0])
+
+
+def _with(w, **changes):
+    import dataclasses
+    return dataclasses.replace(w, **changes)
+
+
+def test_error_codes(P):
+    w = W.make("cfg1")
+    # box_mode 0 with the wrong tile count
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, w.tile, (3, 2, 2), 0, 2, 3, 3)
+    assert e.value.code == -1
+    # tile boundary moved away from the identity
+    bad = w.tile.copy()
+    bad.ctrl[0, 0, 0, 0] += 0.01
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, bad, w.tiles, 0, 2, 3, 3)
+    assert e.value.code == -1
+    # decreasing knots
+    badm = w.macro.copy()
+    k = badm.knots[0].copy()
+    k[3], k[4] = 0.9, 0.2
+    badm.knots = (k, badm.knots[1], badm.knots[2])
+    with pytest.raises(P.IgamtError):
+        P.Plan(badm, w.tile, w.tiles, 0, 2, 3, 3)
+    # NaN control point
+    badm = w.macro.copy()
+    badm.ctrl[1, 1, 1, 0] = np.nan
+    with pytest.raises(P.IgamtError):
+        P.Plan(badm, w.tile, w.tiles, 0, 2, 3, 3)
+    # n_fit < q + 1
+    with pytest.raises(P.IgamtError):
+        P.Plan(w.macro, w.tile, w.tiles, 0, 2, 2, 3)
+    # repeated interior tile knot
+    t2 = W.identity_spline((2, 2, 2), (2, 2, 2))
+    t2.knots = (np.array([0, 0, 0, .5, .5, 1, 1, 1.]), t2.knots[1], t2.knots[2])
+    t2.ctrl = np.concatenate([t2.ctrl, t2.ctrl[:, :, -1:]], axis=2)
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, t2, w.tiles, 0, 2, 3, 3)
+    assert e.value.code in (-1, -6)

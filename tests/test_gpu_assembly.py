@@ -1,0 +1,242 @@
+"""GPU parity of the assembly path (fit, table, contraction, scatter) against the CPU oracle.
+
+Tolerances (relative Frobenius norm per tile block, against the FP64 oracle):
+FP64 1e-12, FP32 1e-6, BF16x3 / F16x3 1e-4.  Integer work (pairs, CSR structure)
+is compared bit for bit; two runs of the same call must be bitwise identical.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly, projection, tables
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 1e-4, "f16x3": 1e-4}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2107_09568_amd as P
+    return P
+
+
+class OracleCase:
+    def __init__(self, w, tile_ids=None):
+        self.w = w
+        self.pairs = tables.pair_set(w.tile)
+        self.table = tables.stiffness_table(w.tile, w.q, w.n_gauss, self.pairs)
+        self.tile_ids = list(range(w.n_tiles)) if tile_ids is None else list(tile_ids)
+        self.coef = projection.all_coefficients(w, self.tile_ids)
+        self.blocks = assembly.tile_blocks(self.table, self.coef)
+        self._bt = dict(zip(self.tile_ids, self.blocks))
+
+    def block(self, t):
+        if t not in self._bt:
+            self._bt[t] = self.table @ projection.tile_coefficients(self.w, t)
+        return self._bt[t]
+
+
+@pytest.fixture(scope="module")
+def cfg1(P, torch):
+    w = W.make("cfg1")
+    _say("cfg1: oracle")
+    oc = OracleCase(w)
+    plan = P.Plan.from_workload(w)
+    _say("cfg1: tables_build")
+    plan.tables_build()
+    torch.cuda.synchronize()
+    return w, oc, plan
+
+
+def _block_errs(got, ref):
+    d = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1)
+    return d / np.linalg.norm(ref.reshape(len(ref), -1), axis=1)
+
+
+def test_table_cfg1(cfg1, torch):
+    w, oc, plan = cfg1
+    T = plan.tables_get().cpu().numpy()
+    err = np.linalg.norm(T - oc.table) / np.linalg.norm(oc.table)
+    _say(f"cfg1 table rel err {err:.2e}")
+    assert err < 1e-13
+    assert np.abs(T - oc.table).max() < 1e-13 * np.abs(oc.table).max()
+
+
+def test_fit_cfg1(cfg1, torch):
+    w, oc, plan = cfg1
+    coef = plan.fit(w.E, w.nu, "f64")
+    plan.check()
+    got = plan.coef_view(coef).cpu().numpy()
+    err = np.abs(got - oc.coef).max() / np.abs(oc.coef).max()
+    _say(f"cfg1 coef max rel err {err:.2e}")
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_blocks_cfg1(cfg1, torch, prec):
+    w, oc, plan = cfg1
+    _say(f"cfg1 contract {prec}")
+    coef = plan.fit(w.E, w.nu, prec)
+    blocks = plan.contract(coef, prec)
+    torch.cuda.synchronize()
+    e = _block_errs(blocks.double().cpu().numpy(), oc.blocks)
+    _say(f"cfg1 {prec} per-block rel err max {e.max():.2e} median {np.median(e):.2e}")
+    assert e.max() < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_csr_cfg1_full(cfg1, torch, prec):
+    w, oc, plan = cfg1
+    _say(f"cfg1 assemble {prec}")
+    vals = plan.assemble(w.E, w.nu, prec)
+    plan.check()
+    rp, ci, v = assembly.assemble_csr(w, oc.pairs, oc.blocks)
+    got = vals.double().cpu().numpy()
+    err = np.linalg.norm(got - v) / np.linalg.norm(v)
+    _say(f"cfg1 {prec} CSR rel err {err:.2e}")
+    assert err < TOL[prec]
+    again = plan.assemble(w.E, w.nu, prec)
+    torch.cuda.synchronize()
+    assert torch.equal(vals, again), "assembly is not bitwise reproducible"
+
+
+def test_device_csr_structure_cfg1(cfg1, torch):
+    w, oc, plan = cfg1
+    rp_d, ci_d = plan.csr_device()
+    rp, ci = plan.csr_host()
+    np.testing.assert_array_equal(rp_d.cpu().numpy(), rp)
+    np.testing.assert_array_equal(ci_d.cpu().numpy(), ci)
+
+
+def test_stage_entry_points_compose(cfg1, torch):
+    """fit -> contract -> scatter through the stage entry points equals assemble."""
+    w, oc, plan = cfg1
+    coef = plan.fit(w.E, w.nu, "f64")
+    blocks = plan.contract(coef, "f64")
+    vals = plan.scatter(blocks, "f64")
+    ref = plan.assemble(w.E, w.nu, "f64")
+    torch.cuda.synchronize()
+    assert torch.equal(vals, ref)
+
+
+def test_rigid_translations_gpu(cfg1, torch, P):
+    w, oc, plan = cfg1
+    vals = plan.assemble(w.E, w.nu, "f64")
+    rp, ci = plan.csr_device()
+    scale = vals.abs().max().item()
+    for a in range(3):
+        t = torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda")
+        t[a::3] = 1.0
+        r = P.spmv(rp, ci, vals, t)
+        assert r.abs().max().item() < 1e-12 * scale
+
+
+def test_tables_missing_is_an_error(P, torch):
+    w = W.make("cfg1")
+    plan = P.Plan.from_workload(w)
+    with pytest.raises(P.IgamtError) as e:
+        plan.assemble(w.E, w.nu, "f64")
+    assert e.value.code == -7
+
+
+def test_degenerate_macro_reported(P, torch):
+    w = W.make("cfg1")
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    folded = w.macro.ctrl.copy()
+    folded[1, 1, 1] = folded[1, 1, 2] + np.array([0.6, 0.0, 0.0])   # interior point pushed through its neighbour
+    plan.set_macro_ctrl(folded)
+    plan.assemble(w.E, w.nu, "f64")
+    with pytest.raises(P.IgamtError) as e:
+        plan.check()
+    assert e.value.code == -3
+    plan.set_macro_ctrl(w.macro.ctrl)
+    plan.assemble(w.E, w.nu, "f64")
+    plan.check()
+
+
+def test_ragged_tile_count_uniform_boxes(P, torch):
+    """27 tiles (not a multiple of 16), uniform boxes straddling macro knots, cubic macro map."""
+    w = W.make("cfg4", n_boxes=3)
+    _say("cfg4(3^3) oracle")
+    oc = OracleCase(w)
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    for prec in ("f64", "f32", "bf16x3"):
+        vals = plan.assemble(w.E, w.nu, prec)
+        plan.check()
+        rp, ci, v = assembly.assemble_csr(w, oc.pairs, oc.blocks)
+        err = np.linalg.norm(vals.double().cpu().numpy() - v) / np.linalg.norm(v)
+        _say(f"cfg4(3^3) {prec} CSR rel err {err:.2e}")
+        assert err < TOL[prec]
+
+
+def test_tables_set_roundtrip(P, torch, cfg1):
+    w, oc, plan = cfg1
+    plan2 = P.Plan.from_workload(w)
+    plan2.tables_set(torch.from_numpy(oc.table).cuda())
+    a = plan2.assemble(w.E, w.nu, "f64")
+    b = plan.assemble(w.E, w.nu, "f64")
+    torch.cuda.synchronize()
+    assert (a - b).abs().max().item() <= 1e-13 * b.abs().max().item()
+    np.testing.assert_array_equal(plan2.tables_get().cpu().numpy(), oc.table)
+
+
+@pytest.fixture(scope="module")
+def cfg2(P, torch):
+    w = W.make("cfg2")
+    rng = np.random.default_rng(2)
+    sample = sorted(rng.choice(w.n_tiles, size=12, replace=False).tolist())
+    _say("cfg2: oracle (table + 12 tiles)")
+    oc = OracleCase(w, sample)
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    torch.cuda.synchronize()
+    return w, oc, plan
+
+
+def test_table_cfg2(cfg2, torch):
+    w, oc, plan = cfg2
+    T = plan.tables_get().cpu().numpy()
+    err = np.linalg.norm(T - oc.table) / np.linalg.norm(oc.table)
+    _say(f"cfg2 table rel err {err:.2e}")
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_blocks_cfg2(cfg2, torch, prec):
+    w, oc, plan = cfg2
+    coef = plan.fit(w.E, w.nu, prec)
+    blocks = plan.contract(coef, prec)
+    plan.check()
+    got = blocks[oc.tile_ids].double().cpu().numpy()
+    e = _block_errs(got, oc.blocks)
+    _say(f"cfg2 {prec} per-block rel err max {e.max():.2e}")
+    assert e.max() < TOL[prec]
+
+
+def test_csr_rows_cfg2(cfg2, torch):
+    w, oc, plan = cfg2
+    vals = plan.assemble(w.E, w.nu, "f64")
+    rp, ci = plan.csr_host()
+    rng = np.random.default_rng(5)
+    rows = rng.choice(plan.n_dofs, size=6, replace=False)
+    ref = assembly.csr_rows(w, oc.pairs, oc.block, rows)
+    v = vals.cpu().numpy()
+    for r in rows:
+        cols, rv = ref[int(r)]
+        np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], cols)
+        got = v[rp[r]:rp[r + 1]]
+        assert np.linalg.norm(got - rv) <= 1e-12 * np.linalg.norm(rv)

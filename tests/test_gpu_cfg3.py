@@ -1,0 +1,82 @@
+"""Full-size parity at the benchmark's workload (torus sector, 32^3 tiles, q = 2) in the same
+launch configuration the benchmark times: sampled tile blocks and sampled CSR rows are
+compared with the oracle, which computes them one by one."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly, projection, tables
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 1e-4, "f16x3": 1e-4}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+    import paper_2107_09568_amd as P
+    w = W.make("cfg3")
+    _say("cfg3: plan + tables")
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    pairs = tables.pair_set(w.tile)
+    table = plan.tables_get().cpu().numpy()
+    ref_table = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    rng = np.random.default_rng(33)
+    # first, last and interior tiles plus a seeded sample
+    sample = sorted(set([0, 1, 31, 32 * 32 - 1, w.n_tiles - 1] + rng.choice(w.n_tiles, 11, replace=False).tolist()))
+    return torch, P, w, plan, pairs, table, ref_table, sample
+
+
+def test_cfg3_table(case):
+    torch, P, w, plan, pairs, table, ref_table, sample = case
+    err = np.linalg.norm(table - ref_table) / np.linalg.norm(ref_table)
+    _say(f"cfg3 table rel err {err:.2e}")
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_cfg3_sampled_blocks_and_rows(case, prec):
+    torch, P, w, plan, pairs, table, ref_table, sample = case
+    _say(f"cfg3 {prec}: assemble")
+    cb, bb = plan.workspace_bytes(prec)
+    ws = plan.workspace(prec)
+    vals = plan.assemble(w.E, w.nu, prec, workspace=ws)
+    plan.check()
+    torch.cuda.synchronize()
+    dt = torch.float64 if prec == "f64" else torch.float32
+    blocks = ws.view(torch.uint8)[cb:cb + w.n_tiles * plan.n_pairs * 9 * (8 if prec == "f64" else 4)].view(dt)
+    blocks = blocks.view(w.n_tiles, plan.n_pairs, 9)
+    P_ = projection.projection_operator(w.q, w.n_fit)
+    errs = []
+    for t in sample:
+        ref = ref_table @ projection.tile_coefficients(w, t, P_)
+        got = blocks[t].double().cpu().numpy()
+        errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    _say(f"cfg3 {prec} sampled per-block rel err max {max(errs):.2e}")
+    assert max(errs) < TOL[prec]
+    # sampled CSR rows (structure bit-exact, values within tolerance)
+    rng = np.random.default_rng(7)
+    rows = [0, plan.n_dofs - 1] + rng.choice(plan.n_dofs, 3, replace=False).tolist()
+    rp, ci = plan.csr_device()
+    cache = {}
+
+    def blk(t):
+        if t not in cache:
+            cache[t] = ref_table @ projection.tile_coefficients(w, t, P_)
+        return cache[t]
+
+    ref = assembly.csr_rows(w, pairs, blk, rows)
+    for r in rows:
+        lo, hi = int(rp[r].item()), int(rp[r + 1].item())
+        cols, rv = ref[int(r)]
+        np.testing.assert_array_equal(ci[lo:hi].cpu().numpy(), cols)
+        got = vals[lo:hi].double().cpu().numpy()
+        assert np.linalg.norm(got - rv) <= TOL[prec] * np.linalg.norm(rv)
+    del vals, ws, blocks, rp, ci
+    torch.cuda.empty_cache()
