@@ -206,7 +206,8 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
     }
   }
 
-  // epilogue: lane holds C[row 4 kq + r][col l16] of each 16x16 block
+  // epilogue: lane holds C[row][col l16] of each 16x16 block with row = 4 kq + r for the
+  // FP32-accumulating instructions and row = kq + 4 r for the FP64 one (measured layouts)
   O *out = (O *)a.out;
 #pragma unroll
   for (int ni = 0; ni < 9; ++ni) {
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t m = row0 + mi * 16 + 4 * kq + r;
+        const int64_t m = row0 + mi * 16 + (MODE == IGAMT_F64 ? kq + 4 * r : 4 * kq + r);
         if (m >= a.M) continue;
         O v = (O)acc[mi][ni][r];
         if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[m] * cs);

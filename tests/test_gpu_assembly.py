@@ -156,12 +156,13 @@ def test_degenerate_macro_reported(P, torch):
     plan = P.Plan.from_workload(w)
     plan.tables_build()
     folded = w.macro.ctrl.copy()
-    folded[1, 1, 1] = folded[1, 1, 2] + np.array([0.6, 0.0, 0.0])   # interior point pushed through its neighbour
+    folded[1, 1, 1, 0] = -0.6   # interior point mirrored past the boundary: det J < 0 at fit points of tile 0 only
     plan.set_macro_ctrl(folded)
     plan.assemble(w.E, w.nu, "f64")
     with pytest.raises(P.IgamtError) as e:
         plan.check()
     assert e.value.code == -3
+    assert "tile 0" in str(e.value)
     plan.set_macro_ctrl(w.macro.ctrl)
     plan.assemble(w.E, w.nu, "f64")
     plan.check()
