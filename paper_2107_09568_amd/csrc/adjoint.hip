@@ -1,15 +1,479 @@
-// Shape sensitivities of u^T K u (Section 4.1.2).
+// Shape sensitivity of u^T K^pi u with respect to the macro control points
+// (Section 4.1.2, eq. (69)-(73)), u fixed.
+//
+// Per tile t, with Coef^(t) the fitted coefficients (eq. (42)) and the table of
+// eq. (57):
+//   u^T K^(t) u = sum_{k,ab} Coef[k][ab] W[k][ab],
+//   W = table^T U,  U[p][ab] = m_p u_(A,a) u_(B,b),  m_p = 2 if A < B else 1,
+// W being the adjoint field of eq. (71)-(73): the lookup table contracted with
+// products of the tile's displacement coefficients.  Then
+//   Abar(xi_s) = P^T W                       (transpose of the projection)
+//   (Fbar, Dbar) from Abar                   (adjoint of A = D G(F))
+//   Jbar = -F^T Fbar F^T + Dbar D F^T        (F = J^-1, D = det J)
+//   mbar_i += sum_n Jbar[c][n] h_n d_n N_i   (J = J_M(a + h xi) diag(h))
+// Kernels: (1) the fit (FP64); (2) the transposed contraction on MFMA, U formed
+// on the fly from the gathered displacement; (3) the FP64 fit adjoint, one
+// workgroup per tile, giving per-tile gradients of the macro control points the
+// tile touches and the tile's share of u^T K u; (4) deterministic reductions
+// over tiles in ascending order.
 #include "device_common.h"
+
+namespace igamt {
+
+// ---- (2) W = table^T U on MFMA ---------------------------------------------
+struct AdjContractArgs {
+  const void *At;         // table transposed [Kp][Mp] (double or float)
+  const int32_t *pairs;   // [M][2]
+  const double *u;        // global displacement [3 n_global]
+  void *W;                // [n_tiles_pad][9][Kp] (double or float)
+  int64_t M, Mp, Kp, n_tiles;
+  int tiles[3], nT[3], NG[3];
+  int n_kblk;
+};
+
+template <bool F64>
+__global__ __launch_bounds__(256) void adjoint_contract_kernel(AdjContractArgs a) {
+  using E = typename std::conditional<F64, double, float>::type;
+  using Acc = typename std::conditional<F64, d4, f4>::type;
+  constexpr int PC = F64 ? 32 : 64;              // pairs per LDS chunk (256 B per column)
+  constexpr int ROW = PC * sizeof(E) + 16;       // padded LDS row bytes
+  __shared__ __attribute__((aligned(16))) char lds[144 * ROW];
+  const int kb = blockIdx.x % a.n_kblk;
+  const int64_t grp = blockIdx.x / a.n_kblk;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
+  const int64_t k0w = (int64_t)kb * 64 + wave * 16;
+
+  Acc acc[9];
+#pragma unroll
+  for (int ni = 0; ni < 9; ++ni) acc[ni] = Acc{0, 0, 0, 0};
+
+  for (int64_t p0 = 0; p0 < a.Mp; p0 += PC) {
+    __syncthreads();
+    for (int e = tid; e < 144 * PC; e += 256) {
+      const int n = e / PC, pp = e - n * PC;
+      const int64_t p = p0 + pp;
+      const int tl = n / 9, ab = n - 9 * tl;
+      const int64_t t = grp * 16 + tl;
+      double v = 0.0;
+      if (p < a.M && t < a.n_tiles) {
+        const int A = a.pairs[2 * p], B = a.pairs[2 * p + 1];
+        const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
+                           (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
+        const int ai[3] = {A % a.nT[0], (A / a.nT[0]) % a.nT[1], A / (a.nT[0] * a.nT[1])};
+        const int bi[3] = {B % a.nT[0], (B / a.nT[0]) % a.nT[1], B / (a.nT[0] * a.nT[1])};
+        int64_t GA = 0, GB = 0;
+        for (int k = 2; k >= 0; --k) {
+          GA = GA * a.NG[k] + tt[k] * (a.nT[k] - 1) + ai[k];
+          GB = GB * a.NG[k] + tt[k] * (a.nT[k] - 1) + bi[k];
+        }
+        const int aa = ab / 3, bb = ab - 3 * aa;
+        v = (A < B ? 2.0 : 1.0) * a.u[3 * GA + aa] * a.u[3 * GB + bb];
+      }
+      *(E *)(lds + n * ROW + pp * sizeof(E)) = (E)v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < PC; ks += 16) {
+      const E *src = (const E *)a.At + (k0w + l16) * a.Mp + p0 + ks + 4 * kq;
+      E av[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) av[s] = src[s];
+#pragma unroll
+      for (int ni = 0; ni < 9; ++ni) {
+        const E *bp = (const E *)(lds + (ni * 16 + l16) * ROW) + ks + 4 * kq;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          if constexpr (F64)
+            acc[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bp[s], acc[ni], 0, 0, 0);
+          else
+            acc[ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bp[s], acc[ni], 0, 0, 0);
+        }
+      }
+    }
+  }
+  E *W = (E *)a.W;
+#pragma unroll
+  for (int ni = 0; ni < 9; ++ni) {
+    const int n = ni * 16 + l16;
+    const int tl = n / 9, ab = n - 9 * tl;
+    const int64_t t = grp * 16 + tl;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t k = k0w + (F64 ? kq + 4 * r : 4 * kq + r);
+      W[(t * 9 + ab) * a.Kp + k] = (E)acc[ni][r];
+    }
+  }
+}
+
+// ---- (3) fit adjoint ---------------------------------------------------------------
+struct FitAdjArgs {
+  const double *knots[3];
+  int nM[3];
+  const double *ctrl;
+  const double *box_a[3];
+  const double *box_h[3];
+  const int32_t *ctrl_lo[3];
+  int tiles[3], Lc[3];
+  int64_t n_tiles;
+  const double *fx;
+  const double *fP;
+  int q, nf, Kp;
+  bool w_f64;
+  double lam, mu;
+  const double *coef;   // [n_tiles_pad][9][Kp] FP64
+  const void *W;        // same layout, double or float
+  double *local_grad;   // [n_tiles][Lz][Ly][Lx][3]
+  double *uKu_part;     // [n_tiles]
+  int32_t *flag;
+};
+
+template <int PM>
+__global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
+  extern __shared__ double smem[];
+  const int nf = a.nf, q1 = a.q + 1;
+  const int ns = nf * nf * nf, npi = q1 * q1 * q1;
+  double *FD = smem;                 // [ns][10]  F, D
+  double *FB = FD + ns * 10;         // [ns][10]  Fbar (before the factor D), Dbar
+  double *buf0 = FB + ns * 10;       // [max(ns, npi)][9]
+  double *buf1 = buf0 + ns * 9;      // [ns][9]
+  __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
+  __shared__ double NB[3][kMaxFit][kMaxDegree + 1], DB[3][kMaxFit][kMaxDegree + 1];
+  __shared__ int SP[3][kMaxFit];
+  __shared__ double red[64];
+  const int tid = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int64_t tbase = t * 9 * (int64_t)a.Kp;
+  for (int e = tid; e < q1 * nf; e += 64) Pm[e] = a.fP[e];
+  const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
+                     (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
+  const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
+  const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
+  // 1-D macro basis at the tile's sample abscissae (tensor grid)
+  for (int e = tid; e < 3 * nf; e += 64) {
+    const int k = e / nf, s = e % nf;
+    const double x = ax[k] + hx[k] * a.fx[s];
+    const int sp = find_span(a.knots[k], a.nM[k], PM, x);
+    double N[PM + 1], dN[PM + 1];
+    bspline_ders<PM>(a.knots[k], sp, x, N, dN);
+    SP[k][s] = sp;
+    for (int r = 0; r <= PM; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
+  }
+  // F and D at the samples; zero the adjoint accumulators
+  for (int s = tid; s < ns; s += 64) {
+    const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
+    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
+    double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+    int span[3];
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) J[c][k] *= hx[k];
+    double F[3][3];
+    const double D = inv3(J, F);
+    if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag, (int32_t)t);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) FD[s * 10 + 3 * r + c] = F[r][c];
+    FD[s * 10 + 9] = D;
+    for (int k = 0; k < 10; ++k) FB[s * 10 + k] = 0.0;
+  }
+  // this tile's share of u^T K u (fixed-order block reduction)
+  {
+    double part = 0.0;
+    for (int64_t e = tid; e < 9 * (int64_t)a.Kp; e += 64) {
+      const double w = a.w_f64 ? ((const double *)a.W)[tbase + e] : (double)((const float *)a.W)[tbase + e];
+      part += a.coef[tbase + e] * w;
+    }
+    red[tid] = part;
+  }
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) a.uKu_part[t] = red[0];
+
+  for (int ij = 0; ij < 9; ++ij) {
+    const int i = ij / 3, j = ij % 3;
+    // W block of (i, j): buf0[C][ab]
+    for (int e = tid; e < npi * 9; e += 64) {
+      const int C = e / 9, ab = e % 9;
+      const int64_t idx = tbase + (int64_t)ab * a.Kp + 9 * C + ij;
+      buf0[e] = a.w_f64 ? ((const double *)a.W)[idx] : (double)((const float *)a.W)[idx];
+    }
+    __syncthreads();
+    // transpose of the z pass: buf1[(s3, c2, c1)][ab] = sum_c3 P[c3][s3] W[(c3, c2, c1)]
+    for (int e = tid; e < nf * q1 * q1 * 9; e += 64) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1, c2 = (r / q1) % q1, s3 = r / (q1 * q1);
+      double v = 0.0;
+      for (int c3 = 0; c3 < q1; ++c3) v += Pm[c3 * nf + s3] * buf0[((c3 * q1 + c2) * q1 + c1) * 9 + ab];
+      buf1[e] = v;
+    }
+    __syncthreads();
+    // transpose of the y pass: buf0[(s3, s2, c1)][ab]
+    for (int e = tid; e < nf * nf * q1 * 9; e += 64) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1, s2 = (r / q1) % nf, s3 = r / (q1 * nf);
+      double v = 0.0;
+      for (int c2 = 0; c2 < q1; ++c2) v += Pm[c2 * nf + s2] * buf1[((s3 * q1 + c2) * q1 + c1) * 9 + ab];
+      buf0[e] = v;
+    }
+    __syncthreads();
+    // transpose of the x pass: buf1[(s3, s2, s1)][ab] = Abar_ij at sample s
+    for (int e = tid; e < ns * 9; e += 64) {
+      const int ab = e % 9, s = e / 9, s1 = s % nf, s23 = s / nf;
+      double v = 0.0;
+      for (int c1 = 0; c1 < q1; ++c1) v += Pm[c1 * nf + s1] * buf0[(s23 * q1 + c1) * 9 + ab];
+      buf1[e] = v;
+    }
+    __syncthreads();
+    // accumulate the adjoint of A_ij = D G_ij(F) into (Fbar / D, Dbar), one sample per thread
+    for (int s = tid; s < ns; s += 64) {
+      const double *F = FD + s * 10;
+      const double D = F[9];
+      const double *Ab = buf1 + s * 9;     // Abar_ij[a][b]
+      double *fb = FB + s * 10;
+      const double fij = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+      double T = 0.0, dbar = 0.0;
+      for (int aa = 0; aa < 3; ++aa) {
+        T += Ab[4 * aa];
+        for (int bb = 0; bb < 3; ++bb) {
+          const double g = a.lam * F[3 * i + aa] * F[3 * j + bb] + (aa == bb ? a.mu * fij : 0.0) +
+                           a.mu * F[3 * i + bb] * F[3 * j + aa];
+          dbar += Ab[3 * aa + bb] * g;
+        }
+      }
+      fb[9] += dbar;
+      for (int c = 0; c < 3; ++c) {
+        double si = 0.0, sj = 0.0;
+        for (int b = 0; b < 3; ++b) {
+          // lambda terms: d/dF_ic of F_ia F_jb uses Abar[c][b] F_jb; d/dF_jc uses Abar[a][c] F_ia
+          si += a.lam * Ab[3 * c + b] * F[3 * j + b] + a.mu * Ab[3 * b + c] * F[3 * j + b];
+          sj += a.lam * Ab[3 * b + c] * F[3 * i + b] + a.mu * Ab[3 * c + b] * F[3 * i + b];
+        }
+        si += a.mu * T * F[3 * j + c];
+        sj += a.mu * T * F[3 * i + c];
+        fb[3 * i + c] += si;
+        fb[3 * j + c] += sj;
+      }
+      (void)D;
+    }
+    __syncthreads();
+  }
+  // Jbar at each sample, scaled by h (stored over FB[s][0..8])
+  for (int s = tid; s < ns; s += 64) {
+    const double *F = FD + s * 10;
+    double *fb = FB + s * 10;
+    const double D = F[9];
+    double Fb[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Fb[r][c] = D * fb[3 * r + c];   // Gbar = D Abar
+    // M = F^T Fb F^T:  M[c][n] = sum_{r,m} F[r][c] Fb[r][m] F[n][m]
+    double Jb[3][3];
+    for (int c = 0; c < 3; ++c)
+      for (int n = 0; n < 3; ++n) {
+        double m = 0.0;
+        for (int r = 0; r < 3; ++r)
+          for (int q = 0; q < 3; ++q) m += F[3 * r + c] * Fb[r][q] * F[3 * n + q];
+        Jb[c][n] = -m + fb[9] * D * F[3 * n + c];
+      }
+    for (int c = 0; c < 3; ++c)
+      for (int n = 0; n < 3; ++n) fb[3 * c + n] = Jb[c][n] * hx[n];
+  }
+  __syncthreads();
+  // local control-point gradients: mbar[i][c] = sum_s sum_n JbarH[s][c][n] d_n N_i(s)
+  const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2];
+  const int lo[3] = {a.ctrl_lo[0][tt[0]], a.ctrl_lo[1][tt[1]], a.ctrl_lo[2][tt[2]]};
+  double *lg = a.local_grad + t * (int64_t)L0 * L1 * L2 * 3;
+  for (int e = tid; e < L0 * L1 * L2 * 3; e += 64) {
+    const int c = e % 3, li = e / 3;
+    const int l[3] = {li % L0, (li / L0) % L1, li / (L0 * L1)};
+    double g = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
+      double v[3], d[3];
+      bool on = true;
+      for (int k = 0; k < 3; ++k) {
+        const int r = lo[k] + l[k] - (SP[k][si[k]] - PM);
+        if (r < 0 || r > PM) { on = false; break; }
+        v[k] = NB[k][si[k]][r];
+        d[k] = DB[k][si[k]][r];
+      }
+      if (!on) continue;
+      const double *jb = FB + s * 10 + 3 * c;
+      g += jb[0] * d[0] * v[1] * v[2] + jb[1] * v[0] * d[1] * v[2] + jb[2] * v[0] * v[1] * d[2];
+    }
+    lg[e] = g;
+  }
+}
+
+// ---- (4) reductions ------------------------------------------------------------------
+struct GradReduceArgs {
+  const int32_t *off[3];
+  const int32_t *lst[3];
+  int nM[3], tiles[3], Lc[3];
+  const double *local_grad;
+  double *grad;
+};
+
+__global__ __launch_bounds__(256) void grad_reduce_kernel(GradReduceArgs a) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)a.nM[0] * a.nM[1] * a.nM[2];
+  if (id >= 3 * n) return;
+  const int c = (int)(id % 3);
+  const int64_t m = id / 3;
+  const int ix = (int)(m % a.nM[0]), iy = (int)((m / a.nM[0]) % a.nM[1]), iz = (int)(m / ((int64_t)a.nM[0] * a.nM[1]));
+  double g = 0.0;
+  for (int ez = a.off[2][iz]; ez < a.off[2][iz + 1]; ++ez)
+    for (int ey = a.off[1][iy]; ey < a.off[1][iy + 1]; ++ey)
+      for (int ex = a.off[0][ix]; ex < a.off[0][ix + 1]; ++ex) {
+        const int64_t t = a.lst[0][2 * ex] + (int64_t)a.tiles[0] * (a.lst[1][2 * ey] + (int64_t)a.tiles[1] * a.lst[2][2 * ez]);
+        const int lx = a.lst[0][2 * ex + 1], ly = a.lst[1][2 * ey + 1], lz = a.lst[2][2 * ez + 1];
+        g += a.local_grad[(((t * a.Lc[2] + lz) * a.Lc[1] + ly) * a.Lc[0] + lx) * 3 + c];
+      }
+  a.grad[id] = g;
+}
+
+__global__ __launch_bounds__(256) void sum_kernel(const double *x, int64_t n, double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+static int64_t grad_ws_layout(const igamt_plan *P, igamt_precision prec, int64_t off[5]) {
+  const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
+  off[0] = 0;                                                        // coef (FP64)
+  off[1] = off[0] + align256(plane * 8);                             // W
+  off[2] = off[1] + align256(plane * (prec == IGAMT_F64 ? 8 : 4));   // local gradients
+  off[3] = off[2] + align256(P->n_tiles * (int64_t)P->Lc[0] * P->Lc[1] * P->Lc[2] * 3 * 8);
+  off[4] = off[3] + align256(P->n_tiles * 8);                        // uKu parts
+  return off[4];
+}
+
+}  // namespace igamt
 
 using namespace igamt;
 
 extern "C" igamt_status igamt_grad_workspace_bytes(const igamt_plan *P, igamt_precision prec, int64_t *bytes) {
-  set_error("not implemented");
-  return IGAMT_EUNSUPPORTED;
+  if (!P || !bytes) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (prec != IGAMT_F64 && prec != IGAMT_F32) { set_error("gradient contraction runs in F64 or F32"); return IGAMT_EUNSUPPORTED; }
+  int64_t off[5];
+  *bytes = grad_ws_layout(P, prec, off);
+  return IGAMT_OK;
 }
 
 extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt_precision prec, const double *d_u,
                                        double *d_grad, double *d_uKu, void *d_workspace, void *stream) {
-  set_error("not implemented");
-  return IGAMT_EUNSUPPORTED;
+  if (!P || !d_u || !d_grad || !d_workspace) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (prec != IGAMT_F64 && prec != IGAMT_F32) { set_error("gradient contraction runs in F64 or F32"); return IGAMT_EUNSUPPORTED; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
+  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
+    set_error("macro maps with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int64_t off[5];
+  grad_ws_layout(P, prec, off);
+  char *ws = (char *)d_workspace;
+  double *coef = (double *)(ws + off[0]);
+  void *W = ws + off[1];
+  double *lg = (double *)(ws + off[2]);
+  double *part = (double *)(ws + off[3]);
+  // (1) fit in FP64
+  if ((st = launch_fit(P, E, nu, IGAMT_F64, coef, stream))) return st;
+  // (2) W = table^T U
+  AdjContractArgs c;
+  c.At = prec == IGAMT_F64 ? (const void *)P->dev.table_t : (const void *)P->dev.table_t_f32;
+  c.pairs = P->dev.pairs;
+  c.u = d_u;
+  c.W = W;
+  c.M = P->n_pairs;
+  c.Mp = P->Mp;
+  c.Kp = P->Kp;
+  c.n_tiles = P->n_tiles;
+  for (int k = 0; k < 3; ++k) {
+    c.tiles[k] = P->tiles[k];
+    c.nT[k] = P->nT[k];
+    c.NG[k] = P->dir[k].NG;
+  }
+  c.n_kblk = P->Kp / 64;
+  const dim3 cgrid((unsigned)(c.n_kblk * P->n_groups)), block(256);
+  if (prec == IGAMT_F64)
+    hipLaunchKernelGGL(adjoint_contract_kernel<true>, cgrid, block, 0, s, c);
+  else
+    hipLaunchKernelGGL(adjoint_contract_kernel<false>, cgrid, block, 0, s, c);
+  IGAMT_LAUNCH_CHECK();
+  // (3) fit adjoint
+  FitAdjArgs f;
+  for (int k = 0; k < 3; ++k) {
+    f.knots[k] = P->dev.macro_knots[k];
+    f.nM[k] = P->nM[k];
+    f.box_a[k] = P->dev.box_a[k];
+    f.box_h[k] = P->dev.box_h[k];
+    f.ctrl_lo[k] = P->dev.ctrl_lo[k];
+    f.tiles[k] = P->tiles[k];
+    f.Lc[k] = P->Lc[k];
+  }
+  f.ctrl = P->dev.macro_ctrl;
+  f.n_tiles = P->n_tiles;
+  f.fx = P->dev.fit_x;
+  f.fP = P->dev.fit_P;
+  f.q = P->q;
+  f.nf = P->n_fit;
+  f.Kp = P->Kp;
+  f.w_f64 = prec == IGAMT_F64;
+  f.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  f.mu = E / (2.0 * (1.0 + nu));
+  f.coef = coef;
+  f.W = W;
+  f.local_grad = lg;
+  f.uKu_part = part;
+  f.flag = P->dev.flag;
+  const int ns = P->n_fit * P->n_fit * P->n_fit;
+  const size_t shm = (size_t)(10 + 10 + 9 + 9) * std::max(ns, P->npi) * sizeof(double);
+  const dim3 fgrid((unsigned)P->n_tiles), fblock(64);
+  switch (P->pM[0]) {
+#define FA_CASE(p)                                                                                      \
+  case p:                                                                                               \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_adjoint_kernel<p>,                 \
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
+    hipLaunchKernelGGL(fit_adjoint_kernel<p>, fgrid, fblock, shm, s, f);                                \
+    break;
+    FA_CASE(1)
+    FA_CASE(2)
+    FA_CASE(3)
+    FA_CASE(4)
+    FA_CASE(5)
+    FA_CASE(6)
+#undef FA_CASE
+    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  // (4) reductions
+  GradReduceArgs g;
+  for (int k = 0; k < 3; ++k) {
+    g.off[k] = P->dev.ctrl_tiles_off[k];
+    g.lst[k] = P->dev.ctrl_tiles[k];
+    g.nM[k] = P->nM[k];
+    g.tiles[k] = P->tiles[k];
+    g.Lc[k] = P->Lc[k];
+  }
+  g.local_grad = lg;
+  g.grad = d_grad;
+  const int64_t nm = 3LL * P->nM[0] * P->nM[1] * P->nM[2];
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, g);
+  IGAMT_LAUNCH_CHECK();
+  if (d_uKu) {
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, part, P->n_tiles, d_uKu);
+    IGAMT_LAUNCH_CHECK();
+  }
+  return IGAMT_OK;
 }

@@ -164,6 +164,43 @@ __device__ inline double f16_scale_for(double bound) {
   return ldexp(1.0, 14 - e);  // bound * scale < 2^14
 }
 
+// Jacobian of the trivariate B-spline map with control points ctrl
+// ([n2][n1][n0][3], x fastest) at parameter x (degree P in every direction);
+// also returns the span and the 1-D basis values/derivatives used.
+template <int P>
+__device__ inline void spline_jacobian(const double *const *knots, const int *n, const double *__restrict__ ctrl,
+                                       const double (&x)[3], double (&J)[3][3], int (&span)[3],
+                                       double (&N)[3][P + 1], double (&dN)[3][P + 1]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    span[k] = find_span(knots[k], n[k], P, x[k]);
+    bspline_ders<P>(knots[k], span[k], x[k], N[k], dN[k]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) J[c][0] = J[c][1] = J[c][2] = 0.0;
+  for (int rz = 0; rz <= P; ++rz) {
+    const int iz = span[2] - P + rz;
+    for (int ry = 0; ry <= P; ++ry) {
+      const int iy = span[1] - P + ry;
+      const double wyz = N[1][ry] * N[2][rz];
+      const double dy = dN[1][ry] * N[2][rz];
+      const double dz = N[1][ry] * dN[2][rz];
+#pragma unroll
+      for (int rx = 0; rx <= P; ++rx) {
+        const int ix = span[0] - P + rx;
+        const double *c = ctrl + 3 * (ix + (int64_t)n[0] * (iy + (int64_t)n[1] * iz));
+        const double g0 = dN[0][rx] * wyz, g1 = N[0][rx] * dy, g2 = N[0][rx] * dz;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          J[cc][0] += c[cc] * g0;
+          J[cc][1] += c[cc] * g1;
+          J[cc][2] += c[cc] * g2;
+        }
+      }
+    }
+  }
+}
+
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace igamt

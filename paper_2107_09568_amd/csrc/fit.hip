@@ -86,34 +86,9 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
     double N[3][PM + 1], dN[3][PM + 1];
     int span[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double x = ax[k] + hx[k] * a.fx[si[k]];
-      span[k] = find_span(a.knots[k], a.nM[k], PM, x);
-      bspline_ders<PM>(a.knots[k], span[k], x, N[k], dN[k]);
-    }
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int rz = 0; rz <= PM; ++rz) {
-      const int iz = span[2] - PM + rz;
-      for (int ry = 0; ry <= PM; ++ry) {
-        const int iy = span[1] - PM + ry;
-        const double wyz = N[1][ry] * N[2][rz];
-        const double dy = dN[1][ry] * N[2][rz];
-        const double dz = N[1][ry] * dN[2][rz];
-#pragma unroll
-        for (int rx = 0; rx <= PM; ++rx) {
-          const int ix = span[0] - PM + rx;
-          const double *c = a.ctrl + 3 * (ix + (int64_t)a.nM[0] * (iy + (int64_t)a.nM[1] * iz));
-          const double g0 = dN[0][rx] * wyz, g1 = N[0][rx] * dy, g2 = N[0][rx] * dz;
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc) {
-            J[cc][0] += c[cc] * g0;
-            J[cc][1] += c[cc] * g1;
-            J[cc][2] += c[cc] * g2;
-          }
-        }
-      }
-    }
+    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
+    double J[3][3];
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll

@@ -1,0 +1,114 @@
+"""GPU parity of the shape-sensitivity path (Section 4.1.2): d(u^T K u)/d(macro control points)
+against the oracle's independent chain (complex-step dA/dJ) and against central finite
+differences of the GPU's own u^T K u (h = 1e-6, FP64)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint, geometry, tables
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(m):
+    print(m, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2107_09568_amd as P
+    return torch, P
+
+
+def _setup(P, torch, w, seed=7):
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    u = W.random_displacement(plan.n_dofs, seed)
+    return plan, u, torch.from_numpy(u).cuda()
+
+
+def test_grad_small_vs_oracle(env):
+    torch, P = env
+    w = W.make("cfg4", n_boxes=3)
+    plan, u, ud = _setup(P, torch, w)
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    g_ref = adjoint.grad_uKu(w, T, pairs, u)
+    v_ref = adjoint.uKu(w, T, pairs, u)
+    val, grad = plan.uKu_grad(w.E, w.nu, ud, "f64")
+    plan.check()
+    g = grad.cpu().numpy()
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    _say(f"small cfg4 grad f64 vs oracle: {err:.2e}; uKu {val.item():.6e} vs {v_ref:.6e}")
+    assert err < 1e-10
+    assert val.item() == pytest.approx(v_ref, rel=1e-12)
+    val32, grad32 = plan.uKu_grad(w.E, w.nu, ud, "f32")
+    e32 = np.abs(grad32.cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    _say(f"small cfg4 grad f32 vs oracle: {e32:.2e}")
+    assert e32 < 1e-4
+
+
+def test_grad_cfg4_vs_fd_and_oracle(env):
+    """Full differentiation workload: 16^3 uniform boxes on a cubic 8^3 macro net, 20 random control
+    points x 3 coordinates, central differences with h = 1e-6 of the GPU FP64 u^T K u."""
+    torch, P = env
+    w = W.make("cfg4")
+    plan, u, ud = _setup(P, torch, w)
+    val, grad = plan.uKu_grad(w.E, w.nu, ud, "f64")
+    val32, grad32 = plan.uKu_grad(w.E, w.nu, ud, "f32")
+    plan.check()
+    g64 = grad.cpu().numpy()
+    g32 = grad32.cpu().numpy()
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    rng = np.random.default_rng(20)
+    ctrl0 = w.macro.ctrl.copy()
+    h = 1e-6
+    worst64 = worst32 = worst_or = 0.0
+    gscale = np.abs(g64).max()
+    for n in range(20):
+        k = tuple(int(v) for v in rng.integers(0, 8, size=3))
+        for c in range(3):
+            idx = (k[2], k[1], k[0], c)
+            vals = []
+            for sgn in (1, -1):
+                cp = ctrl0.copy()
+                cp[idx] += sgn * h
+                plan.set_macro_ctrl(cp)
+                v, _ = plan.uKu_grad(w.E, w.nu, ud, "f64")
+                vals.append(v.item())
+            fd = (vals[0] - vals[1]) / (2 * h)
+            # error relative to the gradient's scale: central differences of u^T K u carry a rounding
+            # floor of about eps |u^T K u| / h, which dominates components much smaller than max |g|
+            worst64 = max(worst64, abs(g64[idx] - fd) / gscale)
+            worst32 = max(worst32, abs(g32[idx] - fd) / gscale)
+        if n < 4:   # oracle gradient restricted to the tiles that touch this control point
+            tl = adjoint.tiles_touching(w, k)
+            go = adjoint.grad_uKu(w, T, pairs, u, tl)
+            for c in range(3):
+                idx = (k[2], k[1], k[0], c)
+                worst_or = max(worst_or, abs(g64[idx] - go[idx]) / gscale)
+    plan.set_macro_ctrl(ctrl0)
+    _say(f"cfg4: FD err / max|g| f64 {worst64:.2e}, f32 {worst32:.2e}; oracle {worst_or:.2e}; "
+         f"FD rounding floor {2.2e-16 * abs(val.item()) / h / gscale:.1e}")
+    assert worst64 < 1e-6
+    assert worst32 < 1e-4
+    assert worst_or < 1e-10
+
+
+def test_autograd_function(env):
+    torch, P = env
+    from paper_2107_09568_amd.autograd import UKU, Compliance
+    w = W.make("cfg4", n_boxes=2)
+    plan, u, ud = _setup(P, torch, w)
+    ctrl = torch.from_numpy(w.macro.ctrl.copy()).cuda().requires_grad_(True)
+    y = UKU.apply(ctrl, ud, plan, w.E, w.nu, "f64")
+    y.backward()
+    _, g = plan.uKu_grad(w.E, w.nu, ud, "f64")
+    assert torch.equal(ctrl.grad, g)
+    ctrl.grad = None
+    c = Compliance.apply(ctrl, ud, plan, w.E, w.nu, "f64")
+    (2.0 * c).backward()
+    assert torch.equal(ctrl.grad, -2.0 * g)
+    assert c.item() == pytest.approx(y.item(), rel=0, abs=0)
