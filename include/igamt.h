@@ -204,16 +204,20 @@ igamt_status igamt_spmv(igamt_precision prec, int64_t n_rows, const int64_t *d_r
  * POD basis of a set of tables (not in the paper; replaces one table build per
  * design of a parameterised tile family).  d_snap double [n_s][n_e] (n_e =
  * n_pairs * n_cols, row-major tables).  Computes the mean, the Gram matrix of
- * the centred snapshots (FP64, device), its eigenpairs (host), and the r
- * leading modes.  Outputs: d_mean float [n_e], d_basis float [r][n_e]
- * (orthonormal rows), h_sigma double [n_s] singular values (descending).
- * d_work double: n_s * n_s + n_s * r.  Synchronises the stream.              */
+ * the centred snapshots (FP64, device), its eigenpairs (host, cyclic Jacobi),
+ * and the r leading modes.  Outputs: d_mean float [n_e], d_basis float
+ * [r][n_e] (orthonormal rows), h_sigma double [n_s] singular values
+ * (descending), h_coeffs double [n_s][r] (may be NULL): the coefficients of
+ * each centred snapshot in the basis (= V Sigma).  d_work double:
+ * 17 n_s^2 + n_s r + n_e.  Synchronises the stream.                           */
 igamt_status igamt_pod_build(const double *d_snap, int32_t n_s, int64_t n_e, int32_t r,
-                             float *d_mean, float *d_basis, double *h_sigma, double *d_work, void *stream);
-/* Table of a design from POD coefficients: table = mean + basis^T c (FP32
- * inputs, FP64 table written into the plan, then the precision copies).      */
+                             float *d_mean, float *d_basis, double *h_sigma, double *h_coeffs,
+                             double *d_work, void *stream);
+/* Table of a design from POD coefficients: table = mean + basis^T (scale c)
+ * (FP32 mean/basis/coefficients d_coeffs [r], r <= 256, reconstructed in FP64
+ * into the plan's table, then the precision copies are derived).             */
 igamt_status igamt_table_from_pod(igamt_plan *plan, const float *d_mean, const float *d_basis,
-                                  int32_t r, const float *d_coeffs, void *stream);
+                                  int32_t r, const float *d_coeffs, double coeff_scale, void *stream);
 /* Relative Frobenius error of the plan's current table on listed rows against
  * exact rows (d_exact double [n_rows][n_cols]); result to d_err double [1].   */
 igamt_status igamt_table_rows_error(const igamt_plan *plan, const int32_t *d_rows, int32_t n_rows,

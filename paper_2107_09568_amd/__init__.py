@@ -240,10 +240,10 @@ class Plan:
         return val, grad
 
     # ---- learned tables ------------------------------------------------------------------
-    def table_from_pod(self, mean, basis, coeffs):
+    def table_from_pod(self, mean, basis, coeffs, scale=1.0):
         r = basis.shape[0]
         check(lib().igamt_table_from_pod(self._h, _ptr(mean), _ptr(basis), int(r), _ptr(coeffs.contiguous()),
-                                         _stream()))
+                                         float(scale), _stream()))
 
     def table_rows_error(self, rows, exact_rows):
         torch = _torch()

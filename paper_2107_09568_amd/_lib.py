@@ -58,8 +58,8 @@ SIGNATURES = {
     "igamt_grad_workspace_bytes": (status, [vp, i32, P_i64]),
     "igamt_uKu_grad": (status, [vp, f64, f64, i32, vp, vp, vp, vp, vp]),
     "igamt_spmv": (status, [i32, i64, vp, vp, vp, vp, vp, vp]),
-    "igamt_pod_build": (status, [vp, i32, i64, i32, vp, vp, vp, vp, vp]),
-    "igamt_table_from_pod": (status, [vp, vp, vp, i32, vp, vp]),
+    "igamt_pod_build": (status, [vp, i32, i64, i32, vp, vp, vp, vp, vp, vp]),
+    "igamt_table_from_pod": (status, [vp, vp, vp, i32, vp, f64, vp]),
     "igamt_table_rows_error": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_mlp_n_params": (i64, [C.POINTER(MlpDesc)]),
     "igamt_mlp_forward": (status, [C.POINTER(MlpDesc), vp, vp, vp, vp, vp]),

@@ -1,0 +1,161 @@
+"""GPU checks of the learned-table path: MLP kernels against the FP64 oracle (forward, loss,
+backward, Adam), the POD build against the oracle's eigen-decomposition, and the full
+parameterised-tile workflow (exact tables -> POD -> training -> prediction with the
+exact-rows error estimate and the fallback)."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import learned as OL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(m):
+    print(m, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2107_09568_amd as P
+    from paper_2107_09568_amd import learned as L
+    return torch, P, L
+
+
+def _flat(params):
+    return np.concatenate([p.ravel() for p in params])
+
+
+def test_mlp_kernels_vs_oracle(env):
+    torch, P, L = env
+    widths = [4, 16, 12, 8]
+    mlp = L.MLP(widths, batch=10, seed=3)
+    params64 = OL.init_mlp(widths, seed=3)        # same recipe and seed: identical values
+    assert np.allclose(mlp.params.cpu().numpy(), _flat(params64).astype(np.float32))
+    params64 = [p.astype(np.float32).astype(np.float64) for p in params64]
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, size=(10, 4))
+    t = rng.standard_normal((10, 8))
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    tr = L.Trainer(mlp, xd, td)
+    y = mlp.forward(xd).cpu().numpy()
+    y_ref, _ = OL.mlp_forward(params64, x.astype(np.float32).astype(np.float64))
+    assert np.abs(y - y_ref).max() < 1e-5 * np.abs(y_ref).max()
+    # one training step: loss, gradients and the Adam update
+    loss_ref, g_ref = OL.loss_and_grads(params64, x.astype(np.float32).astype(np.float64), t.astype(np.float32))
+    tr.step(1e-3)
+    torch.cuda.synchronize()
+    assert tr.loss.item() == pytest.approx(loss_ref, rel=1e-5)
+    g = tr.grads.cpu().numpy()
+    gr = _flat(g_ref)
+    err = np.abs(g - gr).max() / np.abs(gr).max()
+    _say(f"MLP grads vs FP64 oracle: {err:.2e}")
+    assert err < 1e-5
+    p_ref = [p.copy() for p in params64]
+    m = [np.zeros_like(p) for p in p_ref]
+    v = [np.zeros_like(p) for p in p_ref]
+    for p, gg, mm, vv in zip(p_ref, g_ref, m, v):
+        OL.adam_update(p, gg, mm, vv, step=1, lr=1e-3)
+    err = np.abs(mlp.params.cpu().numpy() - _flat(p_ref)).max()
+    assert err < 2e-6
+
+
+def test_pod_vs_oracle(env):
+    torch, P, L = env
+    rng = np.random.default_rng(8)
+    n_s, n_e, r = 48, 5000, 6
+    X = rng.standard_normal((n_s, 9)) @ rng.standard_normal((9, n_e)) + 1e-3 * rng.standard_normal((n_s, n_e))
+    X += 3.0
+    mean, basis, sigma = OL.pod(X, r)
+    Xd = torch.from_numpy(X).cuda()
+    plan_like = type("PlanLike", (), {"n_pairs": 1, "n_cols": n_e})()
+    tn = L.TableNet.__new__(L.TableNet)
+    tn.n_e, tn.rank = n_e, r
+    s, c = tn.fit_pod(Xd)
+    np.testing.assert_allclose(s[: n_s - 1], sigma[: n_s - 1], rtol=1e-9, atol=1e-9 * sigma[0])
+    B = tn.basis.double().cpu().numpy()
+    np.testing.assert_allclose(B @ B.T, np.eye(r), atol=1e-6)
+    overlap = np.abs(B @ basis)          # same subspace, modes equal up to sign
+    np.testing.assert_allclose(overlap, np.eye(r), atol=1e-5)
+    np.testing.assert_allclose(tn.mean.double().cpu().numpy(), mean, rtol=1e-6)
+    ref_c = (X - mean) @ basis
+    np.testing.assert_allclose(np.abs(c), np.abs(ref_c), rtol=1e-6, atol=1e-9 * np.abs(ref_c).max())
+
+
+@pytest.fixture(scope="module")
+def family(env):
+    torch, P, L = env
+    w = W.make("cfg5")
+    plan = P.Plan.from_workload(w)
+    n_train, n_test = w.extra["n_train"], w.extra["n_test"]
+    p_train = W.family_params(w.extra["train_seed"], n_train)
+    p_test = W.family_params(w.extra["test_seed"], n_test)
+    tn = L.TableNet(plan, rank=w.extra["pod_rank"])
+    _say("cfg5: exact tables of the training designs")
+    t0 = time.perf_counter()
+    snaps = tn.exact_tables([W.tile_family(p).ctrl for p in p_train])
+    torch.cuda.synchronize()
+    t_snap = time.perf_counter() - t0
+    _say(f"cfg5: {n_train} exact tables in {t_snap:.2f} s; POD")
+    sigma, _ = tn.fit_pod(snaps)
+    del snaps
+    _say(f"cfg5: sigma[0] {sigma[0]:.3e}, sigma[63] {sigma[63]:.3e}, sigma[64] {sigma[64]:.3e}; training")
+    hist = tn.train(p_train, steps=8000)
+    _say(f"cfg5: training {tn.train_seconds:.2f} s, loss {hist[0][1]:.3e} -> {hist[-1][1]:.3e}")
+    return torch, P, L, w, plan, tn, p_test
+
+
+def test_learned_tables_heldout(family):
+    torch, P, L, w, plan, tn, p_test = family
+    true_errs, est_errs, fallbacks = [], [], 0
+    for p in p_test:
+        ctrl = W.tile_family(p).ctrl
+        plan.set_tile_ctrl(ctrl)
+        plan.tables_build()
+        exact = plan.tables_get()
+        est, fb = tn.table_for(p, ctrl)
+        got = plan.tables_get()
+        true = ((got - exact).norm() / exact.norm()).item()
+        fallbacks += int(fb)
+        if fb:
+            assert torch.equal(got, exact)
+        else:
+            true_errs.append(true)
+            est_errs.append(est)
+            assert true < 3 * tn.tol
+    _say(f"held-out designs: {len(p_test) - fallbacks} learned, {fallbacks} fallbacks; "
+         f"true table err max {max(true_errs, default=0):.2e}, estimator max {max(est_errs, default=0):.2e}")
+    if est_errs:
+        ratio = np.array(est_errs) / np.array(true_errs)
+        assert ratio.min() > 0.2 and ratio.max() < 5.0
+
+
+def test_fallback_out_of_range(family):
+    torch, P, L, w, plan, tn, p_test = family
+    p = np.array([0.6, 0.6, 0.1, 0.55])          # outside the training box
+    ctrl = W.tile_family(p).ctrl
+    est, fb = tn.table_for(p, ctrl)
+    got = plan.tables_get().clone()
+    plan.tables_build()                        # exact table of the same design
+    assert fb and est > tn.tol
+    assert torch.equal(got, plan.tables_get())
+
+
+def test_learned_table_in_assembly(family):
+    """Assembling with a learned table differs from the exact-table assembly by about the table error."""
+    torch, P, L, w, plan, tn, p_test = family
+    p = p_test[0]
+    ctrl = W.tile_family(p).ctrl
+    plan.set_tile_ctrl(ctrl)
+    plan.tables_build()
+    ref = plan.assemble(w.E, w.nu, "f64")
+    est, fb = tn.table_for(p, ctrl)
+    got = plan.assemble(w.E, w.nu, "f64")
+    plan.check()
+    err = ((got - ref).norm() / ref.norm()).item()
+    _say(f"assembly with learned table: CSR rel err {err:.2e} (estimated table err {est:.2e}, fallback {fb})")
+    assert err < 3 * tn.tol
