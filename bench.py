@@ -107,6 +107,86 @@ def cpu_baseline(w, n_sample, seed=11):
                       f"{dt:.1f} s; host has {os.cpu_count()} logical CPUs"}
 
 
+def bench_adjoint(torch, W, P, steps):
+    """Shape gradient of u^T K u on the differentiation workload (16^3 uniform boxes, cubic macro net)."""
+    w = W.make("cfg4")
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    u = torch.from_numpy(W.random_displacement(plan.n_dofs, 7)).cuda()
+    out = {"workload": "16x16x16 uniform boxes on a degree-3 8x8x8 macro net, degree-2 2x2x2-element tile, q=3",
+           "n_tiles": plan.n_tiles}
+    for prec in ("f64", "f32"):
+        ws = plan.grad_workspace(prec)
+        for _ in range(2):
+            plan.uKu_grad(w.E, w.nu, u, prec, workspace=ws)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record()
+            plan.uKu_grad(w.E, w.nu, u, prec, workspace=ws)
+            b.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        out[prec] = {"ms_per_gradient": ms, "tile_gradients_per_s": plan.n_tiles / (ms * 1e-3),
+                     "contraction_flops": 2.0 * plan.n_pairs * plan.n_cols * 9 * plan.n_tiles}
+        del ws
+    plan.check()
+    return out
+
+
+def bench_learned(torch, W, P, n_designs=32):
+    """Per-design table latency on the parameterised tile family: exact table build on the GPU
+    versus MLP + POD reconstruction (+ the exact-row error estimate)."""
+    from paper_2107_09568_amd import learned as L
+    w = W.make("cfg5")
+    plan = P.Plan.from_workload(w)
+    tn = L.TableNet(plan, rank=w.extra["pod_rank"])
+    p_train = W.family_params(w.extra["train_seed"], w.extra["n_train"])
+    p_test = W.family_params(w.extra["test_seed"], w.extra["n_test"])[:n_designs]
+    t0 = time.perf_counter()
+    snaps = tn.exact_tables([W.tile_family(p).ctrl for p in p_train])
+    torch.cuda.synchronize()
+    t_snap = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tn.fit_pod(snaps)
+    t_pod = time.perf_counter() - t0
+    del snaps
+    torch.cuda.empty_cache()
+    hist = tn.train(p_train, steps=8000)
+    ctrls = [W.tile_family(p).ctrl for p in p_test]
+    exact_tabs = []
+    t_exact, t_learn, t_est, errs, fallbacks = [], [], [], [], 0
+    for p, c in zip(p_test, ctrls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.set_tile_ctrl(c)
+        plan.tables_build()
+        torch.cuda.synchronize()
+        t_exact.append(time.perf_counter() - t0)
+        exact = plan.tables_get()
+        t0 = time.perf_counter()
+        plan.set_tile_ctrl(c)
+        plan.table_from_pod(tn.mean, tn.basis, tn.predict_coeffs(p)[0], tn.coeff_scale)
+        torch.cuda.synchronize()
+        t_learn.append(time.perf_counter() - t0)
+        errs.append(((plan.tables_get() - exact).norm() / exact.norm()).item())
+        t0 = time.perf_counter()
+        est, fb = tn.table_for(p, c)
+        torch.cuda.synchronize()
+        t_est.append(time.perf_counter() - t0)
+        fallbacks += int(fb)
+    med = lambda x: float(np.median(x)) * 1e3
+    return {"workload": "degree-2 3x3x3-element tile family (pinch, anisotropy x/y/z) ~ U(0,0.3)^4, "
+                        "512 training / held-out designs, POD r=64, MLP 4-128-128-64 GELU",
+            "designs_timed": len(p_test), "exact_table_ms": med(t_exact), "learned_table_ms": med(t_learn),
+            "learned_with_estimate_ms": med(t_est), "speedup_learned_vs_exact": med(t_exact) / med(t_learn),
+            "speedup_with_estimate_vs_exact": med(t_exact) / med(t_est),
+            "table_rel_err_max": float(max(errs)), "table_rel_err_median": float(np.median(errs)),
+            "fallbacks": fallbacks, "offline_s": {"exact_tables_512": t_snap, "pod": t_pod,
+                                                 "train_8000_steps": tn.train_seconds},
+            "final_loss": hist[-1][1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +196,9 @@ def main():
     ap.add_argument("--precisions", default="f64,f32,bf16x3,f16x3")
     ap.add_argument("--cpu-tiles", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the gradient and learned-table sections")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -125,6 +208,13 @@ def main():
     import workloads as W
     import paper_2107_09568_amd as P
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("bench: calibration copy of 1 GiB done")
     w = W.make(args.config)
     log(f"bench: {args.config} plan")
     plan = P.Plan.from_workload(w)
@@ -195,6 +285,11 @@ def main():
                           "scatter_ms": float(np.median(rr["scatter_ms"])), "fit_ms": float(np.median(rr["fit_ms"])),
                           "max_block_rel_err_vs_f64": err}
     out["variants"] = variants
+    if not args.no_extras:
+        log("bench: shape gradient")
+        out["adjoint"] = bench_adjoint(torch, W, P, args.steps)
+        log("bench: learned tables")
+        out["learned"] = bench_learned(torch, W, P)
     if not args.no_cpu:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_tiles)

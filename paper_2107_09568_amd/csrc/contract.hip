@@ -72,8 +72,10 @@ struct Mode<IGAMT_F16X3> {
   static constexpr int KSTEP = 32;
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <int MODE>
-__device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64_t k0, int tid, uint4 (&r)[9]) {
+__device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64_t k0, int tid, u32x4 (&r)[9]) {
   // 144 columns x 16 pieces of 16 B = 2304 pieces, 9 per thread
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -83,21 +85,21 @@ __device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64
     if constexpr (MODE == IGAMT_F64 || MODE == IGAMT_F32) {
       using E = typename Mode<MODE>::E;
       const char *src = (const char *)((const E *)a.B + col * a.Kp + k0) + 16 * j;
-      r[i] = *(const uint4 *)src;
+      r[i] = *(const u32x4 *)src;
     } else {
       const uint16_t *plane = (j < 8) ? (const uint16_t *)a.B : (const uint16_t *)a.B2;
       const char *src = (const char *)(plane + col * a.Kp + k0) + 16 * (j & 7);
-      r[i] = *(const uint4 *)src;
+      r[i] = *(const u32x4 *)src;
     }
   }
 }
 
-__device__ inline void store_chunk_lds(char *lds, int tid, const uint4 (&r)[9]) {
+__device__ inline void store_chunk_lds(char *lds, int tid, const u32x4 (&r)[9]) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int pc = tid + 256 * i;
     const int n = pc >> 4, j = pc & 15;
-    *(uint4 *)(lds + n * LDS_ROW + 16 * j) = r[i];
+    *(u32x4 *)(lds + n * LDS_ROW + 16 * j) = r[i];
   }
 }
 
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
 #pragma unroll
     for (int ni = 0; ni < 9; ++ni) acc[mi][ni] = Acc{0, 0, 0, 0};
 
-  uint4 pre[9];
+  u32x4 pre[9];
   load_chunk_regs<MODE>(a, grp, 0, tid, pre);
 
   for (int64_t k0 = 0; k0 < a.Kp; k0 += M_::KCH) {
@@ -136,48 +138,38 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
 
 #pragma unroll
     for (int ks = 0; ks < M_::KCH; ks += M_::KSTEP) {
-      if constexpr (MODE == IGAMT_F64) {
-        // lane loads k = ks + 4 kq .. +3 for A rows and B columns; 4 MFMA 16x16x4
-        double av[2][4];
+      // All fragments of the k-step are loaded first; MFMAs are then issued so that
+      // consecutive instructions update different accumulators (18 apart).
+      if constexpr (MODE == IGAMT_F64 || MODE == IGAMT_F32) {
+        using E = typename Mode<MODE>::E;
+        E av[2][4], bv[9][4];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
-          const double *src = (const double *)a.A + (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 4 * kq;
-          const double2 x0 = *(const double2 *)src, x1 = *(const double2 *)(src + 2);
-          av[mi][0] = x0.x; av[mi][1] = x0.y; av[mi][2] = x1.x; av[mi][3] = x1.y;
+          const E *src = (const E *)a.A + (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 4 * kq;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) av[mi][s] = src[s];
         }
 #pragma unroll
         for (int ni = 0; ni < 9; ++ni) {
-          const char *bp = lds + (ni * 16 + l16) * LDS_ROW + (ks + 4 * kq) * 8;
-          const double2 y0 = *(const double2 *)bp, y1 = *(const double2 *)(bp + 16);
-          const double bv[4] = {y0.x, y0.y, y1.x, y1.y};
+          const E *bp = (const E *)(lds + (ni * 16 + l16) * LDS_ROW) + ks + 4 * kq;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) bv[ni][s] = bp[s];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], bv[s], acc[mi][ni], 0, 0, 0);
-        }
-      } else if constexpr (MODE == IGAMT_F32) {
-        float av[2][4];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-          const float *src = (const float *)a.A + (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 4 * kq;
-          const float4 x = *(const float4 *)src;
-          av[mi][0] = x.x; av[mi][1] = x.y; av[mi][2] = x.z; av[mi][3] = x.w;
-        }
-#pragma unroll
-        for (int ni = 0; ni < 9; ++ni) {
-          const float4 y = *(const float4 *)(lds + (ni * 16 + l16) * LDS_ROW + (ks + 4 * kq) * 4);
-          const float bv[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-          for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], bv[s], acc[mi][ni], 0, 0, 0);
-        }
+            for (int ni = 0; ni < 9; ++ni) {
+              if constexpr (MODE == IGAMT_F64)
+                acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
+              else
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
+            }
       } else {
-        // split modes: lane loads 8 consecutive k (16 B) of hi and lo; 3 MFMA 16x16x32
+        // split modes: lane holds 8 consecutive k (16 B) of hi and lo; products lo*hi, hi*lo, hi*hi
         using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
-        V8 ah[2], al[2];
+        V8 ah[2], al[2], bh[9], bl[9];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
           const int64_t off = (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 8 * kq;
@@ -187,46 +179,66 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
 #pragma unroll
         for (int ni = 0; ni < 9; ++ni) {
           const char *bp = lds + (ni * 16 + l16) * LDS_ROW + (ks + 8 * kq) * 2;
-          const V8 bh = *(const V8 *)bp;
-          const V8 bl = *(const V8 *)(bp + 128);
-#pragma unroll
-          for (int mi = 0; mi < 2; ++mi) {
-            if constexpr (MODE == IGAMT_BF16X3) {
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh, acc[mi][ni], 0, 0, 0);
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl, acc[mi][ni], 0, 0, 0);
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh, acc[mi][ni], 0, 0, 0);
-            } else {
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[mi], bh, acc[mi][ni], 0, 0, 0);
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mi], bl, acc[mi][ni], 0, 0, 0);
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[mi], bh, acc[mi][ni], 0, 0, 0);
-            }
-          }
+          bh[ni] = *(const V8 *)bp;
+          bl[ni] = *(const V8 *)(bp + 128);
         }
+#pragma unroll
+        for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+          for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 9; ++ni) {
+              const V8 &x = pr == 0 ? al[mi] : ah[mi];
+              const V8 &y = pr == 1 ? bl[ni] : bh[ni];
+              if constexpr (MODE == IGAMT_BF16X3)
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[mi][ni], 0, 0, 0);
+              else
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[mi][ni], 0, 0, 0);
+            }
       }
     }
   }
 
-  // epilogue: lane holds C[row][col l16] of each 16x16 block with row = 4 kq + r for the
-  // FP32-accumulating instructions and row = kq + 4 r for the FP64 one (measured layouts)
+  // Epilogue.  Lane holds C[row][col l16] of each 16x16 block with row = 4 kq + r for the
+  // FP32-accumulating instructions and row = kq + 4 r for the FP64 one (measured layouts).
+  // The wave's 32 x 144 tile is transposed through LDS so that each tile's 32 rows x 9 values
+  // (contiguous in the block array) are written as whole cache lines.
   O *out = (O *)a.out;
+  O *stage = (O *)lds;
+  constexpr int PER_ROUND = (int)(sizeof(lds) / (32 * 144 * sizeof(O)));   // waves staged per round
+  for (int w0 = 0; w0 < 4; w0 += PER_ROUND) {
+    __syncthreads();
+    if (wave >= w0 && wave < w0 + PER_ROUND) {
+      O *ws = stage + (wave - w0) * 32 * 144;
 #pragma unroll
-  for (int ni = 0; ni < 9; ++ni) {
-    const int n = ni * 16 + l16;
-    const int tl = n / 9, ab = n - 9 * tl;
-    const int64_t t = grp * 16 + tl;
-    if (t >= a.n_tiles) continue;
-    float cs = 1.0f;
-    if constexpr (MODE == IGAMT_F16X3) cs = a.Bscale[t * 9 + ab];
+      for (int ni = 0; ni < 9; ++ni) {
+        const int n = ni * 16 + l16;
+        const int tl = n / 9, ab = n - 9 * tl;
+        float cs = 1.0f;
+        if constexpr (MODE == IGAMT_F16X3) cs = a.Bscale[(grp * 16 + tl) * 9 + ab];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = row0 + mi * 16 + (MODE == IGAMT_F64 ? kq + 4 * r : 4 * kq + r);
-        if (m >= a.M) continue;
-        O v = (O)acc[mi][ni][r];
-        if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[m] * cs);
-        out[(t * a.M + m) * 9 + ab] = v;
+          for (int r = 0; r < 4; ++r) {
+            const int ml = mi * 16 + (MODE == IGAMT_F64 ? kq + 4 * r : 4 * kq + r);
+            O v = (O)acc[mi][ni][r];
+            if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[mb * BM + wave * 32 + ml] * cs);
+            ws[(tl * 32 + ml) * 9 + ab] = v;
+          }
       }
+    }
+    __syncthreads();
+    for (int wv = w0; wv < w0 + PER_ROUND && wv < 4; ++wv) {
+      const O *ws = stage + (wv - w0) * 32 * 144;
+      const int64_t r0 = (int64_t)mb * BM + wv * 32;
+      const int rows = (int)min((int64_t)32, a.M - r0);
+      if (rows <= 0) continue;
+      for (int e = tid; e < 16 * 288; e += 256) {
+        const int tl = e / 288, j = e - 288 * tl;
+        const int64_t t = grp * 16 + tl;
+        if (t < a.n_tiles && j < rows * 9) out[(t * a.M + r0) * 9 + j] = ws[tl * 288 + j];
+      }
+    }
   }
 }
 

@@ -58,6 +58,10 @@ struct DevicePtrs {
   int32_t *ctrl_tiles_off[3] = {nullptr, nullptr, nullptr};  // per macro ctrl index: tiles touching it
   int32_t *ctrl_tiles[3] = {nullptr, nullptr, nullptr};      // (tile, local offset) pairs
   int32_t *flag = nullptr;           // smallest degenerate tile index (INT32_MAX = none)
+  int32_t *line_up = nullptr;        // [n_lines][2] pair range whose A lies in the x-line
+  int32_t *line_lo_off = nullptr;    // [n_lines + 1] offsets into line_lo_p
+  int32_t *line_lo_p = nullptr;      // pairs (B, A) with A in the x-line and B < A
+  int32_t *slot_lut = nullptr;       // [n_T][S_z][S_y][S_x] -> staging slot of (A, B) in A's x-line
   // tables
   double *table = nullptr;           // [Mp][Kp] FP64, zero padded
   double *table_t = nullptr;         // [Kp][Mp] FP64 (transposed, for the adjoint)
@@ -91,6 +95,9 @@ struct igamt_plan {
   std::vector<double> box_a[3], box_h[3];
   std::vector<int32_t> pairs;         // [n_pairs][2]
   std::vector<int32_t> pair_lut;      // [nTt][S2][S1][S0]
+  // per tile-local x-line (y + n_y z) of A: upper pair range, lower pair list, staging slots
+  std::vector<int32_t> line_up, line_lo_off, line_lo_p, slot_lut;
+  int max_line_records = 0;
   igamt::Direction dir[3];
   int64_t n_global, nnz;
   // 1-D fit operator
