@@ -87,18 +87,63 @@ __global__ __launch_bounds__(256) void scatter_kernel(ScatterArgs a) {
       const int ey0 = a.off[1][gy], cy = a.off[1][gy + 1] - ey0;
       const int ez0 = a.off[2][gz], cz = a.off[2][gz + 1] - ez0;
       __syncthreads();   // previous line done with the staging buffers
-      {  // stage the line's records, slot rows and 1-D entries
+      {  // stage the line's records, slot rows and 1-D entries; loads are issued in batches
+         // of 8 per thread before any LDS store so that many requests are in flight
         const T *src = blk + ((int64_t)tile * a.M + up_lo) * 9;
-        for (int e = tid; e < n_up * 9; e += 256) stage[e] = src[e];
-        for (int e = tid; e < n_lo * 9; e += 256) {
-          const int r = e / 9, k = e - 9 * r;
-          stage[(n_up + r) * 9 + k] = blk[((int64_t)tile * a.M + a.lo_p[lo0 + r]) * 9 + k];
+        const int nu = n_up * 9;
+        for (int b0 = 0; b0 < nu; b0 += 256 * 8) {
+          T r[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = b0 + u * 256 + tid;
+            r[u] = e < nu ? src[e] : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = b0 + u * 256 + tid;
+            if (e < nu) stage[e] = r[u];
+          }
+        }
+        const int nl = n_lo * 9;
+        const T *tb = blk + (int64_t)tile * a.M * 9;
+        for (int b0 = 0; b0 < nl; b0 += 256 * 8) {
+          int32_t q[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = b0 + u * 256 + tid;
+            q[u] = e < nl ? a.lo_p[lo0 + e / 9] : 0;
+          }
+          T r[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = b0 + u * 256 + tid;
+            r[u] = e < nl ? tb[(int64_t)q[u] * 9 + (e - 9 * (e / 9))] : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = b0 + u * 256 + tid;
+            if (e < nl) stage[(n_up + e / 9) * 9 + (e - 9 * (e / 9))] = r[u];
+          }
         }
         const int32_t *sl = a.slot + (int64_t)line * a.nT[0] * S3;
-        for (int e = tid; e < a.nT[0] * S3; e += 256) SL[e] = sl[e];
-        for (int i = tid; i < cy; i += 256) EY[i] = a.p[1][ey0 + i];
-        for (int i = tid; i < cz; i += 256) EZ[i] = a.p[2][ez0 + i];
-        for (int o = tid; o < cnt[0]; o += 256) {
+        const int ns = a.nT[0] * (int)S3;
+        for (int b0 = 0; b0 < ns; b0 += 256 * 4) {
+          int32_t r[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = b0 + u * 256 + tid;
+            r[u] = e < ns ? sl[e] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = b0 + u * 256 + tid;
+            if (e < ns) SL[e] = r[u];
+          }
+        }
+        if (tid < cy) EY[tid] = a.p[1][ey0 + tid];
+        if (tid >= 64 && tid - 64 < cz) EZ[tid - 64] = a.p[2][ez0 + tid - 64];
+        if (tid >= 128 && tid - 128 < cnt[0]) {
+          const int o = tid - 128;
           const int gx = gx0 + o;
           const int64_t cx = a.pre[0][gx + 1] - a.pre[0][gx];
           RB[o] = 9 * (a.pre[2][gz] * SY * SX + (int64_t)cz * (a.pre[1][gy] * SX + (int64_t)cy * a.pre[0][gx]));
@@ -205,7 +250,10 @@ igamt_status launch_scatter(igamt_plan *P, igamt_precision prec, const void *d_b
   a.values = d_values;
   const size_t elem = prec == IGAMT_F64 ? 8 : 4;
   const size_t shm = scatter_lds(P, elem, max_x_entries);
-  if (shm > 160 * 1024) { set_error("tile too large for the scatter kernel's LDS staging"); return IGAMT_EUNSUPPORTED; }
+  if (shm > 160 * 1024 || P->nT[0] > 128) {
+    set_error("tile too large for the scatter kernel's LDS staging");
+    return IGAMT_EUNSUPPORTED;
+  }
   const dim3 grid((unsigned)(8 * a.per_xcd)), block(256);
   hipStream_t s = (hipStream_t)stream;
   if (prec == IGAMT_F64) {
