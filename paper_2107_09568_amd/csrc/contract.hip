@@ -3,14 +3,19 @@
 // i.e. C (n_pairs x 9 m_M) = A (n_pairs x K) B (K x 9 m_M), on gfx950 MFMA.
 //
 // Layout: A row-major [Mp][Kp] and B column-major [n_tiles_pad*9][Kp], so both
-// operands are contiguous along k.  A workgroup (4 waves) owns 128 table rows x
-// one group of 16 tiles (144 columns); each wave owns 32 rows x 144 columns
-// (2 x 9 MFMA 16x16 blocks).  B chunks of 256 bytes per column are staged in
-// LDS through registers (next chunk loaded while the current one is consumed);
-// each wave reads its A rows straight from global memory (they are not shared
-// between waves).  Within a lane group the k index is permuted so that every
-// lane loads contiguous k values with one vector load; A and B use the same
-// permutation, so the sum over k is unchanged.
+// operands are contiguous along k.  A workgroup owns 128 table rows x one group
+// of 16 tiles (144 columns).  Its waves split the rows: each wave owns WM 16-row
+// blocks x 144 columns (WM x 9 MFMA 16x16 blocks), WM = 1 with 8 waves for FP64
+// and FP32, WM = 2 with 4 waves for the split modes.  The FP64 shape keeps every
+// register of a wave within the 256 that leave the accumulators in VGPRs: the
+// FP64 MFMA runs about 2.3x slower when it accumulates in AGPRs.
+//
+// B chunks of 256 bytes per column are staged in LDS through registers, one chunk
+// ahead, into alternating buffers; each wave reads its A rows straight from
+// global memory one k-step ahead (they are not shared between waves).  Within a
+// lane group the k index is permuted so that every lane loads contiguous k
+// values with one vector load; A and B use the same permutation, so the sum over
+// k is unchanged.
 //
 // Work order is XCD-aware: consecutive workgroups of one XCD take all row
 // blocks of one column group, so a column group is fetched from HBM once and
@@ -24,6 +29,7 @@ constexpr int BM = 128;                 // table rows per workgroup
 constexpr int BN = 144;                 // columns per workgroup (16 tiles x 9)
 constexpr int CHUNK_BYTES = 256;        // bytes of one B column staged per chunk
 constexpr int LDS_ROW = CHUNK_BYTES + 16;
+constexpr int PIECES = BN * CHUNK_BYTES / 16;   // 16-byte pieces of one staged chunk
 
 struct ContractArgs {
   const void *A;          // table (hi plane for split modes)
@@ -46,6 +52,7 @@ struct Mode<IGAMT_F64> {
   using Acc = d4;
   static constexpr int KCH = 32;         // k per chunk (256 B of doubles)
   static constexpr int KSTEP = 16;       // k consumed per lane-load step
+  static constexpr int WM = 1;           // 16-row blocks per wave
 };
 template <>
 struct Mode<IGAMT_F32> {
@@ -54,6 +61,7 @@ struct Mode<IGAMT_F32> {
   using Acc = f4;
   static constexpr int KCH = 64;
   static constexpr int KSTEP = 16;
+  static constexpr int WM = 1;
 };
 template <>
 struct Mode<IGAMT_BF16X3> {
@@ -62,6 +70,7 @@ struct Mode<IGAMT_BF16X3> {
   using Acc = f4;
   static constexpr int KCH = 64;         // 128 B hi + 128 B lo per column
   static constexpr int KSTEP = 32;
+  static constexpr int WM = 2;
 };
 template <>
 struct Mode<IGAMT_F16X3> {
@@ -70,16 +79,23 @@ struct Mode<IGAMT_F16X3> {
   using Acc = f4;
   static constexpr int KCH = 64;
   static constexpr int KSTEP = 32;
+  static constexpr int WM = 2;
 };
+template <int MODE>
+constexpr int kWaves = BM / (16 * Mode<MODE>::WM);   // waves per workgroup
+template <int MODE>
+constexpr int kPre = (PIECES + 64 * kWaves<MODE> - 1) / (64 * kWaves<MODE>);   // staged pieces per thread
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int MODE>
-__device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64_t k0, int tid, u32x4 (&r)[9]) {
-  // 144 columns x 16 pieces of 16 B = 2304 pieces, 9 per thread
+__device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64_t k0, int tid, u32x4 (&r)[kPre<MODE>]) {
+  // 144 columns x 16 pieces of 16 B; a piece index past the chunk re-reads the first column (unused)
+  constexpr int NT = 64 * kWaves<MODE>;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int pc = tid + 256 * i;
+  for (int i = 0; i < kPre<MODE>; ++i) {
+    int pc = tid + NT * i;
+    if (PIECES % NT != 0 && pc >= PIECES) pc = tid & 15;
     const int n = pc >> 4, j = pc & 15;
     const int64_t col = grp * BN + n;
     if constexpr (MODE == IGAMT_F64 || MODE == IGAMT_F32) {
@@ -94,21 +110,134 @@ __device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64
   }
 }
 
-__device__ inline void store_chunk_lds(char *lds, int tid, const u32x4 (&r)[9]) {
+template <int MODE>
+__device__ inline void store_chunk_lds(char *lds, int tid, const u32x4 (&r)[kPre<MODE>]) {
+  constexpr int NT = 64 * kWaves<MODE>;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int pc = tid + 256 * i;
+  for (int i = 0; i < kPre<MODE>; ++i) {
+    const int pc = tid + NT * i;
+    if (PIECES % NT != 0 && pc >= PIECES) break;
     const int n = pc >> 4, j = pc & 15;
     *(u32x4 *)(lds + n * LDS_ROW + 16 * j) = r[i];
   }
 }
 
+// Wait for this wave's LDS operations, then synchronise the workgroup.  Unlike __syncthreads this
+// does not wait for outstanding global loads, so the register prefetches stay in flight.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Operand fragments of one k-step of one wave: 2 row blocks of A (global) and 9 column blocks of B (LDS).
+template <int MODE, bool SPLIT = (MODE == IGAMT_BF16X3 || MODE == IGAMT_F16X3)>
+struct Frag;
 template <int MODE>
-__global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
+struct Frag<MODE, false> {
+  using E = typename Mode<MODE>::E;
+  // FP64 reads its B fragments from LDS inside mma (one k-slice ahead) instead of a whole k-step
+  // ahead: two full FP64 fragment sets do not fit the register file next to the accumulators.
+  static constexpr bool JIT_B = MODE == IGAMT_F64;
+  static constexpr int WM = Mode<MODE>::WM;
+  E av[WM][4], bv[JIT_B ? 1 : 9][4];
+  __device__ inline void load_a(const ContractArgs &a, int64_t row0, int l16, int kq, int64_t k) {
+#pragma unroll
+    for (int mi = 0; mi < WM; ++mi) {
+      const E *src = (const E *)a.A + (row0 + mi * 16 + l16) * a.Kp + k + 4 * kq;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) av[mi][s] = src[s];
+    }
+  }
+  __device__ inline void load_b(const char *buf, int l16, int kq, int kk) {
+    if constexpr (!JIT_B) {
+#pragma unroll
+      for (int ni = 0; ni < 9; ++ni) {
+        const E *bp = (const E *)(buf + (ni * 16 + l16) * LDS_ROW) + kk + 4 * kq;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bv[ni][s] = bp[s];
+      }
+    }
+  }
+  // consecutive MFMAs update different accumulators (18 apart)
+  __device__ inline void mma(typename Mode<MODE>::Acc (&acc)[WM][9], const char *buf, int l16, int kq, int kk) const {
+    if constexpr (JIT_B) {
+      E b[2][9];
+#pragma unroll
+      for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * LDS_ROW) + kk + 4 * kq);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (s + 1 < 4) {
+#pragma unroll
+          for (int ni = 0; ni < 9; ++ni)
+            b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * LDS_ROW) + kk + 4 * kq + s + 1);
+        }
+#pragma unroll
+        for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 9; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 9; ++ni) {
+            if constexpr (MODE == IGAMT_F64)
+              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
+            else
+              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
+          }
+    }
+  }
+};
+template <int MODE>
+struct Frag<MODE, true> {
+  static constexpr bool JIT_B = false;
+  // lane holds 8 consecutive k (16 B) of the hi and lo planes; products lo*hi, hi*lo, hi*hi
+  using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
+  static constexpr int WM = Mode<MODE>::WM;
+  V8 ah[WM], al[WM], bh[9], bl[9];
+  __device__ inline void load_a(const ContractArgs &a, int64_t row0, int l16, int kq, int64_t k) {
+#pragma unroll
+    for (int mi = 0; mi < WM; ++mi) {
+      const int64_t off = (row0 + mi * 16 + l16) * a.Kp + k + 8 * kq;
+      ah[mi] = *(const V8 *)((const uint16_t *)a.A + off);
+      al[mi] = *(const V8 *)((const uint16_t *)a.A2 + off);
+    }
+  }
+  __device__ inline void load_b(const char *buf, int l16, int kq, int kk) {
+#pragma unroll
+    for (int ni = 0; ni < 9; ++ni) {
+      const char *bp = buf + (ni * 16 + l16) * LDS_ROW + (kk + 8 * kq) * 2;
+      bh[ni] = *(const V8 *)bp;
+      bl[ni] = *(const V8 *)(bp + 128);
+    }
+  }
+  __device__ inline void mma(f4 (&acc)[WM][9], const char *, int, int, int) const {
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+      for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 9; ++ni) {
+          const V8 &x = pr == 0 ? al[mi] : ah[mi];
+          const V8 &y = pr == 1 ? bl[ni] : bh[ni];
+          if constexpr (MODE == IGAMT_BF16X3)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[mi][ni], 0, 0, 0);
+          else
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[mi][ni], 0, 0, 0);
+        }
+  }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(64 * kWaves<MODE>) void contract_kernel(ContractArgs a) {
   using M_ = Mode<MODE>;
+  constexpr int WM = M_::WM;
   using Acc = typename M_::Acc;
   using O = typename M_::O;
-  __shared__ __attribute__((aligned(16))) char lds[BN * LDS_ROW];
+  constexpr int BUF = BN * LDS_ROW;
+  constexpr int SPC = M_::KCH / M_::KSTEP;       // k-steps per staged chunk
+  __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
 
   const int wg = blockIdx.x;
   const int xcd = wg & 7, local = wg >> 3;
@@ -119,97 +248,83 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int64_t row0 = (int64_t)mb * BM + wave * 32;
+  const int64_t row0 = (int64_t)mb * BM + wave * 16 * WM;
+  const int n_chunks = (int)(a.Kp / M_::KCH);
 
-  Acc acc[2][9];
+  Acc acc[WM][9];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 9; ++ni) acc[mi][ni] = Acc{0, 0, 0, 0};
 
-  u32x4 pre[9];
+  // Software pipeline: B chunks go global -> registers -> LDS one chunk ahead into alternating
+  // buffers (one barrier per chunk); the A fragment (and, except for FP64, the B fragment) of
+  // k-step t+1 is loaded while the MFMAs of k-step t run.
+  using F = Frag<MODE>;
+  constexpr bool JIT = F::JIT_B;
+  u32x4 pre[kPre<MODE>];
   load_chunk_regs<MODE>(a, grp, 0, tid, pre);
+  store_chunk_lds<MODE>(lds, tid, pre);
+  if (n_chunks > 1) load_chunk_regs<MODE>(a, grp, M_::KCH, tid, pre);
+  F f[2];
+  f[0].load_a(a, row0, l16, kq, 0);
+  if constexpr (!JIT) {
+    lds_barrier();
+    f[0].load_b(lds, l16, kq, 0);
+  }
 
-  for (int64_t k0 = 0; k0 < a.Kp; k0 += M_::KCH) {
-    __syncthreads();
-    store_chunk_lds(lds, tid, pre);
-    __syncthreads();
-    if (k0 + M_::KCH < a.Kp) load_chunk_regs<MODE>(a, grp, k0 + M_::KCH, tid, pre);
-
-#pragma unroll
-    for (int ks = 0; ks < M_::KCH; ks += M_::KSTEP) {
-      // All fragments of the k-step are loaded first; MFMAs are then issued so that
-      // consecutive instructions update different accumulators (18 apart).
-      if constexpr (MODE == IGAMT_F64 || MODE == IGAMT_F32) {
-        using E = typename Mode<MODE>::E;
-        E av[2][4], bv[9][4];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-          const E *src = (const E *)a.A + (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 4 * kq;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) av[mi][s] = src[s];
-        }
-#pragma unroll
-        for (int ni = 0; ni < 9; ++ni) {
-          const E *bp = (const E *)(lds + (ni * 16 + l16) * LDS_ROW) + ks + 4 * kq;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) bv[ni][s] = bp[s];
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < 9; ++ni) {
-              if constexpr (MODE == IGAMT_F64)
-                acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
-              else
-                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
-            }
-      } else {
-        // split modes: lane holds 8 consecutive k (16 B) of hi and lo; products lo*hi, hi*lo, hi*hi
-        using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
-        V8 ah[2], al[2], bh[9], bl[9];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-          const int64_t off = (row0 + mi * 16 + l16) * a.Kp + k0 + ks + 8 * kq;
-          ah[mi] = *(const V8 *)((const uint16_t *)a.A + off);
-          al[mi] = *(const V8 *)((const uint16_t *)a.A2 + off);
-        }
-#pragma unroll
-        for (int ni = 0; ni < 9; ++ni) {
-          const char *bp = lds + (ni * 16 + l16) * LDS_ROW + (ks + 8 * kq) * 2;
-          bh[ni] = *(const V8 *)bp;
-          bl[ni] = *(const V8 *)(bp + 128);
-        }
-#pragma unroll
-        for (int pr = 0; pr < 3; ++pr)
-#pragma unroll
-          for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < 9; ++ni) {
-              const V8 &x = pr == 0 ? al[mi] : ah[mi];
-              const V8 &y = pr == 1 ? bl[ni] : bh[ni];
-              if constexpr (MODE == IGAMT_BF16X3)
-                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[mi][ni], 0, 0, 0);
-              else
-                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[mi][ni], 0, 0, 0);
-            }
-      }
+  // The loop body has no data-dependent branches (the compiler then tracks the outstanding loads
+  // exactly): prefetches past the last chunk re-read the last valid chunk and are not used.
+  const int64_t k_last = a.Kp - M_::KSTEP;
+  for (int c = 0; c < n_chunks; ++c) {
+    const char *cur = lds + (c & 1) * BUF;
+    char *nxt = lds + ((c + 1) & 1) * BUF;
+    const int64_t c2 = (int64_t)min(c + 2, n_chunks - 1) * M_::KCH;
+    if constexpr (JIT) {
+      // chunk c is visible and every wave has finished reading chunk c-1, whose buffer is refilled
+      lds_barrier();
+      store_chunk_lds<MODE>(nxt, tid, pre);
+      load_chunk_regs<MODE>(a, grp, c2, tid, pre);
     }
+#pragma unroll
+    for (int s = 0; s < SPC; ++s) {
+      const int64_t k = (int64_t)c * M_::KCH + s * M_::KSTEP;
+      F &now = f[s & 1], &next = f[(s + 1) & 1];
+      if (s + 1 < SPC) {
+        next.load_a(a, row0, l16, kq, k + M_::KSTEP);
+        next.load_b(cur, l16, kq, (s + 1) * M_::KSTEP);
+      } else {
+        if constexpr (!JIT) {
+          // every wave has passed the previous barrier, after its last read of chunk c-1
+          store_chunk_lds<MODE>(nxt, tid, pre);
+          load_chunk_regs<MODE>(a, grp, c2, tid, pre);
+          lds_barrier();
+          next.load_b(nxt, l16, kq, 0);
+        }
+        next.load_a(a, row0, l16, kq, min(k + M_::KSTEP, k_last));
+      }
+      // keep the prefetches ahead of this k-step's MFMAs (the scheduler would otherwise sink them
+      // towards their first use in the next k-step)
+      __builtin_amdgcn_sched_barrier(0);
+      now.mma(acc, cur, l16, kq, s * M_::KSTEP);
+    }
+    if constexpr (SPC % 2 == 1) f[0] = f[1];
   }
 
   // Epilogue.  Lane holds C[row][col l16] of each 16x16 block with row = 4 kq + r for the
   // FP32-accumulating instructions and row = kq + 4 r for the FP64 one (measured layouts).
-  // The wave's 32 x 144 tile is transposed through LDS so that each tile's 32 rows x 9 values
-  // (contiguous in the block array) are written as whole cache lines.
+  // The waves' tiles are transposed through LDS, several consecutive waves per round, so that
+  // each tile's rows x 9 values (contiguous in the block array) are written as whole lines.
+  constexpr int NW = kWaves<MODE>, WR = 16 * WM, NT = 64 * NW;
+  constexpr int PER_ROUND = (int)(sizeof(lds) / (WR * 144 * sizeof(O))) < NW
+                                ? (int)(sizeof(lds) / (WR * 144 * sizeof(O))) : NW;   // waves per round
+  constexpr int RR = PER_ROUND * WR;                                             // rows per round
   O *out = (O *)a.out;
   O *stage = (O *)lds;
-  constexpr int PER_ROUND = (int)(sizeof(lds) / (32 * 144 * sizeof(O)));   // waves staged per round
-  for (int w0 = 0; w0 < 4; w0 += PER_ROUND) {
+  for (int w0 = 0; w0 < NW; w0 += PER_ROUND) {
     __syncthreads();
     if (wave >= w0 && wave < w0 + PER_ROUND) {
-      O *ws = stage + (wave - w0) * 32 * 144;
+      const int rbase = (wave - w0) * WR;
 #pragma unroll
       for (int ni = 0; ni < 9; ++ni) {
         const int n = ni * 16 + l16;
@@ -217,26 +332,24 @@ __global__ __launch_bounds__(256, 1) void contract_kernel(ContractArgs a) {
         float cs = 1.0f;
         if constexpr (MODE == IGAMT_F16X3) cs = a.Bscale[(grp * 16 + tl) * 9 + ab];
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int ml = mi * 16 + (MODE == IGAMT_F64 ? kq + 4 * r : 4 * kq + r);
             O v = (O)acc[mi][ni][r];
-            if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[mb * BM + wave * 32 + ml] * cs);
-            ws[(tl * 32 + ml) * 9 + ab] = v;
+            if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[mb * BM + wave * WR + ml] * cs);
+            stage[(tl * RR + rbase + ml) * 9 + ab] = v;
           }
       }
     }
     __syncthreads();
-    for (int wv = w0; wv < w0 + PER_ROUND && wv < 4; ++wv) {
-      const O *ws = stage + (wv - w0) * 32 * 144;
-      const int64_t r0 = (int64_t)mb * BM + wv * 32;
-      const int rows = (int)min((int64_t)32, a.M - r0);
-      if (rows <= 0) continue;
-      for (int e = tid; e < 16 * 288; e += 256) {
-        const int tl = e / 288, j = e - 288 * tl;
+    const int64_t r0 = (int64_t)mb * BM + w0 * WR;
+    const int rows = (int)min((int64_t)RR, a.M - r0);
+    if (rows > 0) {
+      for (int e = tid; e < 16 * RR * 9; e += NT) {
+        const int tl = e / (RR * 9), jj = e - RR * 9 * tl;
         const int64_t t = grp * 16 + tl;
-        if (t < a.n_tiles && j < rows * 9) out[(t * a.M + r0) * 9 + j] = ws[tl * 288 + j];
+        if (t < a.n_tiles && jj < rows * 9) out[(t * a.M + r0) * 9 + jj] = stage[tl * RR * 9 + jj];
       }
     }
   }
@@ -276,13 +389,17 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
     default: set_error("unknown precision"); return IGAMT_EINVAL;
   }
   const int64_t groups8 = (P->n_groups + 7) / 8 * 8;
-  const dim3 grid((unsigned)(a.n_mblk * groups8)), block(256);
+  const dim3 grid((unsigned)(a.n_mblk * groups8));
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
-    case IGAMT_F64: hipLaunchKernelGGL(contract_kernel<IGAMT_F64>, grid, block, 0, s, a); break;
-    case IGAMT_F32: hipLaunchKernelGGL(contract_kernel<IGAMT_F32>, grid, block, 0, s, a); break;
-    case IGAMT_BF16X3: hipLaunchKernelGGL(contract_kernel<IGAMT_BF16X3>, grid, block, 0, s, a); break;
-    case IGAMT_F16X3: hipLaunchKernelGGL(contract_kernel<IGAMT_F16X3>, grid, block, 0, s, a); break;
+    case IGAMT_F64: hipLaunchKernelGGL(contract_kernel<IGAMT_F64>, grid, dim3(64 * kWaves<IGAMT_F64>), 0, s, a); break;
+    case IGAMT_F32: hipLaunchKernelGGL(contract_kernel<IGAMT_F32>, grid, dim3(64 * kWaves<IGAMT_F32>), 0, s, a); break;
+    case IGAMT_BF16X3:
+      hipLaunchKernelGGL(contract_kernel<IGAMT_BF16X3>, grid, dim3(64 * kWaves<IGAMT_BF16X3>), 0, s, a);
+      break;
+    case IGAMT_F16X3:
+      hipLaunchKernelGGL(contract_kernel<IGAMT_F16X3>, grid, dim3(64 * kWaves<IGAMT_F16X3>), 0, s, a);
+      break;
   }
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
