@@ -25,11 +25,16 @@
 
 namespace igamt {
 
-constexpr int BM = 128;                 // table rows per workgroup
 constexpr int BN = 144;                 // columns per workgroup (16 tiles x 9)
 constexpr int CHUNK_BYTES = 256;        // bytes of one B column staged per chunk
 constexpr int LDS_ROW = CHUNK_BYTES + 16;
 constexpr int PIECES = BN * CHUNK_BYTES / 16;   // 16-byte pieces of one staged chunk
+#ifndef NW_F64
+#define NW_F64 8
+#endif
+#ifndef NW_F32
+#define NW_F32 8
+#endif
 
 struct ContractArgs {
   const void *A;          // table (hi plane for split modes)
@@ -53,6 +58,7 @@ struct Mode<IGAMT_F64> {
   static constexpr int KCH = 32;         // k per chunk (256 B of doubles)
   static constexpr int KSTEP = 16;       // k consumed per lane-load step
   static constexpr int WM = 1;           // 16-row blocks per wave
+  static constexpr int NW = NW_F64;      // waves per workgroup
 };
 template <>
 struct Mode<IGAMT_F32> {
@@ -62,6 +68,7 @@ struct Mode<IGAMT_F32> {
   static constexpr int KCH = 64;
   static constexpr int KSTEP = 16;
   static constexpr int WM = 1;
+  static constexpr int NW = NW_F32;
 };
 template <>
 struct Mode<IGAMT_BF16X3> {
@@ -71,6 +78,7 @@ struct Mode<IGAMT_BF16X3> {
   static constexpr int KCH = 64;         // 128 B hi + 128 B lo per column
   static constexpr int KSTEP = 32;
   static constexpr int WM = 2;
+  static constexpr int NW = 4;
 };
 template <>
 struct Mode<IGAMT_F16X3> {
@@ -80,9 +88,12 @@ struct Mode<IGAMT_F16X3> {
   static constexpr int KCH = 64;
   static constexpr int KSTEP = 32;
   static constexpr int WM = 2;
+  static constexpr int NW = 4;
 };
 template <int MODE>
-constexpr int kWaves = BM / (16 * Mode<MODE>::WM);   // waves per workgroup
+constexpr int kWaves = Mode<MODE>::NW;                // waves per workgroup
+template <int MODE>
+constexpr int kBM = 16 * Mode<MODE>::WM * Mode<MODE>::NW;   // table rows per workgroup
 template <int MODE>
 constexpr int kPre = (PIECES + 64 * kWaves<MODE> - 1) / (64 * kWaves<MODE>);   // staged pieces per thread
 
@@ -248,6 +259,7 @@ __global__ __launch_bounds__(64 * kWaves<MODE>) void contract_kernel(ContractArg
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
+  constexpr int BM = kBM<MODE>;
   const int64_t row0 = (int64_t)mb * BM + wave * 16 * WM;
   const int n_chunks = (int)(a.Kp / M_::KCH);
 
@@ -363,7 +375,6 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
   a.M = P->n_pairs;
   a.Kp = P->Kp;
   a.n_tiles = P->n_tiles;
-  a.n_mblk = (int)(P->Mp / BM);
   a.n_groups = (int)P->n_groups;
   a.out = d_blocks;
   a.A2 = nullptr;
@@ -388,6 +399,9 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
       break;
     default: set_error("unknown precision"); return IGAMT_EINVAL;
   }
+  const int bm = prec == IGAMT_F64 ? kBM<IGAMT_F64> : prec == IGAMT_F32 ? kBM<IGAMT_F32> : kBM<IGAMT_BF16X3>;
+  if (P->Mp % bm != 0) { set_error("padded table rows are not a multiple of the row block"); return IGAMT_EINVAL; }
+  a.n_mblk = (int)(P->Mp / bm);
   const int64_t groups8 = (P->n_groups + 7) / 8 * 8;
   const dim3 grid((unsigned)(a.n_mblk * groups8));
   hipStream_t s = (hipStream_t)stream;
