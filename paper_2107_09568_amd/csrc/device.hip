@@ -41,6 +41,7 @@ igamt_status ensure_device(igamt_plan *P) {
     UP(d.dir_pairs[k], P->dir[k].pairs);
     UP(d.dir_off[k], P->dir[k].off);
     UP(d.dir_pre[k], P->dir[k].pre);
+    UP(d.dir_lo[k], P->dir[k].lo);
     UP(d.ctrl_lo[k], P->ctrl_lo[k]);
     UP(d.ctrl_tiles_off[k], P->ctrl_tiles_off[k]);
     UP(d.ctrl_tiles[k], P->ctrl_tiles[k]);
@@ -57,6 +58,8 @@ igamt_status ensure_device(igamt_plan *P) {
   UP(d.line_lo_off, P->line_lo_off);
   UP(d.line_lo_p, P->line_lo_p);
   UP(d.slot_lut, P->slot_lut);
+  UP(d.mirror_perm, P->mirror_perm);
+  UP(d.pair_desc, P->pair_desc);
   IGAMT_HIP(hipMalloc((void **)&d.flag, 4 * sizeof(int32_t)));
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, 0, d.flag, 4, INT32_MAX);
   IGAMT_LAUNCH_CHECK();
@@ -82,12 +85,13 @@ void free_device(igamt_plan *P) {
   (void)hipDeviceSynchronize();
   void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
-                  d.table_h_scale, d.point_data, d.line_up, d.line_lo_off, d.line_lo_p, d.slot_lut};
+                  d.table_h_scale, d.point_data, d.line_up, d.line_lo_off, d.line_lo_p, d.slot_lut,
+                  d.mirror_perm, d.pair_desc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 3; ++k) {
     void *q[] = {d.macro_knots[k], d.box_a[k], d.box_h[k], d.tile_knots[k], d.dir_pairs[k], d.dir_off[k],
-                 d.dir_pre[k], d.ctrl_lo[k], d.ctrl_tiles_off[k], d.ctrl_tiles[k]};
+                 d.dir_pre[k], d.dir_lo[k], d.ctrl_lo[k], d.ctrl_tiles_off[k], d.ctrl_tiles[k]};
     for (void *p : q)
       if (p) (void)hipFree(p);
   }

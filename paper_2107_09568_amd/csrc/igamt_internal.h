@@ -15,6 +15,11 @@ constexpr int kMaxFit = 8;         // fit samples per direction
 constexpr int kMaxGauss = 8;       // table quadrature points per direction
 constexpr int kTileGroup = 16;     // tiles per contraction column group (144 columns)
 constexpr int kColPad = 64;        // table columns padded to a multiple of this
+#ifndef IGAMT_SCATTER_CHUNK
+#define IGAMT_SCATTER_CHUNK 256
+#endif
+constexpr int kScatterChunk = IGAMT_SCATTER_CHUNK;   // block records per scatter workgroup
+constexpr int kDescWords = 12;                        // ints per scatter pair descriptor
 constexpr int kRowPad = 128;       // table rows padded to a multiple of this
 
 void set_error(const std::string &msg);
@@ -34,6 +39,7 @@ struct Direction {
   std::vector<Pair1D> pairs;         // sorted by (g, g2)
   std::vector<int32_t> off;          // [NG + 1] first entry of g
   std::vector<int64_t> pre;          // [NG + 1] exclusive prefix of neighbour counts
+  std::vector<int32_t> lo;           // [NG] first neighbour of g (neighbours of g are lo .. lo + count - 1)
 };
 
 struct DevicePtrs {
@@ -54,6 +60,9 @@ struct DevicePtrs {
   Pair1D *dir_pairs[3] = {nullptr, nullptr, nullptr};
   int32_t *dir_off[3] = {nullptr, nullptr, nullptr};
   int64_t *dir_pre[3] = {nullptr, nullptr, nullptr};
+  int32_t *dir_lo[3] = {nullptr, nullptr, nullptr};
+  int32_t *pair_desc = nullptr;      // [n_pairs][kDescWords] scatter descriptor of each pair
+  int32_t *mirror_perm = nullptr;    // [chunks * kScatterChunk] per scatter chunk: records ordered by (B, A)
   int32_t *ctrl_lo[3] = {nullptr, nullptr, nullptr};     // per tile: first local macro ctrl index
   int32_t *ctrl_tiles_off[3] = {nullptr, nullptr, nullptr};  // per macro ctrl index: tiles touching it
   int32_t *ctrl_tiles[3] = {nullptr, nullptr, nullptr};      // (tile, local offset) pairs
@@ -98,6 +107,12 @@ struct igamt_plan {
   // per tile-local x-line (y + n_y z) of A: upper pair range, lower pair list, staging slots
   std::vector<int32_t> line_up, line_lo_off, line_lo_p, slot_lut;
   int max_line_records = 0;
+  // scatter descriptors, kDescWords per pair: w0 = a_x | a_y << 8 | a_z << 16 | flags << 24
+  // (bits 0-2: a_d = b_d = 0, bits 3-5: a_d = b_d = n_d - 1, bit 6: A = B),
+  // w1 = b_x | b_y << 8 | b_z << 16, w[1 + delta] = index of the same pair in the tile shifted by
+  // delta = dx + 2 dy + 4 dz (delta = 1..7; -1 where the pair does not lie on those faces)
+  std::vector<int32_t> pair_desc;
+  std::vector<int32_t> mirror_perm;   // per scatter chunk of the pair list: local order by (B, A)
   igamt::Direction dir[3];
   int64_t n_global, nnz;
   // 1-D fit operator

@@ -301,6 +301,51 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
     }
     P->line_lo_off[n_lines] = (int32_t)P->line_lo_p.size();
   }
+  // scatter descriptors (see igamt_internal.h)
+  {
+    const int nx = P->nT[0], ny = P->nT[1];
+    P->pair_desc.assign(igamt::kDescWords * P->n_pairs, -1);
+    for (int64_t p = 0; p < P->n_pairs; ++p) {
+      const int A = P->pairs[2 * p], B = P->pairs[2 * p + 1];
+      const int ai[3] = {A % nx, (A / nx) % ny, A / (nx * ny)};
+      const int bi[3] = {B % nx, (B / nx) % ny, B / (nx * ny)};
+      int flags = A == B ? 64 : 0, hi = 0;
+      for (int d = 0; d < 3; ++d) {
+        if (ai[d] == 0 && bi[d] == 0) flags |= 1 << d;
+        if (ai[d] == P->nT[d] - 1 && bi[d] == P->nT[d] - 1) { flags |= 8 << d; hi |= 1 << d; }
+      }
+      int32_t *w = &P->pair_desc[igamt::kDescWords * p];
+      w[0] = ai[0] | ai[1] << 8 | ai[2] << 16 | flags << 24;
+      w[1] = bi[0] | bi[1] << 8 | bi[2] << 16;
+      const int off = ((bi[2] - ai[2] + P->pT[2]) * P->S[1] + (bi[1] - ai[1] + P->pT[1])) * P->S[0] +
+                      (bi[0] - ai[0] + P->pT[0]);
+      for (int delta = 1; delta < 8; ++delta) {
+        if (delta & ~hi) continue;
+        const int dx = delta & 1, dy = (delta >> 1) & 1, dz = delta >> 2;
+        const int A2 = A - dx * (nx - 1) - nx * (dy * (ny - 1) + ny * dz * (P->nT[2] - 1));
+        const int32_t q = P->pair_lut[(int64_t)A2 * lut_stride + off];
+        if (q < 0) { set_error("internal: shifted pair missing"); return IGAMT_EINVAL; }
+        w[1 + delta] = q;
+      }
+    }
+  }
+  // scatter chunks of kScatterChunk consecutive pairs: each chunk's records ordered by (B, A), the
+  // order in which the transposed blocks are written (consecutive A of one B are adjacent in row G_B)
+  {
+    const int64_t C = igamt::kScatterChunk;
+    const int64_t chunks = (P->n_pairs + C - 1) / C;
+    P->mirror_perm.assign(chunks * C, 0);
+    for (int64_t c = 0; c < chunks; ++c) {
+      const int64_t p0 = c * C, n = std::min<int64_t>(C, P->n_pairs - p0);
+      int32_t *perm = &P->mirror_perm[c * C];
+      for (int64_t i = 0; i < C; ++i) perm[i] = i < n ? (int32_t)i : 0;
+      std::stable_sort(perm, perm + n, [&](int32_t x, int32_t y) {
+        const int32_t bx = P->pairs[2 * (p0 + x) + 1], by = P->pairs[2 * (p0 + y) + 1];
+        if (bx != by) return bx < by;
+        return P->pairs[2 * (p0 + x)] < P->pairs[2 * (p0 + y)];
+      });
+    }
+  }
   // glued 1-D structure per direction
   for (int d = 0; d < 3; ++d) {
     Direction &D = P->dir[d];
@@ -309,6 +354,7 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
     D.pairs.clear();
     D.off.assign(D.NG + 1, 0);
     D.pre.assign(D.NG + 1, 0);
+    D.lo.assign(D.NG, 0);
     for (int g = 0; g < D.NG; ++g) {
       D.off[g] = (int32_t)D.pairs.size();
       std::vector<Pair1D> lst;
@@ -336,7 +382,15 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
         }
       }
       std::sort(lst.begin(), lst.end(), [](const Pair1D &a, const Pair1D &b) { return a.g2 < b.g2; });
-      for (size_t r = 0; r < lst.size(); ++r) { lst[r].rank = (int32_t)r; D.pairs.push_back(lst[r]); }
+      for (size_t r = 0; r < lst.size(); ++r) {
+        lst[r].rank = (int32_t)r;
+        D.pairs.push_back(lst[r]);
+        if (lst[r].g2 != lst[0].g2 + (int)r) {   // the scatter computes ranks as g2 - first neighbour
+          set_error("1-D neighbour sets must be contiguous (repeated interior tile knots?)");
+          return IGAMT_EUNSUPPORTED;
+        }
+      }
+      D.lo[g] = lst.empty() ? g : lst[0].g2;
       D.pre[g + 1] = D.pre[g] + (int64_t)lst.size();
     }
     D.off[D.NG] = (int32_t)D.pairs.size();

@@ -1,270 +1,225 @@
 // Stage 3 of the assembly: deterministic scatter of the tile blocks into the
 // fixed CSR structure (step 4 of Section 3.2.4).
 //
-// The three CSR rows of a global control point G_A are contiguous (9 nnb(G_A)
-// values: rows a = 0, 1, 2, each listing the neighbours G_B in ascending order
-// with b = 0, 1, 2).  Every control point is owned by one tile (the tile whose
-// local indices in [0, n-2] hold it; the last tile of a direction also owns the
-// closing layer).  One workgroup per tile loops over the tile's owned x-lines
-// of control points; for each line
-//  1. it stages in LDS the tile's block records that the line's rows read: the
-//     pairs (A, B) with A in the line (one contiguous range, pairs being sorted
-//     by A) and the pairs (B, A) with A in the line and B < A (a fixed list), so
-//     every record of the tile is fetched once as an "upper" record and once as
-//     a "lower" one, the second time usually from L2; the line's rows of the
-//     slot table are staged with them;
-//  2. lanes sweep the (G_A, rank of G_B) slot blocks of the line's rows in CSR
-//     order, so stores are coalesced; contributions of the own tile come from
-//     LDS, those of neighbouring tiles (control points on shared faces) from
-//     global memory, always summed in ascending tile index.
-// The result is bitwise reproducible and no atomics are used.  Tiles are
-// handed out XCD-aware (consecutive tiles on one XCD share neighbours' blocks).
-#include <algorithm>
-
+// A workgroup takes kScatterChunk (256) consecutive block records of one tile (pairs p = (A, B),
+// A <= B tile-local), loads them into LDS with coalesced loads, and gives one
+// thread to each record.
+// The record's global pair {G_A, G_B} may be shared with neighbouring tiles:
+// per direction d, the 1-D pair (a_d, b_d) is shared with tile t_d - 1 when
+// a_d = b_d = 0 and with tile t_d + 1 when a_d = b_d = n_d - 1, and the shared
+// tiles hold it with the local indices shifted by n_d - 1 (the pair offset is
+// unchanged, so no transposition arises).  The record of the lowest tile
+// index owns the global pair: every other record is skipped, the owner
+// sums the contributions in ascending tile index (its own first) and writes the
+// 3x3 block at (G_A, G_B) and its transpose at (G_B, G_A).  Every CSR value is
+// written exactly once, every record is read once (by its owner), no atomics
+// are needed, and the result is bitwise reproducible.  The stores go through the
+// LDS copy with a word-level lane mapping so that consecutive lanes write
+// consecutive words of each contiguous run of blocks in a CSR row.
+//
+// CSR addressing needs no search: the three rows of G are contiguous and hold
+// 9 nnb(G) values, with nnb(G) = c_x c_y c_z the product of the 1-D neighbour
+// counts; their offset is 9 sum_{G' < G} nnb(G'), a combination of 1-D prefix
+// sums; and the rank of G' among the neighbours of G (x fastest) follows from
+// the first 1-D neighbour of each coordinate of G.
+//
+// Work items (tile, record chunk) are split into eight contiguous ranges,
+// one per XCD, so that the records of a tile and of its neighbours (whose rows
+// share cache lines) are handled by one L2.
 #include "device_common.h"
 
 namespace igamt {
 
+constexpr int kScatterThreads = kScatterChunk;
+
+constexpr int kMaxTileN = 16;   // tile control points per direction the LDS slices hold
+
 struct ScatterArgs {
-  const Pair1D *p[3];
-  const int32_t *off[3];
-  const int64_t *pre[3];
-  int NG[3];
-  int tiles[3];
-  int nT[3];
-  int pT[3];
-  int S[3];
-  const int32_t *lut;        // pair index of (A, B), A <= B
-  const int32_t *slot;       // staging slot of (A, B) in A's x-line
-  const int32_t *line_up;
-  const int32_t *lo_off;
-  const int32_t *lo_p;
-  int64_t M, n_tiles, per_xcd;
-  int n_lines;               // x-lines per tile (n_y n_z)
-  int max_records;           // LDS staging capacity (records)
-  int max_x_entries;         // LDS capacity for the owned x-range's 1-D entries
-  const void *blocks;
-  void *values;
+  const int32_t *desc;       // [M][kDescWords] pair descriptors
+  const int64_t *pre[3];     // [NG + 1] prefix sums of 1-D neighbour counts
+  const int32_t *lo[3];      // [NG] first 1-D neighbour
+  const int32_t *mirror_perm;  // per chunk: record order for the transposed blocks
+  int nT[3], tiles[3];
+  int chunks;                // record chunks per tile
+  int64_t M, n_tiles, per_xcd, SX, SY;
+  const void *blocks;        // [n_tiles][M][9]
+  void *values;              // [nnz]
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void scatter_kernel(ScatterArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
+__global__ __launch_bounds__(kScatterThreads) void scatter_kernel(ScatterArgs a) {
+  constexpr int NT = kScatterThreads;
+  __shared__ T vals[NT * 9];          // the chunk's records, then the owners' sums
+  __shared__ int64_t row0[NT][2];     // first value of the block in row 0 of G_A / of G_B (-1: none)
+  __shared__ int32_t nnb[NT][2];      // neighbour counts of G_A / G_B
+  __shared__ int64_t sp[3][kMaxTileN];  // the tile's slice of the 1-D tables: prefix sums,
+  __shared__ int32_t sc[3][kMaxTileN];  // neighbour counts and first neighbours
+  __shared__ int32_t sl[3][kMaxTileN];
   const int64_t w = blockIdx.x;
-  const int64_t tile = (w & 7) * a.per_xcd + (w >> 3);
+  const int64_t item = (w & 7) * a.per_xcd + (w >> 3);
+  const int64_t tile = item / a.chunks;
   if (tile >= a.n_tiles) return;
-  const int tt[3] = {(int)(tile % a.tiles[0]), (int)((tile / a.tiles[0]) % a.tiles[1]),
-                     (int)(tile / ((int64_t)a.tiles[0] * a.tiles[1]))};
-  int cnt[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) cnt[k] = a.nT[k] - 1 + (tt[k] == a.tiles[k] - 1 ? 1 : 0);
-  const int64_t S3 = (int64_t)a.S[0] * a.S[1] * a.S[2];
-
-  T *stage = (T *)smem;                                                       // [max_records][9]
-  int32_t *SL = (int32_t *)(smem + (size_t)a.max_records * 9 * sizeof(T));   // [n_x][S3] slot rows of the line
-  Pair1D *EX = (Pair1D *)(SL + a.nT[0] * S3);                                 // owned x-range entries
-  Pair1D *EY = EX + a.max_x_entries;                                          // entries of gy
-  Pair1D *EZ = EY + 2 * a.pT[1] + 1;                                          // entries of gz
-  int32_t *OX = (int32_t *)(EZ + 2 * a.pT[2] + 1);                            // [cnt_x + 1] local offsets
-  int64_t *RB = (int64_t *)(((uintptr_t)(OX + a.nT[0] + 1) + 7) & ~(uintptr_t)7);   // [cnt_x] row bases
-  int32_t *PF = (int32_t *)(RB + a.nT[0]);                                    // [cnt_x + 1] prefix of nnb
-
+  const int chunk = (int)(item - tile * a.chunks);
+  const int64_t p0 = (int64_t)chunk * NT;
+  const int nrec = (int)min((int64_t)NT, a.M - p0);
   const int tid = threadIdx.x;
   const T *blk = (const T *)a.blocks;
-  T *out = (T *)a.values;
-  const int gx0 = tt[0] * (a.nT[0] - 1);
-  const int ex0 = a.off[0][gx0], nex = a.off[0][gx0 + cnt[0]] - ex0;
-  for (int i = tid; i < nex; i += 256) EX[i] = a.p[0][ex0 + i];
-  for (int o = tid; o <= cnt[0]; o += 256) OX[o] = a.off[0][gx0 + o] - ex0;
-  const int64_t SX = a.pre[0][a.NG[0]], SY = a.pre[1][a.NG[1]];
+  const int tt[3] = {(int)(tile % a.tiles[0]), (int)((tile / a.tiles[0]) % a.tiles[1]),
+                     (int)(tile / ((int64_t)a.tiles[0] * a.tiles[1]))};
 
-  for (int lz = 0; lz < cnt[2]; ++lz)
-    for (int ly = 0; ly < cnt[1]; ++ly) {
-      const int line = ly + a.nT[1] * lz;
-      const int up_lo = a.line_up[2 * line], n_up = a.line_up[2 * line + 1] - up_lo;
-      const int lo0 = a.lo_off[line], n_lo = a.lo_off[line + 1] - lo0;
-      const int gy = tt[1] * (a.nT[1] - 1) + ly, gz = tt[2] * (a.nT[2] - 1) + lz;
-      const int ey0 = a.off[1][gy], cy = a.off[1][gy + 1] - ey0;
-      const int ez0 = a.off[2][gz], cz = a.off[2][gz + 1] - ez0;
-      __syncthreads();   // previous line done with the staging buffers
-      {  // stage the line's records, slot rows and 1-D entries; loads are issued in batches
-         // of 8 per thread before any LDS store so that many requests are in flight
-        const T *src = blk + ((int64_t)tile * a.M + up_lo) * 9;
-        const int nu = n_up * 9;
-        for (int b0 = 0; b0 < nu; b0 += 256 * 8) {
-          T r[8];
+  // 1. independent loads, all issued before the first wait: the pair descriptor, the tile's
+  //    slices of the 1-D tables, and the chunk's records (contiguous, coalesced)
+  const int4 *dp = (const int4 *)(a.desc + kDescWords * (p0 + min(tid, nrec - 1)));
+  const int4 d0 = dp[0], d1 = dp[1];
+  // (loads are unconditional, with clamped indices, so that none waits for another)
+  // (no run-time index into the argument block: that would be a dependent load)
+  const int sd = min(tid / kMaxTileN, 2);
+  const int n_d = sd == 0 ? a.nT[0] : sd == 1 ? a.nT[1] : a.nT[2];
+  const int t_d = sd == 0 ? tt[0] : sd == 1 ? tt[1] : tt[2];
+  const int si = min(tid - sd * kMaxTileN, n_d - 1);
+  const bool slicer = tid < 3 * kMaxTileN && tid - sd * kMaxTileN < n_d;
+  const int64_t *pre_d = sd == 0 ? a.pre[0] : sd == 1 ? a.pre[1] : a.pre[2];
+  const int32_t *lo_d = sd == 0 ? a.lo[0] : sd == 1 ? a.lo[1] : a.lo[2];
+  const int g = t_d * (n_d - 1) + si;
+  const int64_t s_pre = pre_d[g], s_pre1 = pre_d[g + 1];
+  const int32_t s_lo = lo_d[g];
+  {
+    const T *src = blk + (tile * a.M + p0) * 9;
+    const int last = nrec * 9 - 1;
+    T r[9];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = b0 + u * 256 + tid;
-            r[u] = e < nu ? src[e] : (T)0;
-          }
+    for (int k = 0; k < 9; ++k) r[k] = src[min(k * NT + tid, last)];
+    __builtin_amdgcn_sched_barrier(0);   // keep every load above ahead of the first wait
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = b0 + u * 256 + tid;
-            if (e < nu) stage[e] = r[u];
-          }
-        }
-        const int nl = n_lo * 9;
-        const T *tb = blk + (int64_t)tile * a.M * 9;
-        for (int b0 = 0; b0 < nl; b0 += 256 * 8) {
-          int32_t q[8];
+    for (int k = 0; k < 9; ++k) vals[k * NT + tid] = r[k];
+  }
+  if (slicer) {
+    sp[sd][si] = s_pre;
+    sc[sd][si] = (int32_t)(s_pre1 - s_pre);
+    sl[sd][si] = s_lo;
+  }
+
+  // 2. one thread per record: ownership, and the first record of a higher tile sharing the
+  //    global pair is requested before the barrier
+  const int flags = (d0.x >> 24) & 127;
+  const int ai[3] = {d0.x & 255, (d0.x >> 8) & 255, (d0.x >> 16) & 255};
+  const int bi[3] = {d0.y & 255, (d0.y >> 8) & 255, (d0.y >> 16) & 255};
+  bool owner = tid < nrec;
+  int up = 0;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = b0 + u * 256 + tid;
-            q[u] = e < nl ? a.lo_p[lo0 + e / 9] : 0;
-          }
-          T r[8];
+  for (int d = 0; d < 3; ++d) {
+    if ((flags >> d) & 1 && tt[d] > 0) owner = false;                          // a lower tile owns it
+    if ((flags >> (3 + d)) & 1 && tt[d] < a.tiles[d] - 1) up |= 1 << d;       // higher tiles share it
+  }
+  if (!owner) up = 0;
+  const int sh[8] = {-1, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w, -1};
+  const int d7 = up == 7 ? a.desc[kDescWords * (p0 + tid) + 8] : -1;
+  T nb[9];
+  const int first = up & -up;                     // lowest shift: 1, 2 or 4
+  if (up) {
+    const int64_t t2 = tile + (first & 1) + (int64_t)a.tiles[0] * (((first >> 1) & 1) + (int64_t)a.tiles[1] * (first >> 2));
+    const T *src = blk + (t2 * a.M + sh[first]) * 9;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = b0 + u * 256 + tid;
-            r[u] = e < nl ? tb[(int64_t)q[u] * 9 + (e - 9 * (e / 9))] : (T)0;
-          }
+    for (int k = 0; k < 9; ++k) nb[k] = src[k];
+  }
+  __syncthreads();
+
+  if (owner) {
+    if (up) {
+      T v[9];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = b0 + u * 256 + tid;
-            if (e < nl) stage[(n_up + e / 9) * 9 + (e - 9 * (e / 9))] = r[u];
-          }
-        }
-        const int32_t *sl = a.slot + (int64_t)line * a.nT[0] * S3;
-        const int ns = a.nT[0] * (int)S3;
-        for (int b0 = 0; b0 < ns; b0 += 256 * 4) {
-          int32_t r[4];
+      for (int k = 0; k < 9; ++k) v[k] = vals[tid * 9 + k] + nb[k];
+      // further sharing tiles (edges and corners of the tile grid's faces) in ascending tile
+      // index = ascending delta = dx + 2 dy + 4 dz
+      for (int delta = first + 1; delta < 8; ++delta) {
+        if (delta & ~up) continue;
+        const int dx = delta & 1, dy = (delta >> 1) & 1, dz = delta >> 2;
+        const int64_t t2 = tile + dx + (int64_t)a.tiles[0] * (dy + (int64_t)a.tiles[1] * dz);
+        const T *src = blk + (t2 * a.M + (delta == 7 ? d7 : sh[delta])) * 9;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e = b0 + u * 256 + tid;
-            r[u] = e < ns ? sl[e] : 0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e = b0 + u * 256 + tid;
-            if (e < ns) SL[e] = r[u];
-          }
-        }
-        if (tid < cy) EY[tid] = a.p[1][ey0 + tid];
-        if (tid >= 64 && tid - 64 < cz) EZ[tid - 64] = a.p[2][ez0 + tid - 64];
-        if (tid >= 128 && tid - 128 < cnt[0]) {
-          const int o = tid - 128;
-          const int gx = gx0 + o;
-          const int64_t cx = a.pre[0][gx + 1] - a.pre[0][gx];
-          RB[o] = 9 * (a.pre[2][gz] * SY * SX + (int64_t)cz * (a.pre[1][gy] * SX + (int64_t)cy * a.pre[0][gx]));
-          PF[o + 1] = (int32_t)(cx * cy * cz);
-        }
+        for (int k = 0; k < 9; ++k) v[k] += src[k];
       }
-      __syncthreads();
-      if (tid == 0) {
-        PF[0] = 0;
-        for (int o = 0; o < cnt[0]; ++o) PF[o + 1] += PF[o];
-      }
-      __syncthreads();
-      const int W = PF[cnt[0]];
-      for (int i = tid; i < W; i += 256) {
-        int o = 0;
-        while (PF[o + 1] <= i) ++o;
-        const int rank = i - PF[o];
-        const int cx = OX[o + 1] - OX[o];
-        const int nnb = PF[o + 1] - PF[o];
-        const int kx = rank % cx, r2 = rank / cx;
-        const int ky = r2 % cy, kz = r2 / cy;
-        const Pair1D &X = EX[OX[o] + kx], &Y = EY[ky], &Z = EZ[kz];
-        T v[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = (T)0;
-        for (int iz = 0; iz < Z.ntile; ++iz)
-          for (int iy = 0; iy < Y.ntile; ++iy)
-            for (int ix = 0; ix < X.ntile; ++ix) {
-              const int64_t t = X.tile[ix] + (int64_t)a.tiles[0] * (Y.tile[iy] + (int64_t)a.tiles[1] * Z.tile[iz]);
-              const int A = X.li[ix] + a.nT[0] * (Y.li[iy] + a.nT[1] * Z.li[iz]);
-              const int B = X.lj[ix] + a.nT[0] * (Y.lj[iy] + a.nT[1] * Z.lj[iz]);
-              const int dAB = ((Z.lj[iz] - Z.li[iz] + a.pT[2]) * a.S[1] + (Y.lj[iy] - Y.li[iy] + a.pT[1])) * a.S[0] +
-                              (X.lj[ix] - X.li[ix] + a.pT[0]);
-              const T *src;
-              if (t == tile) {
-                src = stage + (int64_t)SL[X.li[ix] * S3 + dAB] * 9;   // own tile: A lies in this x-line
-              } else if (A <= B) {
-                src = blk + (t * a.M + a.lut[A * S3 + dAB]) * 9;
-              } else {
-                const int dBA = ((Z.li[iz] - Z.lj[iz] + a.pT[2]) * a.S[1] + (Y.li[iy] - Y.lj[iy] + a.pT[1])) * a.S[0] +
-                                (X.li[ix] - X.lj[ix] + a.pT[0]);
-                src = blk + (t * a.M + a.lut[B * S3 + dBA]) * 9;
-              }
-              if (A <= B) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) v[k] += src[k];
-              } else {
-#pragma unroll
-                for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-                  for (int bb = 0; bb < 3; ++bb) v[3 * aa + bb] += src[3 * bb + aa];
-              }
-            }
-        T *dst = out + RB[o] + 3 * rank;
-#pragma unroll
-        for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-          for (int bb = 0; bb < 3; ++bb) dst[3 * aa * nnb + bb] = v[3 * aa + bb];
-      }
+      for (int k = 0; k < 9; ++k) vals[tid * 9 + k] = v[k];
     }
-}
+    {
+      const int64_t base = 9 * (sp[2][ai[2]] * a.SY * a.SX + sc[2][ai[2]] * (sp[1][ai[1]] * a.SX +
+                                (int64_t)sc[1][ai[1]] * sp[0][ai[0]]));
+      const int64_t rank = ((int64_t)(bi[2] + tt[2] * (a.nT[2] - 1) - sl[2][ai[2]]) * sc[1][ai[1]] +
+                            (bi[1] + tt[1] * (a.nT[1] - 1) - sl[1][ai[1]])) * sc[0][ai[0]] +
+                           (bi[0] + tt[0] * (a.nT[0] - 1) - sl[0][ai[0]]);
+      row0[tid][0] = base + 3 * rank;
+      nnb[tid][0] = sc[0][ai[0]] * sc[1][ai[1]] * sc[2][ai[2]];
+    }
+    if (!(flags & 64)) {
+      const int64_t base = 9 * (sp[2][bi[2]] * a.SY * a.SX + sc[2][bi[2]] * (sp[1][bi[1]] * a.SX +
+                                (int64_t)sc[1][bi[1]] * sp[0][bi[0]]));
+      const int64_t rank = ((int64_t)(ai[2] + tt[2] * (a.nT[2] - 1) - sl[2][bi[2]]) * sc[1][bi[1]] +
+                            (ai[1] + tt[1] * (a.nT[1] - 1) - sl[1][bi[1]])) * sc[0][bi[0]] +
+                           (ai[0] + tt[0] * (a.nT[0] - 1) - sl[0][bi[0]]);
+      row0[tid][1] = base + 3 * rank;
+      nnb[tid][1] = sc[0][bi[0]] * sc[1][bi[1]] * sc[2][bi[2]];
+    } else {
+      row0[tid][1] = -1;
+    }
+  } else if (tid < nrec) {
+    row0[tid][0] = row0[tid][1] = -1;
+  }
+  __syncthreads();
 
-static size_t scatter_lds(const igamt_plan *P, size_t elem, int max_x_entries) {
-  size_t b = (size_t)P->max_line_records * 9 * elem;
-  b += (size_t)P->nT[0] * P->S[0] * P->S[1] * P->S[2] * 4;
-  b += (size_t)(max_x_entries + 2 * P->pT[1] + 1 + 2 * P->pT[2] + 1) * sizeof(Pair1D);
-  b += (size_t)(P->nT[0] + 1) * 4 + 8;
-  b += (size_t)P->nT[0] * 8 + (size_t)(P->nT[0] + 1) * 4;
-  return b + 64;
+  // 3. stores, lane q -> (row r, piece i, word c) with c fastest, so that consecutive lanes write
+  //    consecutive words wherever consecutive pieces are adjacent in the row:
+  //    blocks at (G_A, G_B) in record order (for one A, consecutive B are adjacent in row G_A),
+  //    transposed blocks at (G_B, G_A) in (B, A) order (for one B, consecutive A are adjacent).
+  T *out = (T *)a.values;
+  const int32_t *perm = a.mirror_perm + p0;
+#pragma unroll
+  for (int it = 0; it < 9; ++it) {
+    const int q = it * NT + tid;
+    const int r = q / (3 * NT), i = (q - r * 3 * NT) / 3, c = q % 3;
+    if (i < nrec && row0[i][0] >= 0) out[row0[i][0] + 3 * r * (int64_t)nnb[i][0] + c] = vals[i * 9 + 3 * r + c];
+  }
+#pragma unroll
+  for (int it = 0; it < 9; ++it) {
+    const int q = it * NT + tid;
+    const int r = q / (3 * NT), i = (q - r * 3 * NT) / 3, c = q % 3;
+    if (i < nrec) {
+      const int j = perm[i];
+      if (row0[j][1] >= 0) out[row0[j][1] + 3 * r * (int64_t)nnb[j][1] + c] = vals[j * 9 + 3 * c + r];
+    }
+  }
 }
 
 igamt_status launch_scatter(igamt_plan *P, igamt_precision prec, const void *d_blocks, void *d_values, void *stream) {
   ScatterArgs a;
-  int max_x_entries = 0;
   for (int k = 0; k < 3; ++k) {
-    a.p[k] = P->dev.dir_pairs[k];
-    a.off[k] = P->dev.dir_off[k];
-    a.pre[k] = P->dev.dir_pre[k];
-    a.NG[k] = P->dir[k].NG;
-    a.tiles[k] = P->tiles[k];
-    a.nT[k] = P->nT[k];
-    a.pT[k] = P->pT[k];
-    a.S[k] = P->S[k];
-  }
-  {
-    const int n = P->nT[0];
-    for (int t = 0; t < P->tiles[0]; ++t) {
-      const int g0 = t * (n - 1), c = n - 1 + (t == P->tiles[0] - 1 ? 1 : 0);
-      max_x_entries = std::max(max_x_entries, P->dir[0].off[g0 + c] - P->dir[0].off[g0]);
+    if (P->nT[k] > kMaxTileN || P->nT[k] > 255) {
+      set_error("tile too large for the scatter kernel");
+      return IGAMT_EUNSUPPORTED;
     }
+    a.pre[k] = P->dev.dir_pre[k];
+    a.lo[k] = P->dev.dir_lo[k];
+    a.nT[k] = P->nT[k];
+    a.tiles[k] = P->tiles[k];
   }
-  a.lut = P->dev.pair_lut;
-  a.slot = P->dev.slot_lut;
-  a.line_up = P->dev.line_up;
-  a.lo_off = P->dev.line_lo_off;
-  a.lo_p = P->dev.line_lo_p;
+  a.desc = P->dev.pair_desc;
+  a.mirror_perm = P->dev.mirror_perm;
   a.M = P->n_pairs;
   a.n_tiles = P->n_tiles;
-  a.n_lines = P->nT[1] * P->nT[2];
-  a.per_xcd = (P->n_tiles + 7) / 8;
-  a.max_records = P->max_line_records;
-  a.max_x_entries = max_x_entries;
+  a.chunks = (int)((P->n_pairs + kScatterThreads - 1) / kScatterThreads);
+  const int64_t items = a.n_tiles * a.chunks;
+  a.per_xcd = (items + 7) / 8;
+  a.SX = P->dir[0].pre[P->dir[0].NG];
+  a.SY = P->dir[1].pre[P->dir[1].NG];
   a.blocks = d_blocks;
   a.values = d_values;
-  const size_t elem = prec == IGAMT_F64 ? 8 : 4;
-  const size_t shm = scatter_lds(P, elem, max_x_entries);
-  if (shm > 160 * 1024 || P->nT[0] > 128) {
-    set_error("tile too large for the scatter kernel's LDS staging");
-    return IGAMT_EUNSUPPORTED;
-  }
-  const dim3 grid((unsigned)(8 * a.per_xcd)), block(256);
+  if (8 * a.per_xcd > INT32_MAX) { set_error("too many scatter work items"); return IGAMT_EUNSUPPORTED; }
+  const dim3 grid((unsigned)(8 * a.per_xcd)), block(kScatterThreads);
   hipStream_t s = (hipStream_t)stream;
-  if (prec == IGAMT_F64) {
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)scatter_kernel<double>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL(scatter_kernel<double>, grid, block, shm, s, a);
-  } else {
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)scatter_kernel<float>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL(scatter_kernel<float>, grid, block, shm, s, a);
-  }
+  if (prec == IGAMT_F64)
+    hipLaunchKernelGGL(scatter_kernel<double>, grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL(scatter_kernel<float>, grid, block, 0, s, a);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
