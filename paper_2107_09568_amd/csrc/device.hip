@@ -54,10 +54,6 @@ igamt_status ensure_device(igamt_plan *P) {
   UP(d.gauss_w, P->gauss_w);
   UP(d.pairs, P->pairs);
   UP(d.pair_lut, P->pair_lut);
-  UP(d.line_up, P->line_up);
-  UP(d.line_lo_off, P->line_lo_off);
-  UP(d.line_lo_p, P->line_lo_p);
-  UP(d.slot_lut, P->slot_lut);
   UP(d.mirror_perm, P->mirror_perm);
   UP(d.pair_desc, P->pair_desc);
   IGAMT_HIP(hipMalloc((void **)&d.flag, 4 * sizeof(int32_t)));
@@ -85,8 +81,7 @@ void free_device(igamt_plan *P) {
   (void)hipDeviceSynchronize();
   void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
-                  d.table_h_scale, d.point_data, d.line_up, d.line_lo_off, d.line_lo_p, d.slot_lut,
-                  d.mirror_perm, d.pair_desc};
+                  d.table_h_scale, d.point_data, d.mirror_perm, d.pair_desc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 3; ++k) {

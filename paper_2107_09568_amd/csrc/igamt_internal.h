@@ -67,10 +67,6 @@ struct DevicePtrs {
   int32_t *ctrl_tiles_off[3] = {nullptr, nullptr, nullptr};  // per macro ctrl index: tiles touching it
   int32_t *ctrl_tiles[3] = {nullptr, nullptr, nullptr};      // (tile, local offset) pairs
   int32_t *flag = nullptr;           // smallest degenerate tile index (INT32_MAX = none)
-  int32_t *line_up = nullptr;        // [n_lines][2] pair range whose A lies in the x-line
-  int32_t *line_lo_off = nullptr;    // [n_lines + 1] offsets into line_lo_p
-  int32_t *line_lo_p = nullptr;      // pairs (B, A) with A in the x-line and B < A
-  int32_t *slot_lut = nullptr;       // [n_T][S_z][S_y][S_x] -> staging slot of (A, B) in A's x-line
   // tables
   double *table = nullptr;           // [Mp][Kp] FP64, zero padded
   double *table_t = nullptr;         // [Kp][Mp] FP64 (transposed, for the adjoint)
@@ -104,9 +100,6 @@ struct igamt_plan {
   std::vector<double> box_a[3], box_h[3];
   std::vector<int32_t> pairs;         // [n_pairs][2]
   std::vector<int32_t> pair_lut;      // [nTt][S2][S1][S0]
-  // per tile-local x-line (y + n_y z) of A: upper pair range, lower pair list, staging slots
-  std::vector<int32_t> line_up, line_lo_off, line_lo_p, slot_lut;
-  int max_line_records = 0;
   // scatter descriptors, kDescWords per pair: w0 = a_x | a_y << 8 | a_z << 16 | flags << 24
   // (bits 0-2: a_d = b_d = 0, bits 3-5: a_d = b_d = n_d - 1, bit 6: A = B),
   // w1 = b_x | b_y << 8 | b_z << 16, w[1 + delta] = index of the same pair in the tile shifted by

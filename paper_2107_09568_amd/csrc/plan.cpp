@@ -258,49 +258,6 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
   }
   P->n_pairs = (int64_t)P->pairs.size() / 2;
   P->Mp = (P->n_pairs + kRowPad - 1) / kRowPad * kRowPad;
-  // x-line staging structure: for the x-line of A (flat A = x + n_x L), the pairs (A, B) with
-  // A in the line form one contiguous range (pairs are sorted by A); the pairs (B, A) with B < A
-  // are listed; each (A, offset) gets the slot of its record in the line's staging order.
-  {
-    const int n_lines = P->nT[1] * P->nT[2];
-    P->line_up.assign(2 * n_lines, 0);
-    P->line_lo_off.assign(n_lines + 1, 0);
-    P->line_lo_p.clear();
-    P->slot_lut.assign(P->nTt * lut_stride, -1);
-    std::vector<std::vector<int32_t>> lower(n_lines);
-    for (int64_t p = 0; p < P->n_pairs; ++p) {
-      const int A = P->pairs[2 * p], B = P->pairs[2 * p + 1];
-      if (A != B) lower[B / P->nT[0]].push_back((int32_t)p);
-    }
-    int64_t p = 0;
-    for (int L = 0; L < n_lines; ++L) {
-      while (p < P->n_pairs && P->pairs[2 * p] < (int64_t)P->nT[0] * L) ++p;
-      const int64_t lo = p;
-      while (p < P->n_pairs && P->pairs[2 * p] < (int64_t)P->nT[0] * (L + 1)) ++p;
-      P->line_up[2 * L] = (int32_t)lo;
-      P->line_up[2 * L + 1] = (int32_t)p;
-      P->line_lo_off[L] = (int32_t)P->line_lo_p.size();
-      for (int32_t q : lower[L]) P->line_lo_p.push_back(q);
-      const int n_up = (int)(p - lo), n_lo = (int)lower[L].size();
-      P->max_line_records = std::max(P->max_line_records, n_up + n_lo);
-      for (int64_t q = lo; q < p; ++q) {
-        const int A = P->pairs[2 * q], B = P->pairs[2 * q + 1];
-        const int dx = B % P->nT[0] - A % P->nT[0] + P->pT[0];
-        const int dy = (B / P->nT[0]) % P->nT[1] - (A / P->nT[0]) % P->nT[1] + P->pT[1];
-        const int dz = B / (P->nT[0] * P->nT[1]) - A / (P->nT[0] * P->nT[1]) + P->pT[2];
-        P->slot_lut[A * lut_stride + ((int64_t)dz * P->S[1] + dy) * P->S[0] + dx] = (int32_t)(q - lo);
-      }
-      for (int r = 0; r < n_lo; ++r) {   // record (B, A) seen from A (the second index) with offset B - A
-        const int64_t q = lower[L][r];
-        const int Bq = P->pairs[2 * q], Aq = P->pairs[2 * q + 1];
-        const int dx = Bq % P->nT[0] - Aq % P->nT[0] + P->pT[0];
-        const int dy = (Bq / P->nT[0]) % P->nT[1] - (Aq / P->nT[0]) % P->nT[1] + P->pT[1];
-        const int dz = Bq / (P->nT[0] * P->nT[1]) - Aq / (P->nT[0] * P->nT[1]) + P->pT[2];
-        P->slot_lut[Aq * lut_stride + ((int64_t)dz * P->S[1] + dy) * P->S[0] + dx] = (int32_t)(n_up + r);
-      }
-    }
-    P->line_lo_off[n_lines] = (int32_t)P->line_lo_p.size();
-  }
   // scatter descriptors (see igamt_internal.h)
   {
     const int nx = P->nT[0], ny = P->nT[1];
