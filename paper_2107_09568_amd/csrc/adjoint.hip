@@ -11,98 +11,57 @@
 //   (Fbar, Dbar) from Abar                   (adjoint of A = D G(F))
 //   Jbar = -F^T Fbar F^T + Dbar D F^T        (F = J^-1, D = det J)
 //   mbar_i += sum_n Jbar[c][n] h_n d_n N_i   (J = J_M(a + h xi) diag(h))
-// Kernels: (1) the fit (FP64); (2) the transposed contraction on MFMA, U formed
-// on the fly from the gathered displacement; (3) the FP64 fit adjoint, one
-// workgroup per tile, giving per-tile gradients of the macro control points the
-// tile touches and the tile's share of u^T K u; (4) deterministic reductions
-// over tiles in ascending order.
+// Kernels: (1) the fit (FP64); (2) U from the gathered displacement, then the
+// transposed contraction W = table^T U on the forward MFMA kernel (W stored
+// [t][k][ab]); (3) the FP64 fit adjoint, one workgroup per tile, giving per-tile
+// gradients of the macro control points the tile touches and the tile's share of
+// u^T K u; (4) reductions over the tiles in a fixed order (bitwise reproducible).
 #include "device_common.h"
 
 namespace igamt {
 
-// ---- (2) W = table^T U on MFMA ---------------------------------------------
-struct AdjContractArgs {
-  const void *At;         // table transposed [Kp][Mp] (double or float)
-  const int32_t *pairs;   // [M][2]
+// ---- (2) U, then W = table^T U on MFMA ------------------------------------------
+// U is formed once per tile, stored like the coefficients of the forward product (one
+// column per (tile, ab), contiguous over the pairs p), so that W = table^T U runs on the
+// forward contraction kernel with the transposed table as its row operand.
+struct UFormArgs {
+  const int32_t *desc;    // [M][kDescWords] pair descriptors (local coordinates of A and B)
   const double *u;        // global displacement [3 n_global]
-  void *W;                // [n_tiles_pad][9][Kp] (double or float)
-  int64_t M, Mp, Kp, n_tiles;
+  void *U;                // [n_tiles_pad][9][Mp] (double or float)
+  int64_t M, Mp, n_tiles, n_tiles_pad;
   int tiles[3], nT[3], NG[3];
-  int n_kblk;
 };
 
-template <bool F64>
-__global__ __launch_bounds__(256) void adjoint_contract_kernel(AdjContractArgs a) {
-  using E = typename std::conditional<F64, double, float>::type;
-  using Acc = typename std::conditional<F64, d4, f4>::type;
-  constexpr int PC = F64 ? 32 : 64;              // pairs per LDS chunk (256 B per column)
-  constexpr int ROW = PC * sizeof(E) + 16;       // padded LDS row bytes
-  __shared__ __attribute__((aligned(16))) char lds[144 * ROW];
-  const int kb = blockIdx.x % a.n_kblk;
-  const int64_t grp = blockIdx.x / a.n_kblk;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
-  const int64_t k0w = (int64_t)kb * 64 + wave * 16;
-
-  Acc acc[9];
+template <typename E>
+__global__ __launch_bounds__(256) void u_form_kernel(UFormArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = blockIdx.y;
+  if (p >= a.Mp || t >= a.n_tiles_pad) return;
+  double v[9];
 #pragma unroll
-  for (int ni = 0; ni < 9; ++ni) acc[ni] = Acc{0, 0, 0, 0};
-
-  for (int64_t p0 = 0; p0 < a.Mp; p0 += PC) {
-    __syncthreads();
-    for (int e = tid; e < 144 * PC; e += 256) {
-      const int n = e / PC, pp = e - n * PC;
-      const int64_t p = p0 + pp;
-      const int tl = n / 9, ab = n - 9 * tl;
-      const int64_t t = grp * 16 + tl;
-      double v = 0.0;
-      if (p < a.M && t < a.n_tiles) {
-        const int A = a.pairs[2 * p], B = a.pairs[2 * p + 1];
-        const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
-                           (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
-        const int ai[3] = {A % a.nT[0], (A / a.nT[0]) % a.nT[1], A / (a.nT[0] * a.nT[1])};
-        const int bi[3] = {B % a.nT[0], (B / a.nT[0]) % a.nT[1], B / (a.nT[0] * a.nT[1])};
-        int64_t GA = 0, GB = 0;
-        for (int k = 2; k >= 0; --k) {
-          GA = GA * a.NG[k] + tt[k] * (a.nT[k] - 1) + ai[k];
-          GB = GB * a.NG[k] + tt[k] * (a.nT[k] - 1) + bi[k];
-        }
-        const int aa = ab / 3, bb = ab - 3 * aa;
-        v = (A < B ? 2.0 : 1.0) * a.u[3 * GA + aa] * a.u[3 * GB + bb];
-      }
-      *(E *)(lds + n * ROW + pp * sizeof(E)) = (E)v;
+  for (int k = 0; k < 9; ++k) v[k] = 0.0;
+  if (p < a.M && t < a.n_tiles) {
+    const int32_t w0 = a.desc[kDescWords * p], w1 = a.desc[kDescWords * p + 1];
+    const int ai[3] = {w0 & 255, (w0 >> 8) & 255, (w0 >> 16) & 255};
+    const int bi[3] = {w1 & 255, (w1 >> 8) & 255, (w1 >> 16) & 255};
+    const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
+                       (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
+    int64_t GA = 0, GB = 0;
+    for (int k = 2; k >= 0; --k) {
+      GA = GA * a.NG[k] + tt[k] * (a.nT[k] - 1) + ai[k];
+      GB = GB * a.NG[k] + tt[k] * (a.nT[k] - 1) + bi[k];
     }
-    __syncthreads();
+    const double m = GA == GB ? 1.0 : 2.0;   // A < B pairs stand for both orders
+    const double uA[3] = {a.u[3 * GA], a.u[3 * GA + 1], a.u[3 * GA + 2]};
+    const double uB[3] = {a.u[3 * GB], a.u[3 * GB + 1], a.u[3 * GB + 2]};
 #pragma unroll
-    for (int ks = 0; ks < PC; ks += 16) {
-      const E *src = (const E *)a.At + (k0w + l16) * a.Mp + p0 + ks + 4 * kq;
-      E av[4];
+    for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) av[s] = src[s];
-#pragma unroll
-      for (int ni = 0; ni < 9; ++ni) {
-        const E *bp = (const E *)(lds + (ni * 16 + l16) * ROW) + ks + 4 * kq;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          if constexpr (F64)
-            acc[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bp[s], acc[ni], 0, 0, 0);
-          else
-            acc[ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bp[s], acc[ni], 0, 0, 0);
-        }
-      }
-    }
+      for (int bb = 0; bb < 3; ++bb) v[3 * aa + bb] = m * uA[aa] * uB[bb];
   }
-  E *W = (E *)a.W;
+  E *U = (E *)a.U;
 #pragma unroll
-  for (int ni = 0; ni < 9; ++ni) {
-    const int n = ni * 16 + l16;
-    const int tl = n / 9, ab = n - 9 * tl;
-    const int64_t t = grp * 16 + tl;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t k = k0w + (F64 ? kq + 4 * r : 4 * kq + r);
-      W[(t * 9 + ab) * a.Kp + k] = (E)acc[ni][r];
-    }
-  }
+  for (int k = 0; k < 9; ++k) U[(t * 9 + k) * a.Mp + p] = (E)v[k];
 }
 
 // ---- (3) fit adjoint ---------------------------------------------------------------
@@ -121,14 +80,16 @@ struct FitAdjArgs {
   bool w_f64;
   double lam, mu;
   const double *coef;   // [n_tiles_pad][9][Kp] FP64
-  const void *W;        // same layout, double or float
+  const void *W;        // [n_tiles][Kp][9], double or float
   double *local_grad;   // [n_tiles][Lz][Ly][Lx][3]
   double *uKu_part;     // [n_tiles]
   int32_t *flag;
 };
 
+constexpr int kFitAdjThreads = 256;   // threads per tile in the fit adjoint
+
 template <int PM>
-__global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
+__global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs a) {
   extern __shared__ double smem[];
   const int nf = a.nf, q1 = a.q + 1;
   const int ns = nf * nf * nf, npi = q1 * q1 * q1;
@@ -139,17 +100,17 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
   __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
   __shared__ double NB[3][kMaxFit][kMaxDegree + 1], DB[3][kMaxFit][kMaxDegree + 1];
   __shared__ int SP[3][kMaxFit];
-  __shared__ double red[64];
+  __shared__ double red[kFitAdjThreads];
   const int tid = threadIdx.x;
   const int64_t t = blockIdx.x;
   const int64_t tbase = t * 9 * (int64_t)a.Kp;
-  for (int e = tid; e < q1 * nf; e += 64) Pm[e] = a.fP[e];
+  for (int e = tid; e < q1 * nf; e += kFitAdjThreads) Pm[e] = a.fP[e];
   const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
                      (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
   const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
   const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
   // 1-D macro basis at the tile's sample abscissae (tensor grid)
-  for (int e = tid; e < 3 * nf; e += 64) {
+  for (int e = tid; e < 3 * nf; e += kFitAdjThreads) {
     const int k = e / nf, s = e % nf;
     const double x = ax[k] + hx[k] * a.fx[s];
     const int sp = find_span(a.knots[k], a.nM[k], PM, x);
@@ -159,7 +120,7 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
     for (int r = 0; r <= PM; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
   }
   // F and D at the samples; zero the adjoint accumulators
-  for (int s = tid; s < ns; s += 64) {
+  for (int s = tid; s < ns; s += kFitAdjThreads) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PM + 1], dN[3][PM + 1];
@@ -180,14 +141,16 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
   // this tile's share of u^T K u (fixed-order block reduction)
   {
     double part = 0.0;
-    for (int64_t e = tid; e < 9 * (int64_t)a.Kp; e += 64) {
-      const double w = a.w_f64 ? ((const double *)a.W)[tbase + e] : (double)((const float *)a.W)[tbase + e];
+    for (int64_t e = tid; e < 9 * (int64_t)a.Kp; e += kFitAdjThreads) {
+      const int64_t ab = e / a.Kp, k = e - ab * a.Kp;
+      const int64_t wi = (t * a.Kp + k) * 9 + ab;   // W is stored [t][k][ab]
+      const double w = a.w_f64 ? ((const double *)a.W)[wi] : (double)((const float *)a.W)[wi];
       part += a.coef[tbase + e] * w;
     }
     red[tid] = part;
   }
   __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
+  for (int s = kFitAdjThreads / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
@@ -196,14 +159,14 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
   for (int ij = 0; ij < 9; ++ij) {
     const int i = ij / 3, j = ij % 3;
     // W block of (i, j): buf0[C][ab]
-    for (int e = tid; e < npi * 9; e += 64) {
+    for (int e = tid; e < npi * 9; e += kFitAdjThreads) {
       const int C = e / 9, ab = e % 9;
-      const int64_t idx = tbase + (int64_t)ab * a.Kp + 9 * C + ij;
+      const int64_t idx = (t * a.Kp + 9 * C + ij) * 9 + ab;   // W is stored [t][k][ab]
       buf0[e] = a.w_f64 ? ((const double *)a.W)[idx] : (double)((const float *)a.W)[idx];
     }
     __syncthreads();
     // transpose of the z pass: buf1[(s3, c2, c1)][ab] = sum_c3 P[c3][s3] W[(c3, c2, c1)]
-    for (int e = tid; e < nf * q1 * q1 * 9; e += 64) {
+    for (int e = tid; e < nf * q1 * q1 * 9; e += kFitAdjThreads) {
       const int ab = e % 9, r = e / 9, c1 = r % q1, c2 = (r / q1) % q1, s3 = r / (q1 * q1);
       double v = 0.0;
       for (int c3 = 0; c3 < q1; ++c3) v += Pm[c3 * nf + s3] * buf0[((c3 * q1 + c2) * q1 + c1) * 9 + ab];
@@ -211,7 +174,7 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
     }
     __syncthreads();
     // transpose of the y pass: buf0[(s3, s2, c1)][ab]
-    for (int e = tid; e < nf * nf * q1 * 9; e += 64) {
+    for (int e = tid; e < nf * nf * q1 * 9; e += kFitAdjThreads) {
       const int ab = e % 9, r = e / 9, c1 = r % q1, s2 = (r / q1) % nf, s3 = r / (q1 * nf);
       double v = 0.0;
       for (int c2 = 0; c2 < q1; ++c2) v += Pm[c2 * nf + s2] * buf1[((s3 * q1 + c2) * q1 + c1) * 9 + ab];
@@ -219,7 +182,7 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
     }
     __syncthreads();
     // transpose of the x pass: buf1[(s3, s2, s1)][ab] = Abar_ij at sample s
-    for (int e = tid; e < ns * 9; e += 64) {
+    for (int e = tid; e < ns * 9; e += kFitAdjThreads) {
       const int ab = e % 9, s = e / 9, s1 = s % nf, s23 = s / nf;
       double v = 0.0;
       for (int c1 = 0; c1 < q1; ++c1) v += Pm[c1 * nf + s1] * buf0[(s23 * q1 + c1) * 9 + ab];
@@ -227,7 +190,7 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
     }
     __syncthreads();
     // accumulate the adjoint of A_ij = D G_ij(F) into (Fbar / D, Dbar), one sample per thread
-    for (int s = tid; s < ns; s += 64) {
+    for (int s = tid; s < ns; s += kFitAdjThreads) {
       const double *F = FD + s * 10;
       const double D = F[9];
       const double *Ab = buf1 + s * 9;     // Abar_ij[a][b]
@@ -260,7 +223,7 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
     __syncthreads();
   }
   // Jbar at each sample, scaled by h (stored over FB[s][0..8])
-  for (int s = tid; s < ns; s += 64) {
+  for (int s = tid; s < ns; s += kFitAdjThreads) {
     const double *F = FD + s * 10;
     double *fb = FB + s * 10;
     const double D = F[9];
@@ -284,7 +247,7 @@ __global__ __launch_bounds__(64) void fit_adjoint_kernel(FitAdjArgs a) {
   const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2];
   const int lo[3] = {a.ctrl_lo[0][tt[0]], a.ctrl_lo[1][tt[1]], a.ctrl_lo[2][tt[2]]};
   double *lg = a.local_grad + t * (int64_t)L0 * L1 * L2 * 3;
-  for (int e = tid; e < L0 * L1 * L2 * 3; e += 64) {
+  for (int e = tid; e < L0 * L1 * L2 * 3; e += kFitAdjThreads) {
     const int c = e % 3, li = e / 3;
     const int l[3] = {li % L0, (li / L0) % L1, li / (L0 * L1)};
     double g = 0.0;
@@ -315,22 +278,36 @@ struct GradReduceArgs {
   double *grad;
 };
 
+// One workgroup per macro control point: the (tile, local index) contributions are split
+// over the threads in a fixed strided order and combined by a fixed tree, so the gradient is
+// bitwise reproducible.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(GradReduceArgs a) {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)a.nM[0] * a.nM[1] * a.nM[2];
-  if (id >= 3 * n) return;
-  const int c = (int)(id % 3);
-  const int64_t m = id / 3;
+  __shared__ double red[3][256];
+  const int64_t m = blockIdx.x;
+  const int tid = threadIdx.x;
   const int ix = (int)(m % a.nM[0]), iy = (int)((m / a.nM[0]) % a.nM[1]), iz = (int)(m / ((int64_t)a.nM[0] * a.nM[1]));
-  double g = 0.0;
-  for (int ez = a.off[2][iz]; ez < a.off[2][iz + 1]; ++ez)
-    for (int ey = a.off[1][iy]; ey < a.off[1][iy + 1]; ++ey)
-      for (int ex = a.off[0][ix]; ex < a.off[0][ix + 1]; ++ex) {
-        const int64_t t = a.lst[0][2 * ex] + (int64_t)a.tiles[0] * (a.lst[1][2 * ey] + (int64_t)a.tiles[1] * a.lst[2][2 * ez]);
-        const int lx = a.lst[0][2 * ex + 1], ly = a.lst[1][2 * ey + 1], lz = a.lst[2][2 * ez + 1];
-        g += a.local_grad[(((t * a.Lc[2] + lz) * a.Lc[1] + ly) * a.Lc[0] + lx) * 3 + c];
-      }
-  a.grad[id] = g;
+  const int ex0 = a.off[0][ix], nx = a.off[0][ix + 1] - ex0;
+  const int ey0 = a.off[1][iy], ny = a.off[1][iy + 1] - ey0;
+  const int ez0 = a.off[2][iz], nz = a.off[2][iz + 1] - ez0;
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int f = tid; f < nx * ny * nz; f += 256) {
+    const int ex = ex0 + f % nx, ey = ey0 + (f / nx) % ny, ez = ez0 + f / (nx * ny);
+    const int64_t t = a.lst[0][2 * ex] + (int64_t)a.tiles[0] * (a.lst[1][2 * ey] + (int64_t)a.tiles[1] * a.lst[2][2 * ez]);
+    const int lx = a.lst[0][2 * ex + 1], ly = a.lst[1][2 * ey + 1], lz = a.lst[2][2 * ez + 1];
+    const double *src = a.local_grad + (((t * a.Lc[2] + lz) * a.Lc[1] + ly) * a.Lc[0] + lx) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] += src[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) red[c][tid] = g[c];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + s];
+    __syncthreads();
+  }
+  if (tid < 3) a.grad[3 * m + tid] = red[tid][0];
 }
 
 __global__ __launch_bounds__(256) void sum_kernel(const double *x, int64_t n, double *out) {
@@ -346,14 +323,16 @@ __global__ __launch_bounds__(256) void sum_kernel(const double *x, int64_t n, do
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-static int64_t grad_ws_layout(const igamt_plan *P, igamt_precision prec, int64_t off[5]) {
+static int64_t grad_ws_layout(const igamt_plan *P, igamt_precision prec, int64_t off[6]) {
   const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
+  const int64_t eb = prec == IGAMT_F64 ? 8 : 4;
   off[0] = 0;                                                        // coef (FP64)
-  off[1] = off[0] + align256(plane * 8);                             // W
-  off[2] = off[1] + align256(plane * (prec == IGAMT_F64 ? 8 : 4));   // local gradients
+  off[1] = off[0] + align256(plane * 8);                             // W [n_tiles][Kp][9]
+  off[2] = off[1] + align256(plane * eb);                            // local gradients
   off[3] = off[2] + align256(P->n_tiles * (int64_t)P->Lc[0] * P->Lc[1] * P->Lc[2] * 3 * 8);
   off[4] = off[3] + align256(P->n_tiles * 8);                        // uKu parts
-  return off[4];
+  off[5] = off[4] + align256(P->n_tiles_pad * 9 * P->Mp * eb);       // U [n_tiles_pad][9][Mp]
+  return off[5];
 }
 
 }  // namespace igamt
@@ -363,7 +342,7 @@ using namespace igamt;
 extern "C" igamt_status igamt_grad_workspace_bytes(const igamt_plan *P, igamt_precision prec, int64_t *bytes) {
   if (!P || !bytes) { set_error("NULL argument"); return IGAMT_EINVAL; }
   if (prec != IGAMT_F64 && prec != IGAMT_F32) { set_error("gradient contraction runs in F64 or F32"); return IGAMT_EUNSUPPORTED; }
-  int64_t off[5];
+  int64_t off[6];
   *bytes = grad_ws_layout(P, prec, off);
   return IGAMT_OK;
 }
@@ -380,37 +359,39 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
     return IGAMT_EUNSUPPORTED;
   }
   hipStream_t s = (hipStream_t)stream;
-  int64_t off[5];
+  int64_t off[6];
   grad_ws_layout(P, prec, off);
   char *ws = (char *)d_workspace;
   double *coef = (double *)(ws + off[0]);
   void *W = ws + off[1];
   double *lg = (double *)(ws + off[2]);
   double *part = (double *)(ws + off[3]);
+  void *U = ws + off[4];
   // (1) fit in FP64
   if ((st = launch_fit(P, E, nu, IGAMT_F64, coef, stream))) return st;
-  // (2) W = table^T U
-  AdjContractArgs c;
-  c.At = prec == IGAMT_F64 ? (const void *)P->dev.table_t : (const void *)P->dev.table_t_f32;
-  c.pairs = P->dev.pairs;
+  // (2) U, then W = table^T U
+  UFormArgs c;
+  c.desc = P->dev.pair_desc;
   c.u = d_u;
-  c.W = W;
+  c.U = U;
   c.M = P->n_pairs;
   c.Mp = P->Mp;
-  c.Kp = P->Kp;
   c.n_tiles = P->n_tiles;
+  c.n_tiles_pad = P->n_tiles_pad;
   for (int k = 0; k < 3; ++k) {
     c.tiles[k] = P->tiles[k];
     c.nT[k] = P->nT[k];
     c.NG[k] = P->dir[k].NG;
   }
-  c.n_kblk = P->Kp / 64;
-  const dim3 cgrid((unsigned)(c.n_kblk * P->n_groups)), block(256);
+  const dim3 ugrid((unsigned)((P->Mp + 255) / 256), (unsigned)P->n_tiles_pad);
   if (prec == IGAMT_F64)
-    hipLaunchKernelGGL(adjoint_contract_kernel<true>, cgrid, block, 0, s, c);
+    hipLaunchKernelGGL(u_form_kernel<double>, ugrid, dim3(256), 0, s, c);
   else
-    hipLaunchKernelGGL(adjoint_contract_kernel<false>, cgrid, block, 0, s, c);
+    hipLaunchKernelGGL(u_form_kernel<float>, ugrid, dim3(256), 0, s, c);
   IGAMT_LAUNCH_CHECK();
+  if ((st = launch_gemm_tiles(prec, prec == IGAMT_F64 ? (const void *)P->dev.table_t : (const void *)P->dev.table_t_f32,
+                              U, W, P->Kp, transposed_rows(P), P->Mp, P->n_tiles, P->n_groups, stream)))
+    return st;
   // (3) fit adjoint
   FitAdjArgs f;
   for (int k = 0; k < 3; ++k) {
@@ -439,7 +420,7 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   f.flag = P->dev.flag;
   const int ns = P->n_fit * P->n_fit * P->n_fit;
   const size_t shm = (size_t)(10 + 10 + 9 + 9) * std::max(ns, P->npi) * sizeof(double);
-  const dim3 fgrid((unsigned)P->n_tiles), fblock(64);
+  const dim3 fgrid((unsigned)P->n_tiles), fblock(kFitAdjThreads);
   switch (P->pM[0]) {
 #define FA_CASE(p)                                                                                      \
   case p:                                                                                               \
@@ -469,7 +450,7 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   g.local_grad = lg;
   g.grad = d_grad;
   const int64_t nm = 3LL * P->nM[0] * P->nM[1] * P->nM[2];
-  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)(nm / 3)), dim3(256), 0, s, g);
   IGAMT_LAUNCH_CHECK();
   if (d_uKu) {
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, part, P->n_tiles, d_uKu);

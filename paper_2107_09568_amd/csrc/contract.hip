@@ -419,6 +419,39 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
   return IGAMT_OK;
 }
 
+igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *B, void *out, int64_t rows,
+                               int64_t rows_pad, int64_t kdim, int64_t n_tiles, int64_t n_groups, void *stream) {
+  if (prec != IGAMT_F64 && prec != IGAMT_F32) { set_error("tile GEMM runs in F64 or F32"); return IGAMT_EUNSUPPORTED; }
+  const int bm = prec == IGAMT_F64 ? kBM<IGAMT_F64> : kBM<IGAMT_F32>;
+  const int kch = prec == IGAMT_F64 ? Mode<IGAMT_F64>::KCH : Mode<IGAMT_F32>::KCH;
+  if (rows_pad % bm != 0 || kdim % kch != 0 || rows > rows_pad) {
+    set_error("tile GEMM operands are not padded to the kernel's blocks");
+    return IGAMT_EINVAL;
+  }
+  ContractArgs a;
+  a.A = A;
+  a.A2 = nullptr;
+  a.Ascale = nullptr;
+  a.B = B;
+  a.B2 = nullptr;
+  a.Bscale = nullptr;
+  a.out = out;
+  a.M = rows;
+  a.Kp = kdim;
+  a.n_tiles = n_tiles;
+  a.n_mblk = (int)(rows_pad / bm);
+  a.n_groups = (int)n_groups;
+  const int64_t groups8 = (n_groups + 7) / 8 * 8;
+  const dim3 grid((unsigned)(a.n_mblk * groups8));
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == IGAMT_F64)
+    hipLaunchKernelGGL(contract_kernel<IGAMT_F64>, grid, dim3(64 * kWaves<IGAMT_F64>), 0, s, a);
+  else
+    hipLaunchKernelGGL(contract_kernel<IGAMT_F32>, grid, dim3(64 * kWaves<IGAMT_F32>), 0, s, a);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
 }  // namespace igamt
 
 using namespace igamt;

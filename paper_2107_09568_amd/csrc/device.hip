@@ -61,9 +61,12 @@ igamt_status ensure_device(igamt_plan *P) {
   IGAMT_LAUNCH_CHECK();
   const int64_t MK = P->Mp * P->Kp;
   IGAMT_HIP(hipMalloc((void **)&d.table, MK * sizeof(double)));
-  IGAMT_HIP(hipMalloc((void **)&d.table_t, MK * sizeof(double)));
+  const int64_t MKt = transposed_rows(P) * P->Mp;   // rows past Kp stay zero
+  IGAMT_HIP(hipMalloc((void **)&d.table_t, MKt * sizeof(double)));
+  IGAMT_HIP(hipMemset(d.table_t, 0, MKt * sizeof(double)));
   IGAMT_HIP(hipMalloc((void **)&d.table_f32, MK * sizeof(float)));
-  IGAMT_HIP(hipMalloc((void **)&d.table_t_f32, MK * sizeof(float)));
+  IGAMT_HIP(hipMalloc((void **)&d.table_t_f32, MKt * sizeof(float)));
+  IGAMT_HIP(hipMemset(d.table_t_f32, 0, MKt * sizeof(float)));
   IGAMT_HIP(hipMalloc((void **)&d.table_bf, 2 * MK * sizeof(uint16_t)));
   IGAMT_HIP(hipMalloc((void **)&d.table_h, 2 * MK * sizeof(uint16_t)));
   IGAMT_HIP(hipMalloc((void **)&d.table_h_scale, P->Mp * sizeof(float)));

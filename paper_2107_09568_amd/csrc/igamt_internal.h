@@ -69,9 +69,9 @@ struct DevicePtrs {
   int32_t *flag = nullptr;           // smallest degenerate tile index (INT32_MAX = none)
   // tables
   double *table = nullptr;           // [Mp][Kp] FP64, zero padded
-  double *table_t = nullptr;         // [Kp][Mp] FP64 (transposed, for the adjoint)
+  double *table_t = nullptr;         // [transposed_rows][Mp] FP64 (transposed, zero padded, for the adjoint)
   float *table_f32 = nullptr;        // [Mp][Kp]
-  float *table_t_f32 = nullptr;      // [Kp][Mp]
+  float *table_t_f32 = nullptr;      // [transposed_rows][Mp]
   uint16_t *table_bf = nullptr;      // hi [Mp][Kp] then lo [Mp][Kp]
   uint16_t *table_h = nullptr;       // hi then lo, scaled rows
   float *table_h_scale = nullptr;    // [Mp] inverse row scale
@@ -137,4 +137,10 @@ igamt_status launch_contract(igamt_plan *plan, igamt_precision prec, const void 
                              void *stream);
 igamt_status launch_scatter(igamt_plan *plan, igamt_precision prec, const void *d_blocks, void *d_values,
                             void *stream);
+// C (rows x 9 n_tiles) = A (rows_pad x kdim, row-major) B (kdim per column, 9 n_tiles_pad columns),
+// written as out[t][row][ab] for row < rows; FP64 or FP32 operands (contract.hip)
+igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *B, void *out, int64_t rows,
+                               int64_t rows_pad, int64_t kdim, int64_t n_tiles, int64_t n_groups, void *stream);
+// rows of the transposed table (table columns padded to a multiple of the contraction's row block)
+inline int64_t transposed_rows(const igamt_plan *P) { return (P->Kp + 127) / 128 * 128; }
 }  // namespace igamt
