@@ -119,8 +119,13 @@ igamt_status igamt_plan_csr_device(igamt_plan *plan, int64_t *d_row_ptr, int32_t
  * New macro control points [n_ctrl z][y][x][3], from host (on_device = 0) or
  * device memory (on_device = 1).                                              */
 igamt_status igamt_set_macro_ctrl(igamt_plan *plan, const double *ctrl, int32_t on_device, void *stream);
-/* New reference-tile control points (host), same knots; tables must be rebuilt. */
+/* New reference-tile control points (host), same knots; tables must be rebuilt.
+ * Boundary points must stay at their Greville positions (IGAMT_EINVAL).       */
 igamt_status igamt_set_tile_ctrl(igamt_plan *plan, const double *ctrl);
+/* The same from device memory (double [n_z][n_y][n_x][3]), queued on the
+ * stream; the boundary check runs on the device and a violation is reported
+ * by the next igamt_check (IGAMT_EINVAL).                                     */
+igamt_status igamt_set_tile_ctrl_device(igamt_plan *plan, const double *d_ctrl, void *stream);
 
 /* --- lookup tables (eq. (52), (57)) ------------------------------------------
  * Table layout (row-major): table[p][9 C + 3 i + j], p = pair index, C =
@@ -131,6 +136,11 @@ igamt_status igamt_set_tile_ctrl(igamt_plan *plan, const double *ctrl);
  * the FP32 and split BF16 / F16 copies used by the other precisions are
  * derived on the device.                                                      */
 igamt_status igamt_tables_build(igamt_plan *plan, void *stream);
+/* tables_build whose kernels do nothing unless *d_gate != 0 (int32 on the
+ * device), so that a decision taken on the device (igamt_table_rows_check)
+ * selects the exact table without a host round trip.  The plan must already
+ * hold a table (built, set or reconstructed), which is kept when the gate is 0. */
+igamt_status igamt_tables_build_gated(igamt_plan *plan, const int32_t *d_gate, void *stream);
 igamt_status igamt_tables_set(igamt_plan *plan, const double *d_table, void *stream);
 igamt_status igamt_tables_get(const igamt_plan *plan, double *d_out, void *stream);
 /* Exact FP64 table rows for the listed pair indices (device int32 [n_rows]) into
@@ -222,6 +232,11 @@ igamt_status igamt_table_from_pod(igamt_plan *plan, const float *d_mean, const f
  * exact rows (d_exact double [n_rows][n_cols]); result to d_err double [1].   */
 igamt_status igamt_table_rows_error(const igamt_plan *plan, const int32_t *d_rows, int32_t n_rows,
                                     const double *d_exact, double *d_err, void *stream);
+/* The same error, plus a decision for igamt_tables_build_gated: d_gate int32 [1]
+ * is set to 0 when the error is <= tol and to 1 otherwise (also for NaN).    */
+igamt_status igamt_table_rows_check(const igamt_plan *plan, const int32_t *d_rows, int32_t n_rows,
+                                    const double *d_exact, double tol, double *d_err, int32_t *d_gate,
+                                    void *stream);
 
 /* Multilayer perceptron x -> GELU(x W1 + b1) -> ... -> x W_L + b_L (no
  * activation on the last layer), GELU(z) = 0.5 z (1 + erf(z / sqrt 2)).
@@ -249,6 +264,21 @@ igamt_status igamt_mlp_backward(const igamt_mlp_desc *desc, const float *d_param
 /* Adam with bias correction, in place on d_params, d_m, d_v (float [n]). */
 igamt_status igamt_adam_step(float *d_params, const float *d_grads, float *d_m, float *d_v, int64_t n,
                              float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* The whole learned-table step for one design, queued on the stream with no host
+ * synchronisation: MLP forward (desc->batch = 1, d_x the scaled parameters
+ * [1][n_in], d_act / d_y its workspace and output [1][r]), POD reconstruction
+ * into the plan's table (as igamt_table_from_pod with the MLP output as
+ * coefficients), exact rebuild of the check rows (as igamt_tables_build_rows,
+ * into d_exact_rows double [n_rows][n_cols]), their error and gate (as
+ * igamt_table_rows_check), and the exact table in place of the learned one when
+ * the gate is set (as igamt_tables_build_gated).  The tile control points of the
+ * design must have been set before.                                           */
+igamt_status igamt_table_learned(igamt_plan *plan, const igamt_mlp_desc *desc, const float *d_params,
+                                 const float *d_x, float *d_act, float *d_y, const float *d_mean,
+                                 const float *d_basis, double coeff_scale, const int32_t *d_rows,
+                                 int32_t n_rows, double *d_exact_rows, double tol, double *d_err,
+                                 int32_t *d_gate, void *stream);
 
 #ifdef __cplusplus
 }

@@ -134,12 +134,23 @@ class Plan:
             check(lib().igamt_set_macro_ctrl(self._h, a.ctypes.data_as(C.c_void_p), 0, _stream()))
 
     def set_tile_ctrl(self, ctrl):
-        a = np.ascontiguousarray(ctrl, dtype=np.float64)
-        assert a.size == 3 * self.n_tile_ctrl
-        check(lib().igamt_set_tile_ctrl(self._h, a.ctypes.data_as(C.c_void_p)))
+        torch = _torch()
+        if isinstance(ctrl, torch.Tensor):
+            assert ctrl.is_cuda and ctrl.dtype == torch.float64 and ctrl.is_contiguous()
+            assert ctrl.numel() == 3 * self.n_tile_ctrl
+            check(lib().igamt_set_tile_ctrl_device(self._h, _ptr(ctrl), _stream()))
+        else:
+            a = np.ascontiguousarray(ctrl, dtype=np.float64)
+            assert a.size == 3 * self.n_tile_ctrl
+            check(lib().igamt_set_tile_ctrl(self._h, a.ctypes.data_as(C.c_void_p)))
 
-    def tables_build(self):
-        check(lib().igamt_tables_build(self._h, _stream()))
+    def tables_build(self, gate=None):
+        if gate is None:
+            check(lib().igamt_tables_build(self._h, _stream()))
+        else:
+            torch = _torch()
+            assert gate.is_cuda and gate.dtype == torch.int32
+            check(lib().igamt_tables_build_gated(self._h, _ptr(gate), _stream()))
 
     def tables_set(self, table):
         torch = _torch()
@@ -244,6 +255,15 @@ class Plan:
         r = basis.shape[0]
         check(lib().igamt_table_from_pod(self._h, _ptr(mean), _ptr(basis), int(r), _ptr(coeffs.contiguous()),
                                          float(scale), _stream()))
+
+    def table_rows_check(self, rows, exact_rows, tol, err=None, gate=None):
+        """(relative error on the rows, int32 gate = error > tol), both left on the device."""
+        torch = _torch()
+        err = torch.empty(1, dtype=torch.float64, device="cuda") if err is None else err
+        gate = torch.empty(1, dtype=torch.int32, device="cuda") if gate is None else gate
+        check(lib().igamt_table_rows_check(self._h, _ptr(rows), int(rows.numel()), _ptr(exact_rows), float(tol),
+                                           _ptr(err), _ptr(gate), _stream()))
+        return err, gate
 
     def table_rows_error(self, rows, exact_rows):
         torch = _torch()

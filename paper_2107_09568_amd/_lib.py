@@ -45,7 +45,9 @@ SIGNATURES = {
     "igamt_plan_csr_device": (status, [vp, vp, vp, vp]),
     "igamt_set_macro_ctrl": (status, [vp, vp, i32, vp]),
     "igamt_set_tile_ctrl": (status, [vp, vp]),
+    "igamt_set_tile_ctrl_device": (status, [vp, vp, vp]),
     "igamt_tables_build": (status, [vp, vp]),
+    "igamt_tables_build_gated": (status, [vp, vp, vp]),
     "igamt_tables_set": (status, [vp, vp, vp]),
     "igamt_tables_get": (status, [vp, vp, vp]),
     "igamt_tables_build_rows": (status, [vp, vp, i32, vp, vp]),
@@ -61,6 +63,9 @@ SIGNATURES = {
     "igamt_pod_build": (status, [vp, i32, i64, i32, vp, vp, vp, vp, vp, vp]),
     "igamt_table_from_pod": (status, [vp, vp, vp, i32, vp, f64, vp]),
     "igamt_table_rows_error": (status, [vp, vp, i32, vp, vp, vp]),
+    "igamt_table_rows_check": (status, [vp, vp, i32, vp, f64, vp, vp, vp]),
+    "igamt_table_learned": (status, [vp, C.POINTER(MlpDesc), vp, vp, vp, vp, vp, vp, f64, vp, i32, vp, f64, vp, vp,
+                                     vp]),
     "igamt_mlp_n_params": (i64, [C.POINTER(MlpDesc)]),
     "igamt_mlp_forward": (status, [C.POINTER(MlpDesc), vp, vp, vp, vp, vp]),
     "igamt_mse_loss": (status, [C.POINTER(MlpDesc), vp, vp, vp, vp, vp]),

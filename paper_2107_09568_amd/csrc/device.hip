@@ -48,6 +48,7 @@ igamt_status ensure_device(igamt_plan *P) {
   }
   UP(d.macro_ctrl, P->ctrlM);
   UP(d.tile_ctrl, P->ctrlT);
+  UP(d.tile_grev, P->grevT);
   UP(d.fit_x, P->fit_x);
   UP(d.fit_P, P->fit_P);
   UP(d.gauss_x, P->gauss_x);
@@ -82,7 +83,7 @@ void free_device(igamt_plan *P) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(d.device);
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
+  void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
                   d.table_h_scale, d.point_data, d.mirror_perm, d.pair_desc};
   for (void *p : ptrs)
@@ -95,6 +96,24 @@ void free_device(igamt_plan *P) {
   }
   (void)hipSetDevice(cur);
   d = DevicePtrs();
+}
+
+igamt_status upload_tile_ctrl(igamt_plan *P) {
+  IGAMT_HIP(hipMemcpy(P->dev.tile_ctrl, P->ctrlT.data(), P->ctrlT.size() * sizeof(double), hipMemcpyHostToDevice));
+  return IGAMT_OK;
+}
+
+// A tile control point on the tile boundary that is not at its Greville position breaks the
+// gluing of neighbouring tiles: the smallest such point index goes to flag[2].
+static __global__ void tile_boundary_kernel(const double *__restrict__ ctrl, const double *__restrict__ grev, int nx,
+                                            int ny, int nz, int32_t *flag) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nx * ny * nz) return;
+  const int i = id % nx, j = (id / nx) % ny, k = id / (nx * ny);
+  if (!(i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1)) return;
+  const double e = fabs(ctrl[3 * id] - grev[i]) + fabs(ctrl[3 * id + 1] - grev[nx + j]) +
+                   fabs(ctrl[3 * id + 2] - grev[nx + ny + k]);
+  if (!(e <= 1e-12)) atomicMin(flag + 2, id);
 }
 
 igamt_status upload_macro_ctrl(igamt_plan *P, const double *ctrl, int on_device, void *stream) {
@@ -114,10 +133,11 @@ igamt_status upload_macro_ctrl(igamt_plan *P, const double *ctrl, int on_device,
 
 // One block per table row: FP32 copy, bfloat16 hi/lo split, float16 hi/lo split
 // with a power-of-two row scale (padding rows/columns are zero and stay zero).
-static __global__ __launch_bounds__(256) void table_copies_kernel(const double *__restrict__ T, int64_t Kp,
+static __global__ __launch_bounds__(256) void table_copies_kernel(const int32_t *gate, const double *__restrict__ T, int64_t Kp,
                                                                   float *__restrict__ T32, uint16_t *__restrict__ Tbf,
                                                                   uint16_t *__restrict__ Th, float *__restrict__ hscale,
                                                                   int64_t MK) {
+  if (gate && *gate == 0) return;
   const int64_t row = blockIdx.x;
   const double *r = T + row * Kp;
   __shared__ double red[256];
@@ -144,8 +164,9 @@ static __global__ __launch_bounds__(256) void table_copies_kernel(const double *
   }
 }
 
-static __global__ void transpose_kernel(const double *__restrict__ T, int64_t Mp, int64_t Kp,
+static __global__ void transpose_kernel(const int32_t *gate, const double *__restrict__ T, int64_t Mp, int64_t Kp,
                                         double *__restrict__ Tt, float *__restrict__ Tt32) {
+  if (gate && *gate == 0) return;
   __shared__ double tile[32][33];
   const int64_t k0 = (int64_t)blockIdx.x * 32, m0 = (int64_t)blockIdx.y * 32;
   for (int j = threadIdx.y; j < 32; j += 8) tile[j][threadIdx.x] = T[(m0 + j) * Kp + k0 + threadIdx.x];
@@ -157,14 +178,14 @@ static __global__ void transpose_kernel(const double *__restrict__ T, int64_t Mp
   }
 }
 
-igamt_status derive_table_copies(igamt_plan *P, void *stream) {
+igamt_status derive_table_copies(igamt_plan *P, void *stream, const int32_t *gate) {
   hipStream_t s = (hipStream_t)stream;
   DevicePtrs &d = P->dev;
-  hipLaunchKernelGGL(table_copies_kernel, dim3((unsigned)P->Mp), dim3(256), 0, s, d.table, (int64_t)P->Kp,
+  hipLaunchKernelGGL(table_copies_kernel, dim3((unsigned)P->Mp), dim3(256), 0, s, gate, d.table, (int64_t)P->Kp,
                      d.table_f32, d.table_bf, d.table_h, d.table_h_scale, P->Mp * P->Kp);
   IGAMT_LAUNCH_CHECK();
   hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(P->Kp / 32), (unsigned)(P->Mp / 32)), dim3(32, 8), 0, s,
-                     d.table, (int64_t)P->Mp, (int64_t)P->Kp, d.table_t, d.table_t_f32);
+                     gate, d.table, (int64_t)P->Mp, (int64_t)P->Kp, d.table_t, d.table_t_f32);
   IGAMT_LAUNCH_CHECK();
   P->tables_ready = true;
   return IGAMT_OK;
@@ -317,6 +338,19 @@ extern "C" igamt_status igamt_plan_csr_device(igamt_plan *P, int64_t *d_row_ptr,
   return IGAMT_OK;
 }
 
+extern "C" igamt_status igamt_set_tile_ctrl_device(igamt_plan *P, const double *d_ctrl, void *stream) {
+  if (!P || !d_ctrl) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  IGAMT_HIP(hipMemcpyAsync(P->dev.tile_ctrl, d_ctrl, 3 * P->nTt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(tile_boundary_kernel, dim3((unsigned)((P->nTt + 255) / 256)), dim3(256), 0, s, P->dev.tile_ctrl,
+                     P->dev.tile_grev, P->nT[0], P->nT[1], P->nT[2], P->dev.flag);
+  IGAMT_LAUNCH_CHECK();
+  P->tables_ready = false;
+  return IGAMT_OK;
+}
+
 extern "C" igamt_status igamt_check(igamt_plan *P, void *stream, int64_t *bad_tile) {
   if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
   if (bad_tile) *bad_tile = -1;
@@ -337,6 +371,10 @@ extern "C" igamt_status igamt_check(igamt_plan *P, void *stream, int64_t *bad_ti
     if (bad_tile) *bad_tile = h[1];
     set_error("reference tile map not positively oriented in micro element " + std::to_string(h[1]));
     return IGAMT_EDEGENERATE;
+  }
+  if (h[2] != INT32_MAX) {
+    set_error("tile boundary control point " + std::to_string(h[2]) + " is not at its Greville position");
+    return IGAMT_EINVAL;
   }
   return IGAMT_OK;
 }

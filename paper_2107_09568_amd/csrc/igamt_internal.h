@@ -53,6 +53,7 @@ struct DevicePtrs {
   double *fit_P = nullptr;           // [(q+1) * n_fit] 1-D projection matrix
   double *tile_knots[3] = {nullptr, nullptr, nullptr};
   double *tile_ctrl = nullptr;
+  double *tile_grev = nullptr;       // [n_x + n_y + n_z] Greville abscissae of the tile knots
   double *gauss_x = nullptr;         // [n_gauss] nodes on [0,1]
   double *gauss_w = nullptr;
   int32_t *pairs = nullptr;          // [n_pairs][2]
@@ -89,6 +90,7 @@ struct igamt_plan {
   int pT[3], nT[3];
   std::vector<double> kT[3];
   std::vector<double> ctrlT;
+  std::vector<double> grevT;           // Greville abscissae of the tile knots, x then y then z
   int eT[3];                          // micro elements per direction
   // descriptor
   int tiles[3], box_mode, q, n_fit, n_gauss;
@@ -128,7 +130,10 @@ int find_span_host(const std::vector<double> &U, int n, int p, double x);
 igamt_status ensure_device(igamt_plan *plan);
 void free_device(igamt_plan *plan);
 igamt_status upload_macro_ctrl(igamt_plan *plan, const double *ctrl, int on_device, void *stream);
-igamt_status derive_table_copies(igamt_plan *plan, void *stream);
+// copies for the other precisions; with a gate, the kernels do nothing unless *gate != 0
+igamt_status derive_table_copies(igamt_plan *plan, void *stream, const int32_t *gate = nullptr);
+// synchronous upload of the host tile control points
+igamt_status upload_tile_ctrl(igamt_plan *plan);
 // stage launchers (fit.hip, contract.hip, scatter.hip)
 int64_t coef_bytes(const igamt_plan *plan, igamt_precision prec);
 int64_t blocks_bytes(const igamt_plan *plan, igamt_precision prec);

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(256) void pod_reconstruct_kernel(const float *__res
 
 __global__ __launch_bounds__(256) void rows_error_kernel(const double *__restrict__ table, int64_t Kp, int K,
                                                          const int32_t *__restrict__ rows, int n_rows, int64_t n_pairs,
-                                                         const double *__restrict__ exact, double *__restrict__ err) {
+                                                         const double *__restrict__ exact, double *__restrict__ err,
+                                                         double tol, int32_t *__restrict__ gate) {
   __shared__ double num[256], den[256];
   double a = 0.0, b = 0.0;
   for (int64_t i = threadIdx.x; i < (int64_t)n_rows * K; i += 256) {
@@ -185,7 +186,11 @@ __global__ __launch_bounds__(256) void rows_error_kernel(const double *__restric
     if (threadIdx.x < s) { num[threadIdx.x] += num[threadIdx.x + s]; den[threadIdx.x] += den[threadIdx.x + s]; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) err[0] = sqrt(num[0] / den[0]);
+  if (threadIdx.x == 0) {
+    const double e = sqrt(num[0] / den[0]);
+    err[0] = e;
+    if (gate) gate[0] = e <= tol ? 0 : 1;   // NaN (bad row, empty reference) also asks for the exact table
+  }
 }
 
 // ---- MLP -----------------------------------------------------------------------------
@@ -380,7 +385,21 @@ extern "C" igamt_status igamt_table_rows_error(const igamt_plan *P, const int32_
   if (!P || !d_rows || !d_exact || !d_err || n_rows < 1) { set_error("invalid argument"); return IGAMT_EINVAL; }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
   hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
-                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err);
+                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, 0.0, nullptr);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_table_rows_check(const igamt_plan *P, const int32_t *d_rows, int32_t n_rows,
+                                               const double *d_exact, double tol, double *d_err, int32_t *d_gate,
+                                               void *stream) {
+  if (!P || !d_rows || !d_exact || !d_err || !d_gate || n_rows < 1 || !(tol >= 0.0)) {
+    set_error("invalid argument");
+    return IGAMT_EINVAL;
+  }
+  if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
+  hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
+                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
@@ -460,4 +479,27 @@ extern "C" igamt_status igamt_adam_step(float *d_params, const float *d_grads, f
                      n, lr, beta1, beta2, eps, c1, c2);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_tables_build_rows(igamt_plan *P, const int32_t *d_rows, int32_t n_rows, double *d_out,
+                                                void *stream);
+extern "C" igamt_status igamt_tables_build_gated(igamt_plan *P, const int32_t *d_gate, void *stream);
+
+extern "C" igamt_status igamt_table_learned(igamt_plan *P, const igamt_mlp_desc *mlp, const float *d_params,
+                                            const float *d_x, float *d_act, float *d_y, const float *d_mean,
+                                            const float *d_basis, double coeff_scale, const int32_t *d_rows,
+                                            int32_t n_rows, double *d_exact_rows, double tol, double *d_err,
+                                            int32_t *d_gate, void *stream) {
+  if (!P || !mlp || !d_params || !d_x || !d_act || !d_y || !d_mean || !d_basis || !d_rows || !d_exact_rows ||
+      !d_err || !d_gate) {
+    set_error("NULL argument");
+    return IGAMT_EINVAL;
+  }
+  if (mlp->batch != 1) { set_error("the learned table path predicts one design (batch 1)"); return IGAMT_EINVAL; }
+  igamt_status st;
+  if ((st = igamt_mlp_forward(mlp, d_params, d_x, d_act, d_y, stream))) return st;
+  if ((st = igamt_table_from_pod(P, d_mean, d_basis, mlp->widths[mlp->n_layers], d_y, coeff_scale, stream))) return st;
+  if ((st = igamt_tables_build_rows(P, d_rows, n_rows, d_exact_rows, stream))) return st;
+  if ((st = igamt_table_rows_check(P, d_rows, n_rows, d_exact_rows, tol, d_err, d_gate, stream))) return st;
+  return igamt_tables_build_gated(P, d_gate, stream);
 }

@@ -188,6 +188,8 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
   {
     std::vector<double> g[3];
     for (int d = 0; d < 3; ++d) g[d] = greville(P->kT[d], P->pT[d], P->nT[d]);
+    P->grevT.clear();
+    for (int d = 0; d < 3; ++d) P->grevT.insert(P->grevT.end(), g[d].begin(), g[d].end());
     for (int k = 0; k < P->nT[2]; ++k)
       for (int j = 0; j < P->nT[1]; ++j)
         for (int i = 0; i < P->nT[0]; ++i) {
@@ -488,5 +490,6 @@ extern "C" igamt_status igamt_set_tile_ctrl(igamt_plan *P, const double *ctrl) {
       }
   P->ctrlT = c;
   P->tables_ready = false;
+  if (P->dev.ready) return upload_tile_ctrl(P);
   return IGAMT_OK;
 }

@@ -7,9 +7,9 @@
 // Pass 1 (one thread per micro element x Gauss point) evaluates the tile map
 // and stores, per point, w det J_T, the Bernstein values N_C(T^r(theta)) and the
 // mapped gradients of the (p+1)^3 active functions.  Pass 2 (one thread per
-// table row and Bernstein index C) sums the 9 (i, j) integrals over the micro
-// elements shared by A and B, in ascending element and point order, so the
-// table is bitwise reproducible.
+// table entry: row, Bernstein index C, (i, j)) sums over the micro elements
+// shared by A and B in ascending element and point order, so the table is
+// bitwise reproducible.
 #include "device_common.h"
 
 namespace igamt {
@@ -23,10 +23,12 @@ struct TableArgs {
   int64_t stride;        // doubles per point record
   double *pts;
   int32_t *flag;
+  const int32_t *gate;   // optional: do nothing unless *gate != 0
 };
 
 template <int PT>
 __global__ __launch_bounds__(64) void table_points_kernel(TableArgs a) {
+  if (a.gate && *a.gate == 0) return;
   const int G = a.ng * a.ng * a.ng;
   const int64_t id = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int64_t nE = (int64_t)a.eT[0] * a.eT[1] * a.eT[2];
@@ -100,17 +102,23 @@ struct TableSumArgs {
   const double *pts;
   double *out;
   int64_t out_stride;    // doubles per output row
+  const int32_t *gate;   // optional: do nothing unless *gate != 0
 };
 
+// One thread per table entry (row, C, ij): the sum over the shared micro elements and their
+// Gauss points runs in ascending element and point order, so every entry is bitwise
+// reproducible and the same whether the whole table or a row subset is built.
 __global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
+  if (a.gate && *a.gate == 0) return;
   const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= a.n_rows * a.npi) return;
-  const int64_t row = id / a.npi;
-  const int C = (int)(id % a.npi);
+  if (id >= a.n_rows * a.npi * 9) return;
+  const int ij = (int)(id % 9), i = ij / 3, j = ij - 3 * i;
+  const int C = (int)((id / 9) % a.npi);
+  const int64_t row = id / (9 * (int64_t)a.npi);
   const int64_t p = a.rows ? a.rows[row] : row;
+  double *o = a.out + row * a.out_stride + 9 * C + ij;
   if (p < 0 || p >= a.n_pairs) {  // invalid row index: flag the output instead of reading out of bounds
-    double *o = a.out + row * a.out_stride + 9 * C;
-    for (int k = 0; k < 9; ++k) o[k] = __builtin_nan("");
+    *o = __builtin_nan("");
     return;
   }
   const int A = a.pairs[2 * p], B = a.pairs[2 * p + 1];
@@ -124,9 +132,7 @@ __global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
   }
   const int G = a.ng * a.ng * a.ng;
   const int p1 = a.pT + 1;
-  double acc[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  double acc = 0.0;
   for (int ez = lo[2]; ez <= hi[2]; ++ez)
     for (int ey = lo[1]; ey <= hi[1]; ++ey)
       for (int ex = lo[0]; ex <= hi[0]; ++ex) {
@@ -136,26 +142,20 @@ __global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
         const double *pd = a.pts + e * G * a.stride;
         for (int g = 0; g < G; ++g, pd += a.stride) {
           const double wn = pd[0] * pd[1 + C];
-          const double *gA = pd + 1 + a.npi + 3 * la;
-          const double *gB = pd + 1 + a.npi + 3 * lb;
-          const double a0 = wn * gA[0], a1 = wn * gA[1], a2 = wn * gA[2];
-          const double b0 = gB[0], b1 = gB[1], b2 = gB[2];
-          acc[0] += a0 * b0; acc[1] += a0 * b1; acc[2] += a0 * b2;
-          acc[3] += a1 * b0; acc[4] += a1 * b1; acc[5] += a1 * b2;
-          acc[6] += a2 * b0; acc[7] += a2 * b1; acc[8] += a2 * b2;
+          const double ga = wn * pd[1 + a.npi + 3 * la + i];
+          acc += ga * pd[1 + a.npi + 3 * lb + j];
         }
       }
-  double *o = a.out + row * a.out_stride + 9 * C;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) o[k] = acc[k];
+  *o = acc;
 }
 
-static __global__ void zero_f64(double *p, int64_t n) {
+static __global__ void zero_f64(const int32_t *gate, double *p, int64_t n) {
+  if (gate && *gate == 0) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
 }
 
-static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride) {
+static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride, const int32_t *gate) {
   const int G = P->n_gauss * P->n_gauss * P->n_gauss;
   const int64_t nE = (int64_t)P->eT[0] * P->eT[1] * P->eT[2];
   const int nact = (P->pT[0] + 1) * (P->pT[1] + 1) * (P->pT[2] + 1);
@@ -165,9 +165,6 @@ static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride) {
     set_error("reference tiles with different degrees per direction are not supported");
     return IGAMT_EUNSUPPORTED;
   }
-  // the tile control points may have changed since the last upload
-  IGAMT_HIP(hipMemcpyAsync(P->dev.tile_ctrl, P->ctrlT.data(), P->ctrlT.size() * sizeof(double),
-                           hipMemcpyHostToDevice, s));
   TableArgs a;
   for (int k = 0; k < 3; ++k) {
     a.knots[k] = P->dev.tile_knots[k];
@@ -183,6 +180,7 @@ static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride) {
   a.stride = stride;
   a.pts = P->dev.point_data;
   a.flag = P->dev.flag;
+  a.gate = gate;
   const dim3 grid((unsigned)((nE * G + 63) / 64)), block(64);
   switch (P->pT[0]) {
     case 1: hipLaunchKernelGGL(table_points_kernel<1>, grid, block, 0, s, a); break;
@@ -201,6 +199,7 @@ static TableSumArgs sum_args(const igamt_plan *P, int64_t stride) {
   TableSumArgs b;
   b.pairs = P->dev.pairs;
   b.rows = nullptr;
+  b.gate = nullptr;
   b.n_rows = P->n_pairs;
   b.n_pairs = P->n_pairs;
   for (int k = 0; k < 3; ++k) {
@@ -219,23 +218,34 @@ static TableSumArgs sum_args(const igamt_plan *P, int64_t stride) {
 
 using namespace igamt;
 
-extern "C" igamt_status igamt_tables_build(igamt_plan *P, void *stream) {
-  if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
+static igamt_status build_tables(igamt_plan *P, void *stream, const int32_t *gate) {
   igamt_status st = ensure_device(P);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   int64_t stride = 0;
-  if ((st = run_points(P, s, stride))) return st;
+  if ((st = run_points(P, s, stride, gate))) return st;
   const int64_t MK = P->Mp * P->Kp;
-  hipLaunchKernelGGL(zero_f64, dim3((unsigned)((MK + 255) / 256)), dim3(256), 0, s, P->dev.table, MK);
+  hipLaunchKernelGGL(zero_f64, dim3((unsigned)((MK + 255) / 256)), dim3(256), 0, s, gate, P->dev.table, MK);
   IGAMT_LAUNCH_CHECK();
   TableSumArgs b = sum_args(P, stride);
   b.out = P->dev.table;
   b.out_stride = P->Kp;
-  const int64_t n = P->n_pairs * P->npi;
+  b.gate = gate;
+  const int64_t n = P->n_pairs * P->npi * 9;
   hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
   IGAMT_LAUNCH_CHECK();
-  return derive_table_copies(P, stream);
+  return derive_table_copies(P, stream, gate);
+}
+
+extern "C" igamt_status igamt_tables_build(igamt_plan *P, void *stream) {
+  if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  return build_tables(P, stream, nullptr);
+}
+
+extern "C" igamt_status igamt_tables_build_gated(igamt_plan *P, const int32_t *d_gate, void *stream) {
+  if (!P || !d_gate) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (!P->tables_ready) { set_error("a gated build replaces an existing table: build or set one first"); return IGAMT_ESTATE; }
+  return build_tables(P, stream, d_gate);
 }
 
 extern "C" igamt_status igamt_tables_build_rows(igamt_plan *P, const int32_t *d_rows, int32_t n_rows, double *d_out,
@@ -245,13 +255,13 @@ extern "C" igamt_status igamt_tables_build_rows(igamt_plan *P, const int32_t *d_
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   int64_t stride = 0;
-  if ((st = run_points(P, s, stride))) return st;
+  if ((st = run_points(P, s, stride, nullptr))) return st;
   TableSumArgs b = sum_args(P, stride);
   b.rows = d_rows;
   b.n_rows = n_rows;
   b.out = d_out;
   b.out_stride = P->K;
-  const int64_t n = (int64_t)n_rows * P->npi;
+  const int64_t n = (int64_t)n_rows * P->npi * 9;
   hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;

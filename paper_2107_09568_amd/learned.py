@@ -6,7 +6,8 @@ replaces the per-design build by a POD basis of the family's tables and a small
 MLP from the parameters to the POD coefficients; the exact table builder stays
 the fallback and the judge: a seeded subset of table rows is built exactly and
 compared with the learned table, and the exact table replaces it when the
-estimated relative error exceeds the tolerance.
+estimated relative error exceeds the tolerance.  The per-design path queues
+everything on the stream, the fallback decision included.
 
 Every numerical step runs in libigamt kernels (table builder, POD Gram and
 modes, MLP forward/backward/Adam, reconstruction, row error); this module only
@@ -160,6 +161,38 @@ class TableNet:
         x = (np.asarray(p, dtype=np.float64) - self.lo) / (self.hi - self.lo) * 2.0 - 1.0
         return torch.from_numpy(x.astype(np.float32)).cuda()
 
+    def _buffers(self):
+        """Device buffers of the per-design path and pinned host staging (allocated once)."""
+        torch = _torch()
+        if getattr(self, "_dev", None) is None:
+            n_c = 3 * self.plan.n_tile_ctrl
+            self._dev = {
+                "rows": torch.from_numpy(self.check_rows.astype(np.int32)).cuda(),
+                "ctrl": torch.empty(n_c, dtype=torch.float64, device="cuda"),
+                "x": torch.empty((1, 4), dtype=torch.float32, device="cuda"),
+                "err": torch.empty(1, dtype=torch.float64, device="cuda"),
+                "gate": torch.empty(1, dtype=torch.int32, device="cuda"),
+                "exact_rows": torch.empty((len(self.check_rows), self.plan.n_cols), dtype=torch.float64,
+                                          device="cuda"),
+                "h_ctrl": torch.empty(n_c, dtype=torch.float64).pin_memory(),
+                "h_x": torch.empty((1, 4), dtype=torch.float32).pin_memory(),
+                "copied": torch.cuda.Event(),
+            }
+        return self._dev
+
+    def _upload(self, p, tile_ctrl):
+        """Design parameters (scaled to [-1, 1]) and tile control points to the device, asynchronously."""
+        torch = _torch()
+        b = self._buffers()
+        b["copied"].synchronize()          # the staging buffers of the previous design have been read
+        x = (np.asarray(p, dtype=np.float64).reshape(1, -1) - self.lo) / (self.hi - self.lo) * 2.0 - 1.0
+        b["h_x"].numpy()[...] = x
+        b["h_ctrl"].numpy()[...] = np.ascontiguousarray(tile_ctrl, dtype=np.float64).ravel()
+        b["x"].copy_(b["h_x"], non_blocking=True)
+        b["ctrl"].copy_(b["h_ctrl"], non_blocking=True)
+        b["copied"].record()
+        return b
+
     # ---- offline ----------------------------------------------------------------------
     def exact_tables(self, tile_ctrls):
         """Exact FP64 tables of the given designs (device table builder), shape (n, n_e)."""
@@ -207,22 +240,30 @@ class TableNet:
         x = self.scale_inputs(np.atleast_2d(p))
         return self.mlp.forward(x)
 
+    def table_for_async(self, p, tile_ctrl):
+        """Queue the table of design p (tile control points tile_ctrl) into the plan: learned
+        reconstruction, exact rebuild of the check rows, error estimate, and the exact table in
+        place of the learned one when the estimate exceeds the tolerance -- the decision is taken
+        on the device, nothing waits on the host.  Returns device tensors (estimated relative
+        error [1] float64, fallback flag [1] int32)."""
+        b = self._upload(p, tile_ctrl)
+        self.plan.set_tile_ctrl(b["ctrl"])
+        self.mlp.set_batch(1)
+        check(lib().igamt_table_learned(self.plan._h, C.byref(self.mlp.desc), _ptr(self.mlp.params), _ptr(b["x"]),
+                                        _ptr(self.mlp.act), _ptr(self.mlp.y), _ptr(self.mean), _ptr(self.basis),
+                                        float(self.coeff_scale), _ptr(b["rows"]), int(b["rows"].numel()),
+                                        _ptr(b["exact_rows"]), float(self.tol), _ptr(b["err"]), _ptr(b["gate"]),
+                                        _stream()))
+        return b["err"], b["gate"]
+
     def table_for(self, p, tile_ctrl, force_exact=False):
         """Put the table of design p (tile control points tile_ctrl) into the plan.
 
         Returns (estimated relative error of the learned table on the check rows,
         True if the exact builder was used)."""
-        torch = _torch()
-        self.plan.set_tile_ctrl(tile_ctrl)
-        if not force_exact:
-            c = self.predict_coeffs(p)[0]
-            self.plan.table_from_pod(self.mean, self.basis, c, self.coeff_scale)
-            rows = torch.from_numpy(self.check_rows.astype(np.int32)).cuda()
-            exact_rows = self.plan.tables_build_rows(rows)
-            err = float(self.plan.table_rows_error(rows, exact_rows).item())
-            if err <= self.tol:
-                return err, False
-        else:
-            err = float("nan")
-        self.plan.tables_build()
-        return err, True
+        if force_exact:
+            self.plan.set_tile_ctrl(tile_ctrl)
+            self.plan.tables_build()
+            return float("nan"), True
+        err, gate = self.table_for_async(p, tile_ctrl)
+        return float(err.item()), bool(gate.item())

@@ -159,3 +159,40 @@ def test_learned_table_in_assembly(family):
     err = ((got - ref).norm() / ref.norm()).item()
     _say(f"assembly with learned table: CSR rel err {err:.2e} (estimated table err {est:.2e}, fallback {fb})")
     assert err < 3 * tn.tol
+
+
+def test_device_tile_ctrl_and_gated_build(env):
+    """Tile control points from device memory, the device boundary check, and the gated exact
+    build: gate 0 keeps the plan's table, gate 1 replaces it by the exact one."""
+    torch, P, L = env
+    w = W.make("cfg1")
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    exact_host = plan.tables_get().clone()
+    ctrl_d = torch.from_numpy(np.ascontiguousarray(w.tile.ctrl).ravel()).cuda()
+    plan.set_tile_ctrl(ctrl_d)
+    plan.tables_build()
+    assert torch.equal(plan.tables_get(), exact_host)
+    plan.check()
+    # a learned-looking table, then the gate decides
+    fake = exact_host * (1.0 + 1e-3)
+    plan.tables_set(fake)
+    gate = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.tables_build(gate=gate)
+    assert torch.equal(plan.tables_get(), fake)
+    rows = torch.arange(0, plan.n_pairs, 7, dtype=torch.int32, device="cuda")
+    exact_rows = plan.tables_build_rows(rows)
+    err, gate = plan.table_rows_check(rows, exact_rows, 5e-4)
+    assert gate.item() == 1 and err.item() == pytest.approx(1e-3, rel=1e-6)
+    err2, gate2 = plan.table_rows_check(rows, exact_rows, 2e-3)
+    assert gate2.item() == 0
+    plan.tables_build(gate=gate)
+    assert torch.equal(plan.tables_get(), exact_host)
+    # a moved boundary point is reported by the next check
+    bad = ctrl_d.clone()
+    bad[0] += 0.01
+    plan.set_tile_ctrl(bad)
+    with pytest.raises(P.IgamtError, match="Greville"):
+        plan.check()
+    plan.set_tile_ctrl(ctrl_d)
+    plan.check()
