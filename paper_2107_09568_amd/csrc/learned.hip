@@ -16,6 +16,8 @@
 #include <numeric>
 #include <vector>
 
+#include <limits>
+
 #include "device_common.h"
 
 namespace igamt {
@@ -109,44 +111,92 @@ __global__ __launch_bounds__(256) void pod_basis_kernel(const double *__restrict
     if (k0 + k < r) basis[(int64_t)(k0 + k) * n_e + e] = (float)acc[k];
 }
 
-// Cyclic Jacobi eigen-decomposition of a symmetric matrix (row-major, n x n).
-// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors.
-static void jacobi_eigen(std::vector<double> &A, int n, std::vector<double> &V) {
+// Symmetric eigen-decomposition (row-major A, n x n): Householder reduction to tridiagonal
+// form T = Q^T A Q, then implicit symmetric QR steps with the Wilkinson shift on T, each step a
+// chase of the bulge by Givens rotations that are also applied to Q (the method of Golub and
+// Van Loan, Matrix Computations, sections 8.3.1-8.3.3).  On return A's diagonal holds the
+// eigenvalues and V's columns (V[i n + k]) the eigenvectors.
+static void sym_eigen(std::vector<double> &A, int n, std::vector<double> &V) {
+  auto at = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
   V.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, diag = 0.0;
-    for (int i = 0; i < n; ++i) {
-      diag += A[(size_t)i * n + i] * A[(size_t)i * n + i];
-      for (int j = i + 1; j < n; ++j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+  std::vector<double> v(n), pv(n), w(n);
+  // 1. Householder: column k below the subdiagonal is annihilated by H = I - beta v v^T
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;   // length of the reflected part (indices k+1 .. n-1)
+    double nx = 0.0;
+    for (int i = 0; i < m; ++i) nx += at(k + 1 + i, k) * at(k + 1 + i, k);
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const double x0 = at(k + 1, k);
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    for (int i = 0; i < m; ++i) v[i] = at(k + 1 + i, k);
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (int i = 0; i < m; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // trailing block: A <- A - v w^T - w v^T with p = beta A v, w = p - (beta/2)(p.v) v
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += at(k + 1 + i, k + 1 + j) * v[j];
+      pv[i] = beta * acc;
     }
-    if (off <= 1e-30 * diag || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[(size_t)p * n + q];
-        if (std::fabs(apq) < 1e-300) continue;
-        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-        // rotation angle that zeroes A[p][q]: t = tan(theta) from the smaller root
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-        for (int k = 0; k < n; ++k) {   // columns p, q
-          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + p] = c * akp - s * akq;
-          A[(size_t)k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {   // rows p, q
-          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)p * n + k] = c * apk - s * aqk;
-          A[(size_t)q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = c * vkp - s * vkq;
-          V[(size_t)k * n + q] = s * vkp + c * vkq;
-        }
-      }
+    double pvv = 0.0;
+    for (int i = 0; i < m; ++i) pvv += pv[i] * v[i];
+    const double kk = 0.5 * beta * pvv;
+    for (int i = 0; i < m; ++i) w[i] = pv[i] - kk * v[i];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) at(k + 1 + i, k + 1 + j) -= v[i] * w[j] + w[i] * v[j];
+    at(k + 1, k) = at(k, k + 1) = alpha;
+    for (int i = 1; i < m; ++i) at(k + 1 + i, k) = at(k, k + 1 + i) = 0.0;
+    // Q <- Q H on columns k+1 .. n-1
+    for (int r = 0; r < n; ++r) {
+      double t = 0.0;
+      for (int j = 0; j < m; ++j) t += V[(size_t)r * n + k + 1 + j] * v[j];
+      t *= beta;
+      for (int j = 0; j < m; ++j) V[(size_t)r * n + k + 1 + j] -= t * v[j];
+    }
   }
+  std::vector<double> d(n), e(n > 1 ? n - 1 : 1, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = at(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(i + 1, i);
+  // 2. implicit symmetric QR with Wilkinson shift on (d, e)
+  const double eps = std::numeric_limits<double>::epsilon();
+  int hi = n - 1, iters = 0;
+  while (hi > 0 && iters < 64 * n) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    ++iters;
+    const double dl = 0.5 * (d[hi - 1] - d[hi]), bl = e[hi - 1];
+    const double mu = d[hi] - bl * bl / (dl + (dl >= 0.0 ? 1.0 : -1.0) * std::hypot(dl, bl));
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : z / r;
+      if (k > lo) e[k - 1] = r;   // (k-1, k) after zeroing the bulge at (k-1, k+1)
+      const double ak = d[k], ak1 = d[k + 1], bk = e[k];
+      d[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+      d[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+      e[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+      if (k + 1 < hi) {
+        x = e[k];
+        z = s * e[k + 1];        // new bulge at (k, k+2)
+        e[k + 1] = c * e[k + 1];
+      }
+      for (int i = 0; i < n; ++i) {  // Q <- Q R^T on columns k, k+1
+        const double qk = V[(size_t)i * n + k], qk1 = V[(size_t)i * n + k + 1];
+        V[(size_t)i * n + k] = c * qk + s * qk1;
+        V[(size_t)i * n + k + 1] = -s * qk + c * qk1;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) at(i, i) = d[i];
 }
 
 // table[p][k] = mean[e] + sum_r basis[r][e] c[r], e = p * K + k
@@ -338,7 +388,7 @@ extern "C" igamt_status igamt_pod_build(const double *d_snap, int32_t n_s, int64
   std::vector<double> A((size_t)n_s * n_s), V;
   IGAMT_HIP(hipMemcpyAsync(A.data(), G, A.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   IGAMT_HIP(hipStreamSynchronize(s));
-  jacobi_eigen(A, n_s, V);
+  sym_eigen(A, n_s, V);
   std::vector<int> order(n_s);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(),
