@@ -10,7 +10,7 @@
 // register of a wave within the 256 that leave the accumulators in VGPRs: the
 // FP64 MFMA runs about 2.3x slower when it accumulates in AGPRs.
 //
-// B chunks of 256 bytes per column are staged in LDS through registers, one chunk
+// B chunks (64 k values per column) are staged in LDS through registers, one chunk
 // ahead, into alternating buffers; each wave reads its A rows straight from
 // global memory one k-step ahead (they are not shared between waves).  Within a
 // lane group the k index is permuted so that every lane loads contiguous k
@@ -26,11 +26,11 @@
 namespace igamt {
 
 constexpr int BN = 144;                 // columns per workgroup (16 tiles x 9)
-constexpr int CHUNK_BYTES = 256;        // bytes of one B column staged per chunk
-constexpr int LDS_ROW = CHUNK_BYTES + 16;
-constexpr int PIECES = BN * CHUNK_BYTES / 16;   // 16-byte pieces of one staged chunk
 #ifndef NW_F64
 #define NW_F64 8
+#endif
+#ifndef KCH_F64
+#define KCH_F64 32
 #endif
 #ifndef NW_F32
 #define NW_F32 8
@@ -55,7 +55,7 @@ struct Mode<IGAMT_F64> {
   using E = double;                      // stored element
   using O = double;
   using Acc = d4;
-  static constexpr int KCH = 32;         // k per chunk (256 B of doubles)
+  static constexpr int KCH = KCH_F64;    // k per staged chunk (256 B of doubles per column)
   static constexpr int KSTEP = 16;       // k consumed per lane-load step
   static constexpr int WM = 1;           // 16-row blocks per wave
   static constexpr int NW = NW_F64;      // waves per workgroup
@@ -95,7 +95,16 @@ constexpr int kWaves = Mode<MODE>::NW;                // waves per workgroup
 template <int MODE>
 constexpr int kBM = 16 * Mode<MODE>::WM * Mode<MODE>::NW;   // table rows per workgroup
 template <int MODE>
-constexpr int kPre = (PIECES + 64 * kWaves<MODE> - 1) / (64 * kWaves<MODE>);   // staged pieces per thread
+constexpr int kChunkBytes =   // bytes of one B column per staged chunk (split modes: hi then lo half)
+    Mode<MODE>::KCH * ((MODE == IGAMT_F64 || MODE == IGAMT_F32) ? (int)sizeof(typename Mode<MODE>::E) : 4);
+template <int MODE>
+constexpr int kLdsRow = kChunkBytes<MODE> + 16;   // padded LDS row of one column
+template <int MODE>
+constexpr int kPpc = kChunkBytes<MODE> / 16;      // 16-byte pieces per column
+template <int MODE>
+constexpr int kPieces = BN * kPpc<MODE>;          // 16-byte pieces of one staged chunk
+template <int MODE>
+constexpr int kPre = (kPieces<MODE> + 64 * kWaves<MODE> - 1) / (64 * kWaves<MODE>);   // staged pieces per thread
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -106,16 +115,17 @@ __device__ inline void load_chunk_regs(const ContractArgs &a, int64_t grp, int64
 #pragma unroll
   for (int i = 0; i < kPre<MODE>; ++i) {
     int pc = tid + NT * i;
-    if (PIECES % NT != 0 && pc >= PIECES) pc = tid & 15;
-    const int n = pc >> 4, j = pc & 15;
+    if (kPieces<MODE> % NT != 0 && pc >= kPieces<MODE>) pc = tid % kPpc<MODE>;
+    const int n = pc / kPpc<MODE>, j = pc % kPpc<MODE>;
     const int64_t col = grp * BN + n;
     if constexpr (MODE == IGAMT_F64 || MODE == IGAMT_F32) {
       using E = typename Mode<MODE>::E;
       const char *src = (const char *)((const E *)a.B + col * a.Kp + k0) + 16 * j;
       r[i] = *(const u32x4 *)src;
     } else {
-      const uint16_t *plane = (j < 8) ? (const uint16_t *)a.B : (const uint16_t *)a.B2;
-      const char *src = (const char *)(plane + col * a.Kp + k0) + 16 * (j & 7);
+      constexpr int H = kPpc<MODE> / 2;   // pieces of the hi half
+      const uint16_t *plane = (j < H) ? (const uint16_t *)a.B : (const uint16_t *)a.B2;
+      const char *src = (const char *)(plane + col * a.Kp + k0) + 16 * (j % H);
       r[i] = *(const u32x4 *)src;
     }
   }
@@ -127,9 +137,9 @@ __device__ inline void store_chunk_lds(char *lds, int tid, const u32x4 (&r)[kPre
 #pragma unroll
   for (int i = 0; i < kPre<MODE>; ++i) {
     const int pc = tid + NT * i;
-    if (PIECES % NT != 0 && pc >= PIECES) break;
-    const int n = pc >> 4, j = pc & 15;
-    *(u32x4 *)(lds + n * LDS_ROW + 16 * j) = r[i];
+    if (kPieces<MODE> % NT != 0 && pc >= kPieces<MODE>) break;
+    const int n = pc / kPpc<MODE>, j = pc % kPpc<MODE>;
+    *(u32x4 *)(lds + n * kLdsRow<MODE> + 16 * j) = r[i];
   }
 }
 
@@ -160,7 +170,7 @@ struct Frag<MODE, false> {
     if constexpr (!JIT_B) {
 #pragma unroll
       for (int ni = 0; ni < 9; ++ni) {
-        const E *bp = (const E *)(buf + (ni * 16 + l16) * LDS_ROW) + kk + 4 * kq;
+        const E *bp = (const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq;
 #pragma unroll
         for (int s = 0; s < 4; ++s) bv[ni][s] = bp[s];
       }
@@ -171,13 +181,13 @@ struct Frag<MODE, false> {
     if constexpr (JIT_B) {
       E b[2][9];
 #pragma unroll
-      for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * LDS_ROW) + kk + 4 * kq);
+      for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         if (s + 1 < 4) {
 #pragma unroll
           for (int ni = 0; ni < 9; ++ni)
-            b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * LDS_ROW) + kk + 4 * kq + s + 1);
+            b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq + s + 1);
         }
 #pragma unroll
         for (int mi = 0; mi < WM; ++mi)
@@ -218,9 +228,9 @@ struct Frag<MODE, true> {
   __device__ inline void load_b(const char *buf, int l16, int kq, int kk) {
 #pragma unroll
     for (int ni = 0; ni < 9; ++ni) {
-      const char *bp = buf + (ni * 16 + l16) * LDS_ROW + (kk + 8 * kq) * 2;
+      const char *bp = buf + (ni * 16 + l16) * kLdsRow<MODE> + (kk + 8 * kq) * 2;
       bh[ni] = *(const V8 *)bp;
-      bl[ni] = *(const V8 *)(bp + 128);
+      bl[ni] = *(const V8 *)(bp + kChunkBytes<MODE> / 2);
     }
   }
   __device__ inline void mma(f4 (&acc)[WM][9], const char *, int, int, int) const {
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(64 * kWaves<MODE>) void contract_kernel(ContractArg
   constexpr int WM = M_::WM;
   using Acc = typename M_::Acc;
   using O = typename M_::O;
-  constexpr int BUF = BN * LDS_ROW;
+  constexpr int BUF = BN * kLdsRow<MODE>;
   constexpr int SPC = M_::KCH / M_::KSTEP;       // k-steps per staged chunk
   __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
 
