@@ -21,6 +21,8 @@
 // blocks of one column group, so a column group is fetched from HBM once and
 // reused from that XCD's L2 while the whole table stays resident in the
 // last-level cache.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace igamt {
@@ -45,7 +47,8 @@ struct ContractArgs {
   const float *Bscale;    // F16X3 inverse column scales [n_tiles_pad][9]
   void *out;              // [n_tiles][M][9]
   int64_t M, Kp, n_tiles;
-  int n_mblk, n_groups;
+  int n_mblk, n_groups;  // row blocks; groups of this launch
+  int64_t grp0;          // first group of this launch
 };
 
 template <int MODE>
@@ -262,9 +265,9 @@ __global__ __launch_bounds__(64 * kWaves<MODE>) void contract_kernel(ContractArg
 
   const int wg = blockIdx.x;
   const int xcd = wg & 7, local = wg >> 3;
-  const int64_t grp = (int64_t)(local / a.n_mblk) * 8 + xcd;
+  const int64_t grp = a.grp0 + (int64_t)(local / a.n_mblk) * 8 + xcd;
   const int mb = local % a.n_mblk;
-  if (grp >= a.n_groups) return;
+  if (grp >= a.grp0 + a.n_groups) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -377,7 +380,10 @@ __global__ __launch_bounds__(64 * kWaves<MODE>) void contract_kernel(ContractArg
   }
 }
 
-igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_coef, void *d_blocks, void *stream) {
+igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_coef, void *d_blocks, void *stream,
+                             int64_t g0, int64_t g1) {
+  if (g1 < 0) g1 = P->n_groups;
+  if (g0 < 0 || g1 > P->n_groups || g0 >= g1) { set_error("invalid tile group range"); return IGAMT_EINVAL; }
   if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
   ContractArgs a;
   const int64_t MK = P->Mp * P->Kp;
@@ -385,7 +391,8 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
   a.M = P->n_pairs;
   a.Kp = P->Kp;
   a.n_tiles = P->n_tiles;
-  a.n_groups = (int)P->n_groups;
+  a.n_groups = (int)(g1 - g0);
+  a.grp0 = g0;
   a.out = d_blocks;
   a.A2 = nullptr;
   a.B2 = nullptr;
@@ -412,7 +419,7 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
   const int bm = prec == IGAMT_F64 ? kBM<IGAMT_F64> : prec == IGAMT_F32 ? kBM<IGAMT_F32> : kBM<IGAMT_BF16X3>;
   if (P->Mp % bm != 0) { set_error("padded table rows are not a multiple of the row block"); return IGAMT_EINVAL; }
   a.n_mblk = (int)(P->Mp / bm);
-  const int64_t groups8 = (P->n_groups + 7) / 8 * 8;
+  const int64_t groups8 = (int64_t)(a.n_groups + 7) / 8 * 8;
   const dim3 grid((unsigned)(a.n_mblk * groups8));
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
@@ -451,6 +458,7 @@ igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *
   a.n_tiles = n_tiles;
   a.n_mblk = (int)(rows_pad / bm);
   a.n_groups = (int)n_groups;
+  a.grp0 = 0;
   const int64_t groups8 = (n_groups + 7) / 8 * 8;
   const dim3 grid((unsigned)(a.n_mblk * groups8));
   hipStream_t s = (hipStream_t)stream;
@@ -485,7 +493,37 @@ extern "C" igamt_status igamt_assemble(igamt_plan *P, double E, double nu, igamt
   char *ws = (char *)d_workspace;
   void *coef = ws;
   void *blocks = ws + coef_bytes(P, prec);
-  if ((st = launch_fit(P, E, nu, prec, coef, stream))) return st;
-  if ((st = launch_contract(P, prec, coef, blocks, stream))) return st;
-  return launch_scatter(P, prec, blocks, d_values, stream);
+  // Slab pipeline: the tile grid is cut into slabs of whole z-planes of tiles; fit and
+  // contraction run slab after slab on the caller's stream, and the scatter of slab k runs on
+  // the plan's second stream once slab k+1 is contracted (its owner records read the blocks of
+  // the next z-plane of tiles).  The memory-bound scatter then overlaps the MFMA-bound
+  // contraction.  Each kernel computes the same values in either order, so the result is the
+  // same bits as the serial path.
+  const int64_t plane = (int64_t)P->tiles[0] * P->tiles[1];
+  const int nz = P->tiles[2];
+  if (plane % kTileGroup != 0 || nz < 4 || P->n_tiles < 4096 || P->n_tiles != P->n_tiles_pad) {
+    if ((st = launch_fit(P, E, nu, prec, coef, stream))) return st;
+    if ((st = launch_contract(P, prec, coef, blocks, stream))) return st;
+    return launch_scatter(P, prec, blocks, d_values, stream);
+  }
+  if ((st = pipeline_resources(P))) return st;
+  hipStream_t s = (hipStream_t)stream, aux = (hipStream_t)P->dev.aux_stream;
+  const int per = (nz + 7) / 8;                 // z-planes per slab (at most 8 slabs)
+  const int n_slab = (nz + per - 1) / per;
+  auto slab_t0 = [&](int k) { return (int64_t)std::min(nz, k * per) * plane; };
+  for (int k = 0; k <= n_slab; ++k) {
+    if (k < n_slab) {
+      const int64_t t0 = slab_t0(k), t1 = slab_t0(k + 1);
+      if ((st = launch_fit(P, E, nu, prec, coef, stream, t0, t1))) return st;
+      if ((st = launch_contract(P, prec, coef, blocks, stream, t0 / kTileGroup, t1 / kTileGroup))) return st;
+      IGAMT_HIP(hipEventRecord((hipEvent_t)P->dev.events[k], s));
+    }
+    if (k >= 1) {   // scatter of slab k-1 after the contraction of slab k (or of the last slab)
+      IGAMT_HIP(hipStreamWaitEvent(aux, (hipEvent_t)P->dev.events[std::min(k, n_slab - 1)], 0));
+      if ((st = launch_scatter(P, prec, blocks, d_values, aux, slab_t0(k - 1), slab_t0(k)))) return st;
+    }
+  }
+  IGAMT_HIP(hipEventRecord((hipEvent_t)P->dev.events[16], aux));
+  IGAMT_HIP(hipStreamWaitEvent(s, (hipEvent_t)P->dev.events[16], 0));
+  return IGAMT_OK;
 }

@@ -27,6 +27,7 @@ struct FitArgs {
   double lam, mu;
   void *out;
   int64_t plane;        // n_tiles_pad * 9 * Kp elements per stored plane
+  int64_t t0;           // first tile of the launch
   int32_t *flag;
 };
 
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   __shared__ double colmax[64][9];
   __shared__ double scale[9];
   const int tid = threadIdx.x;
-  const int64_t t = blockIdx.x;
+  const int64_t t = a.t0 + blockIdx.x;
   const int64_t tbase = t * 9 * (int64_t)a.Kp;
 
   if (t >= a.n_tiles) {  // padding tile: zeros
@@ -192,7 +193,10 @@ int64_t blocks_bytes(const igamt_plan *P, igamt_precision prec) {
   return align256(P->n_tiles * P->n_pairs * 9 * (prec == IGAMT_F64 ? 8 : 4));
 }
 
-igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_coef, void *stream) {
+igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_coef, void *stream,
+                        int64_t t0, int64_t t1) {
+  if (t1 < 0) t1 = P->n_tiles_pad;
+  if (t0 < 0 || t1 > P->n_tiles_pad || t0 >= t1) { set_error("invalid tile range"); return IGAMT_EINVAL; }
   if (!(E > 0.0) || !std::isfinite(E) || !(nu > -1.0 && nu < 0.5)) {
     set_error("material constants must satisfy E > 0 and -1 < nu < 0.5");
     return IGAMT_EINVAL;
@@ -219,7 +223,8 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.plane = P->n_tiles_pad * 9 * (int64_t)P->Kp;
   a.flag = P->dev.flag;
   const size_t shm = (size_t)28 * P->n_fit * P->n_fit * P->n_fit * sizeof(double);
-  const dim3 grid((unsigned)P->n_tiles_pad), block(64);
+  a.t0 = t0;
+  const dim3 grid((unsigned)(t1 - t0)), block(64);
   hipStream_t s = (hipStream_t)stream;
   // all macro directions share one degree in the device evaluator
   if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {

@@ -68,6 +68,8 @@ struct DevicePtrs {
   int32_t *ctrl_tiles_off[3] = {nullptr, nullptr, nullptr};  // per macro ctrl index: tiles touching it
   int32_t *ctrl_tiles[3] = {nullptr, nullptr, nullptr};      // (tile, local offset) pairs
   int32_t *flag = nullptr;           // smallest degenerate tile index (INT32_MAX = none)
+  void *aux_stream = nullptr;        // second stream of the slab pipeline (hipStream_t, default priority)
+  void *events[17] = {};             // hipEvent_t: slab contractions done (16) and the pipeline's end
   // tables
   double *table = nullptr;           // [Mp][Kp] FP64, zero padded
   double *table_t = nullptr;         // [transposed_rows][Mp] FP64 (transposed, zero padded, for the adjoint)
@@ -134,14 +136,20 @@ igamt_status upload_macro_ctrl(igamt_plan *plan, const double *ctrl, int on_devi
 igamt_status derive_table_copies(igamt_plan *plan, void *stream, const int32_t *gate = nullptr);
 // synchronous upload of the host tile control points
 igamt_status upload_tile_ctrl(igamt_plan *plan);
+// the plan's second stream and events for the slab pipeline (created on first use)
+igamt_status pipeline_resources(igamt_plan *plan);
 // stage launchers (fit.hip, contract.hip, scatter.hip)
 int64_t coef_bytes(const igamt_plan *plan, igamt_precision prec);
 int64_t blocks_bytes(const igamt_plan *plan, igamt_precision prec);
-igamt_status launch_fit(igamt_plan *plan, double E, double nu, igamt_precision prec, void *d_coef, void *stream);
+// tile range [t0, t1) (t1 <= n_tiles_pad); t1 < 0 means all tiles
+igamt_status launch_fit(igamt_plan *plan, double E, double nu, igamt_precision prec, void *d_coef, void *stream,
+                        int64_t t0 = 0, int64_t t1 = -1);
+// tile groups [g0, g1) of kTileGroup tiles; g1 < 0 means all groups
 igamt_status launch_contract(igamt_plan *plan, igamt_precision prec, const void *d_coef, void *d_blocks,
-                             void *stream);
+                             void *stream, int64_t g0 = 0, int64_t g1 = -1);
+// owner records of the tiles [t0, t1); t1 < 0 means all tiles
 igamt_status launch_scatter(igamt_plan *plan, igamt_precision prec, const void *d_blocks, void *d_values,
-                            void *stream);
+                            void *stream, int64_t t0 = 0, int64_t t1 = -1);
 // C (rows x 9 n_tiles) = A (rows_pad x kdim, row-major) B (kdim per column, 9 n_tiles_pad columns),
 // written as out[t][row][ab] for row < rows; FP64 or FP32 operands (contract.hip)
 igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *B, void *out, int64_t rows,

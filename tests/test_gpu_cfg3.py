@@ -80,3 +80,21 @@ def test_cfg3_sampled_blocks_and_rows(case, prec):
         assert np.linalg.norm(got - rv) <= TOL[prec] * np.linalg.norm(rv)
     del vals, ws, blocks, rp, ci
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cfg3_pipelined_assembly_bit_identical(case, prec):
+    """igamt_assemble (fit/contraction and scatter of consecutive tile slabs on two streams) gives
+    the same bits as the three stages run one after the other on one stream."""
+    torch, P, w, plan, pairs, table, ref_table, sample = case
+    cb, bb = plan.workspace_bytes(prec)
+    ws = plan.workspace(prec)
+    v_pipe = plan.assemble(w.E, w.nu, prec, workspace=ws)
+    coef = ws
+    dt = torch.float64 if prec == "f64" else torch.float32
+    blocks = ws.view(torch.uint8)[cb:cb + bb].view(dt)
+    plan.fit(w.E, w.nu, prec, out=coef)
+    plan.contract(coef, prec, out=blocks)
+    v_serial = plan.scatter(blocks, prec)
+    torch.cuda.synchronize()
+    assert torch.equal(v_pipe, v_serial)
