@@ -96,6 +96,8 @@ struct Mode<IGAMT_F16X3> {
 template <int MODE>
 constexpr int kWaves = Mode<MODE>::NW;                // waves per workgroup
 template <int MODE>
+constexpr int kMinGroups = (MODE == IGAMT_BF16X3 || MODE == IGAMT_F16X3) ? 2 : 1;   // workgroups per CU
+template <int MODE>
 constexpr int kBM = 16 * Mode<MODE>::WM * Mode<MODE>::NW;   // table rows per workgroup
 template <int MODE>
 constexpr int kChunkBytes =   // bytes of one B column per staged chunk (split modes: hi then lo half)
@@ -215,11 +217,14 @@ struct Frag<MODE, false> {
 };
 template <int MODE>
 struct Frag<MODE, true> {
-  static constexpr bool JIT_B = false;
-  // lane holds 8 consecutive k (16 B) of the hi and lo planes; products lo*hi, hi*lo, hi*hi
+  // Split modes: lane holds 8 consecutive k (16 B) of the hi and lo planes; products lo*hi, hi*lo,
+  // hi*hi.  Only the A fragment is prefetched a k-step ahead; B fragments are read from LDS two
+  // column blocks at a time inside mma (the next pair while the current pair's MFMAs run), which
+  // keeps a wave within the 256 registers that leave the accumulators in VGPRs.
+  static constexpr bool JIT_B = true;
   using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
   static constexpr int WM = Mode<MODE>::WM;
-  V8 ah[WM], al[WM], bh[9], bl[9];
+  V8 ah[WM], al[WM];
   __device__ inline void load_a(const ContractArgs &a, int64_t row0, int l16, int kq, int64_t k) {
 #pragma unroll
     for (int mi = 0; mi < WM; ++mi) {
@@ -228,33 +233,44 @@ struct Frag<MODE, true> {
       al[mi] = *(const V8 *)((const uint16_t *)a.A2 + off);
     }
   }
-  __device__ inline void load_b(const char *buf, int l16, int kq, int kk) {
+  __device__ inline void load_b(const char *, int, int, int) {}
+  __device__ static inline void read_pair(const char *buf, int l16, int kq, int kk, int n0, V8 (&h)[2], V8 (&l)[2]) {
 #pragma unroll
-    for (int ni = 0; ni < 9; ++ni) {
+    for (int q = 0; q < 2; ++q) {
+      const int ni = min(n0 + q, 8);
       const char *bp = buf + (ni * 16 + l16) * kLdsRow<MODE> + (kk + 8 * kq) * 2;
-      bh[ni] = *(const V8 *)bp;
-      bl[ni] = *(const V8 *)(bp + kChunkBytes<MODE> / 2);
+      h[q] = *(const V8 *)bp;
+      l[q] = *(const V8 *)(bp + kChunkBytes<MODE> / 2);
     }
   }
-  __device__ inline void mma(f4 (&acc)[WM][9], const char *, int, int, int) const {
+  __device__ inline void mma(f4 (&acc)[WM][9], const char *buf, int l16, int kq, int kk) const {
+    V8 bh[2][2], bl[2][2];
+    read_pair(buf, l16, kq, kk, 0, bh[0], bl[0]);
 #pragma unroll
-    for (int pr = 0; pr < 3; ++pr)
+    for (int pi = 0; pi < 5; ++pi) {
+      if (pi + 1 < 5) read_pair(buf, l16, kq, kk, 2 * (pi + 1), bh[(pi + 1) & 1], bl[(pi + 1) & 1]);
 #pragma unroll
-      for (int mi = 0; mi < WM; ++mi)
+      for (int pr = 0; pr < 3; ++pr)
 #pragma unroll
-        for (int ni = 0; ni < 9; ++ni) {
-          const V8 &x = pr == 0 ? al[mi] : ah[mi];
-          const V8 &y = pr == 1 ? bl[ni] : bh[ni];
-          if constexpr (MODE == IGAMT_BF16X3)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[mi][ni], 0, 0, 0);
-          else
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[mi][ni], 0, 0, 0);
-        }
+        for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int ni = 2 * pi + q;
+            if (ni < 9) {
+              const V8 &x = pr == 0 ? al[mi] : ah[mi];
+              const V8 &y = pr == 1 ? bl[pi & 1][q] : bh[pi & 1][q];
+              if constexpr (MODE == IGAMT_BF16X3)
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[mi][ni], 0, 0, 0);
+              else
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc[mi][ni], 0, 0, 0);
+            }
+          }
+    }
   }
 };
 
 template <int MODE>
-__global__ __launch_bounds__(64 * kWaves<MODE>) void contract_kernel(ContractArgs a) {
+__global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_kernel(ContractArgs a) {
   using M_ = Mode<MODE>;
   constexpr int WM = M_::WM;
   using Acc = typename M_::Acc;
