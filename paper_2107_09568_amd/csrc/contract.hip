@@ -5,10 +5,11 @@
 // Layout: A row-major [Mp][Kp] and B column-major [n_tiles_pad*9][Kp], so both
 // operands are contiguous along k.  A workgroup owns 128 table rows x one group
 // of 16 tiles (144 columns).  Its waves split the rows: each wave owns WM 16-row
-// blocks x 144 columns (WM x 9 MFMA 16x16 blocks), WM = 1 with 8 waves for FP64
-// and FP32, WM = 2 with 4 waves for the split modes.  The FP64 shape keeps every
-// register of a wave within the 256 that leave the accumulators in VGPRs: the
-// FP64 MFMA runs about 2.3x slower when it accumulates in AGPRs.
+// blocks x 144 columns (WM x 9 MFMA 16x16 blocks), WM = 1 with 8 waves for FP64,
+// WM = 2 with 4 waves (two workgroups per CU) for FP32 and the split modes.  Every
+// shape keeps a wave within the 256 registers that leave the accumulators in
+// VGPRs: the FP64 MFMA runs about 2.3x slower, the BF16 one about 1.4x slower,
+// when it accumulates in AGPRs.
 //
 // B chunks (64 k values per column) are staged in LDS through registers, one chunk
 // ahead, into alternating buffers; each wave reads its A rows straight from
@@ -33,9 +34,6 @@ constexpr int BN = 144;                 // columns per workgroup (16 tiles x 9)
 #endif
 #ifndef KCH_F64
 #define KCH_F64 32
-#endif
-#ifndef NW_F32
-#define NW_F32 8
 #endif
 
 struct ContractArgs {
@@ -70,8 +68,8 @@ struct Mode<IGAMT_F32> {
   using Acc = f4;
   static constexpr int KCH = 64;
   static constexpr int KSTEP = 16;
-  static constexpr int WM = 1;
-  static constexpr int NW = NW_F32;
+  static constexpr int WM = 2;
+  static constexpr int NW = 4;
 };
 template <>
 struct Mode<IGAMT_BF16X3> {
@@ -96,7 +94,7 @@ struct Mode<IGAMT_F16X3> {
 template <int MODE>
 constexpr int kWaves = Mode<MODE>::NW;                // waves per workgroup
 template <int MODE>
-constexpr int kMinGroups = (MODE == IGAMT_BF16X3 || MODE == IGAMT_F16X3) ? 2 : 1;   // workgroups per CU
+constexpr int kMinGroups = MODE != IGAMT_F64 ? 2 : 1;   // workgroups per CU
 template <int MODE>
 constexpr int kBM = 16 * Mode<MODE>::WM * Mode<MODE>::NW;   // table rows per workgroup
 template <int MODE>
@@ -158,9 +156,9 @@ struct Frag;
 template <int MODE>
 struct Frag<MODE, false> {
   using E = typename Mode<MODE>::E;
-  // FP64 reads its B fragments from LDS inside mma (one k-slice ahead) instead of a whole k-step
-  // ahead: two full FP64 fragment sets do not fit the register file next to the accumulators.
-  static constexpr bool JIT_B = MODE == IGAMT_F64;
+  // B fragments are read from LDS inside mma (one k-slice ahead) instead of a whole k-step ahead:
+  // two full fragment sets do not fit the register file next to the accumulators.
+  static constexpr bool JIT_B = true;
   static constexpr int WM = Mode<MODE>::WM;
   E av[WM][4], bv[JIT_B ? 1 : 9][4];
   __device__ inline void load_a(const ContractArgs &a, int64_t row0, int l16, int kq, int64_t k) {
@@ -198,7 +196,12 @@ struct Frag<MODE, false> {
         for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
           for (int ni = 0; ni < 9; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+            {
+              if constexpr (MODE == IGAMT_F64)
+                acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+              else
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+            }
       }
     } else {
 #pragma unroll
