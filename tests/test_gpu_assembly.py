@@ -241,3 +241,43 @@ def test_csr_rows_cfg2(cfg2, torch):
         np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], cols)
         got = v[rp[r]:rp[r + 1]]
         assert np.linalg.norm(got - rv) <= 1e-12 * np.linalg.norm(rv)
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (1, 2, 3), (5, 1, 1)])
+def test_small_and_flat_tile_grids(P, torch, grid):
+    """A single tile (nothing shared, 15 padding tiles in the contraction), a 1x2x3 grid and a
+    5x1x1 row of tiles (sharing along one direction only), against the oracle's CSR."""
+    import dataclasses
+    w = dataclasses.replace(W.make("cfg4", n_boxes=1), tiles=grid)
+    oc = OracleCase(w)
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    rp, ci, v = assembly.assemble_csr(w, oc.pairs, oc.blocks)
+    for prec in ("f64", "f32"):
+        vals = plan.assemble(w.E, w.nu, prec)
+        plan.check()
+        err = np.linalg.norm(vals.double().cpu().numpy() - v) / np.linalg.norm(v)
+        _say(f"grid {grid} {prec} CSR rel err {err:.2e}")
+        assert err < TOL[prec]
+        assert torch.equal(vals, plan.assemble(w.E, w.nu, prec))
+
+
+def test_pipelined_assembly_partial_last_slab(P, torch):
+    """16x16x20 tiles: the assembly runs in slabs of 3 z-planes with a partial last slab; the
+    result equals the three stages run one after the other."""
+    import dataclasses
+    w = dataclasses.replace(W.make("cfg4", n_boxes=16), tiles=(16, 16, 20))
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    for prec in ("f64", "f32"):
+        cb, bb = plan.workspace_bytes(prec)
+        ws = plan.workspace(prec)
+        v_pipe = plan.assemble(w.E, w.nu, prec, workspace=ws)
+        dt = torch.float64 if prec == "f64" else torch.float32
+        blocks = ws.view(torch.uint8)[cb:cb + bb].view(dt)
+        plan.fit(w.E, w.nu, prec, out=ws)
+        plan.contract(ws, prec, out=blocks)
+        v_serial = plan.scatter(blocks, prec)
+        plan.check()
+        torch.cuda.synchronize()
+        assert torch.equal(v_pipe, v_serial)
