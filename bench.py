@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="cfg3", choices=sorted(WORKLOADS))
     ap.add_argument("--precisions", default="f64,f32,bf16x3,f16x3")
-    ap.add_argument("--cpu-tiles", type=int, default=1024)
+    ap.add_argument("--cpu-tiles", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient and learned-table sections")
     ap.add_argument("--copy-calibration", action="store_true",
