@@ -196,6 +196,28 @@ def bench_learned(torch, W, P, n_designs=32):
         t_est.append(time.perf_counter() - t0)
         fallbacks += int(gate_t.item())
     med = lambda x: float(np.median(x)) * 1e3
+    # a batch of designs: exact tables of all of them, against the batched learned path
+    # (one MLP forward, one reconstruction, exact check rows, exact tables where the gate is set)
+    p_all = W.family_params(w.extra["test_seed"], w.extra["n_test"])
+    c_all = torch.from_numpy(np.stack([np.ascontiguousarray(W.tile_family(p).ctrl).ravel() for p in p_all])).cuda()
+    out = plan.tables_build_batch(c_all)
+    tn.tables_for_batch(p_all, c_all)
+    t_bx, t_bl = [], []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.tables_build_batch(c_all, out=out)
+        torch.cuda.synchronize()
+        t_bx.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        tabs, err_b, gate_b = tn.tables_for_batch(p_all, c_all)
+        torch.cuda.synchronize()
+        t_bl.append(time.perf_counter() - t0)
+    batch_err = ((tabs - out).flatten(1).norm(dim=1) / out.flatten(1).norm(dim=1)).max().item()
+    batch = {"designs": len(p_all), "exact_ms": med(t_bx), "learned_with_estimate_ms": med(t_bl),
+             "speedup": med(t_bx) / med(t_bl), "fallbacks": int(gate_b.sum().item()),
+             "table_rel_err_max": batch_err}
+    del out, tabs
     return {"workload": "degree-2 3x3x3-element tile family (pinch, anisotropy x/y/z) ~ U(0,0.3)^4, "
                         "512 training / held-out designs, POD r=64, MLP 4-128-128-64 GELU",
             "designs_timed": len(p_test), "exact_table_ms": med(t_exact), "learned_table_ms": med(t_learn),
@@ -204,7 +226,7 @@ def bench_learned(torch, W, P, n_designs=32):
             "table_rel_err_max": float(max(errs)), "table_rel_err_median": float(np.median(errs)),
             "fallbacks": fallbacks, "offline_s": {"exact_tables_512": t_snap, "pod": t_pod,
                                                  "train_8000_steps": tn.train_seconds},
-            "final_loss": hist[-1][1]}
+            "final_loss": hist[-1][1], "batch": batch}
 
 
 def main():

@@ -285,6 +285,53 @@ igamt_status igamt_table_learned(igamt_plan *plan, const igamt_mlp_desc *desc, c
                                  int32_t n_rows, double *d_exact_rows, double tol, double *d_err,
                                  int32_t *d_gate, void *stream);
 
+/* --- batches of designs ----------------------------------------------------
+ * The same table steps for n_design designs of one tile family at once (same
+ * knots, degree and pair set as the plan's reference tile, different control
+ * points).  Tables of a batch are dense, d_tables double
+ * [n_design][n_pairs][n_cols]; the plan's own table is not touched.  Tile
+ * control points d_ctrl double [n_design][n_tile_ctrl][3] on the device; a
+ * boundary point off its Greville position is reported by igamt_check, as for
+ * igamt_set_tile_ctrl.  1 <= n_design <= 65535.  Scratch for the point records
+ * of the batch is allocated on the first call and grown when a larger batch
+ * needs it.
+ *
+ * Exact tables (eq. (52), as igamt_tables_build); with d_gate (int32
+ * [n_design], may be NULL) design b is built only when d_gate[b] != 0 and its
+ * table is left as it is otherwise.                                           */
+igamt_status igamt_tables_build_batch(igamt_plan *plan, const double *d_ctrl, int32_t n_design,
+                                      const int32_t *d_gate, double *d_tables, void *stream);
+/* Exact rows of each design's table (as igamt_tables_build_rows) into d_out
+ * double [n_design][n_rows][n_cols].                                          */
+igamt_status igamt_tables_build_rows_batch(igamt_plan *plan, const double *d_ctrl, int32_t n_design,
+                                           const int32_t *d_rows, int32_t n_rows, double *d_out, void *stream);
+/* POD reconstruction of n_design tables, tables[b][e] = mean[e] + sum_k
+ * basis[k][e] * coeff_scale * coeffs[b][k] (d_coeffs float [n_design][r]),
+ * bit-identical per design to igamt_table_from_pod.  d_coef_work: double
+ * scratch of igamt_pod_batch_work_doubles(r, n_design) elements.              */
+igamt_status igamt_tables_from_pod_batch(const igamt_plan *plan, const float *d_mean, const float *d_basis,
+                                         int32_t r, const float *d_coeffs, int32_t n_design, double coeff_scale,
+                                         double *d_coef_work, double *d_tables, void *stream);
+int64_t igamt_pod_batch_work_doubles(int32_t r, int32_t n_design);
+/* Per-design error and gate (as igamt_table_rows_check) of batch tables against
+ * exact rows d_exact double [n_design][n_rows][n_cols]; d_err double
+ * [n_design], d_gate int32 [n_design].                                        */
+igamt_status igamt_tables_rows_check_batch(const igamt_plan *plan, const double *d_tables, int32_t n_design,
+                                           const int32_t *d_rows, int32_t n_rows, const double *d_exact,
+                                           double tol, double *d_err, int32_t *d_gate, void *stream);
+/* The learned path for a batch: MLP forward with desc->batch = n_design
+ * designs (d_x float [n_design][n_in]), batched reconstruction into d_tables,
+ * exact check rows, per-design error and gate, and exact tables in place of
+ * the learned ones of the designs whose gate is set; nothing waits on the
+ * host.  d_exact_rows double [n_design][n_rows][n_cols], d_err / d_gate
+ * [n_design], d_coef_work as for igamt_tables_from_pod_batch.                 */
+igamt_status igamt_tables_learned_batch(igamt_plan *plan, const igamt_mlp_desc *desc, const float *d_params,
+                                        const float *d_x, float *d_act, float *d_y, const float *d_mean,
+                                        const float *d_basis, double coeff_scale, const double *d_ctrl,
+                                        const int32_t *d_rows, int32_t n_rows, double *d_exact_rows, double tol,
+                                        double *d_err, int32_t *d_gate, double *d_coef_work, double *d_tables,
+                                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -273,6 +273,58 @@ class Plan:
                                            _stream()))
         return err
 
+    # ---- batches of designs of the plan's tile family -------------------------------------
+    def _batch_ctrl(self, ctrls):
+        torch = _torch()
+        assert ctrls.is_cuda and ctrls.dtype == torch.float64 and ctrls.is_contiguous()
+        assert ctrls.numel() == ctrls.shape[0] * 3 * self.n_tile_ctrl
+        return int(ctrls.shape[0])
+
+    def tables_build_batch(self, ctrls, gate=None, out=None):
+        """Exact tables of a batch of designs (device tile control points [B, n_tile_ctrl, 3]) into
+        a dense [B, n_pairs, n_cols] tensor; with an int32 gate [B], only designs with gate != 0."""
+        torch = _torch()
+        B = self._batch_ctrl(ctrls)
+        if out is None:
+            out = torch.empty((B, self.n_pairs, self.n_cols), dtype=torch.float64, device="cuda")
+        if gate is not None:
+            assert gate.is_cuda and gate.dtype == torch.int32 and gate.numel() == B
+        check(lib().igamt_tables_build_batch(self._h, _ptr(ctrls), B, None if gate is None else _ptr(gate),
+                                             _ptr(out), _stream()))
+        return out
+
+    def tables_build_rows_batch(self, ctrls, rows):
+        torch = _torch()
+        B = self._batch_ctrl(ctrls)
+        rows = rows.to(device="cuda", dtype=torch.int32).contiguous()
+        out = torch.empty((B, rows.numel(), self.n_cols), dtype=torch.float64, device="cuda")
+        check(lib().igamt_tables_build_rows_batch(self._h, _ptr(ctrls), B, _ptr(rows), int(rows.numel()), _ptr(out),
+                                                  _stream()))
+        return out
+
+    def tables_from_pod_batch(self, mean, basis, coeffs, scale=1.0, out=None):
+        torch = _torch()
+        coeffs = coeffs.contiguous()
+        B, r = int(coeffs.shape[0]), int(basis.shape[0])
+        work = torch.empty(lib().igamt_pod_batch_work_doubles(r, B), dtype=torch.float64, device="cuda")
+        if out is None:
+            out = torch.empty((B, self.n_pairs, self.n_cols), dtype=torch.float64, device="cuda")
+        check(lib().igamt_tables_from_pod_batch(self._h, _ptr(mean), _ptr(basis), r, _ptr(coeffs), B, float(scale),
+                                                _ptr(work), _ptr(out), _stream()))
+        return out
+
+    def tables_rows_check_batch(self, tables, rows, exact_rows, tol):
+        """Per-design (relative error on the rows [B], int32 gate [B]), left on the device."""
+        torch = _torch()
+        B = int(tables.shape[0])
+        rows = rows.to(device="cuda", dtype=torch.int32).contiguous()
+        err = torch.empty(B, dtype=torch.float64, device="cuda")
+        gate = torch.empty(B, dtype=torch.int32, device="cuda")
+        check(lib().igamt_tables_rows_check_batch(self._h, _ptr(tables.contiguous()), B, _ptr(rows),
+                                                  int(rows.numel()), _ptr(exact_rows.contiguous()), float(tol),
+                                                  _ptr(err), _ptr(gate), _stream()))
+        return err, gate
+
 
 def spmv(row_ptr, col_idx, values, x, out=None):
     torch = _torch()

@@ -66,6 +66,13 @@ SIGNATURES = {
     "igamt_table_rows_check": (status, [vp, vp, i32, vp, f64, vp, vp, vp]),
     "igamt_table_learned": (status, [vp, C.POINTER(MlpDesc), vp, vp, vp, vp, vp, vp, f64, vp, i32, vp, f64, vp, vp,
                                      vp]),
+    "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
+    "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),
+    "igamt_tables_from_pod_batch": (status, [vp, vp, vp, i32, vp, i32, f64, vp, vp, vp]),
+    "igamt_pod_batch_work_doubles": (i64, [i32, i32]),
+    "igamt_tables_rows_check_batch": (status, [vp, vp, i32, vp, i32, vp, f64, vp, vp, vp]),
+    "igamt_tables_learned_batch": (status, [vp, C.POINTER(MlpDesc), vp, vp, vp, vp, vp, vp, f64, vp, vp, i32, vp,
+                                            f64, vp, vp, vp, vp, vp]),
     "igamt_mlp_n_params": (i64, [C.POINTER(MlpDesc)]),
     "igamt_mlp_forward": (status, [C.POINTER(MlpDesc), vp, vp, vp, vp, vp]),
     "igamt_mse_loss": (status, [C.POINTER(MlpDesc), vp, vp, vp, vp, vp]),

@@ -79,6 +79,7 @@ struct DevicePtrs {
   uint16_t *table_h = nullptr;       // hi then lo, scaled rows
   float *table_h_scale = nullptr;    // [Mp] inverse row scale
   double *point_data = nullptr;      // table builder scratch
+  double *batch_points = nullptr;    // point records of batched designs (grown on demand)
 };
 
 }  // namespace igamt
@@ -121,6 +122,7 @@ struct igamt_plan {
   std::vector<int32_t> ctrl_tiles_off[3], ctrl_tiles[3];
   // state
   bool tables_ready = false;
+  int64_t batch_points_cap = 0;       // doubles allocated in dev.batch_points
   igamt::DevicePtrs dev;
 };
 

@@ -210,16 +210,60 @@ __global__ __launch_bounds__(256) void pod_reconstruct_kernel(const float *__res
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n_e) return;
   double v = mean[e];
-  for (int k = 0; k < r; ++k) v += (double)basis[(int64_t)k * n_e + e] * cs[k];
+  for (int k = 0; k < r; ++k) v += (double)basis[(int64_t)k * n_e + e] * cs[k];   // same form as the batch kernel
   const int64_t p = e / K, col = e - p * K;
   table[p * Kp + col] = v;
 }
 
+// Scaled coefficients of a batch, transposed and padded: cd[k][b] = scale * c[b][k] for b < B,
+// 0 for B <= b < Bp.
+__global__ __launch_bounds__(256) void pod_coeffs_kernel(const float *__restrict__ c, int B, int Bp, int r,
+                                                         double scale, double *__restrict__ cd) {
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= r * Bp) return;
+  const int k = id / Bp, b = id - k * Bp;
+  cd[id] = b < B ? scale * (double)c[(int64_t)b * r + k] : 0.0;
+}
+
+// tables[b][e] = mean[e] + sum_k basis[k][e] cd[k][b] for a group of DB designs per thread:
+// every basis value is loaded once per group and the coefficients, uniform over the
+// workgroup, come through scalar loads.  The per-design sum runs over k in ascending order,
+// exactly as the one-design kernel, so both give the same table bit for bit.
+template <int DB>
+__global__ __launch_bounds__(256) void pod_reconstruct_batch_kernel(const float *__restrict__ mean,
+                                                                    const float *__restrict__ basis, int r,
+                                                                    const double *__restrict__ cd, int B, int Bp,
+                                                                    int n_groups, int64_t n_e,
+                                                                    double *__restrict__ tables) {
+  const int g = blockIdx.x % n_groups;
+  const int64_t e = (int64_t)(blockIdx.x / n_groups) * 256 + threadIdx.x;
+  if (e >= n_e) return;
+  const double m = mean[e];
+  double v[DB];
+#pragma unroll
+  for (int d = 0; d < DB; ++d) v[d] = m;
+  const double *cg = cd + g * DB;
+  for (int k = 0; k < r; ++k) {
+    const double x = (double)basis[(int64_t)k * n_e + e];
+    const double *ck = cg + (int64_t)k * Bp;
+#pragma unroll
+    for (int d = 0; d < DB; ++d) v[d] += x * ck[d];
+  }
+#pragma unroll
+  for (int d = 0; d < DB; ++d)
+    if (g * DB + d < B) tables[(int64_t)(g * DB + d) * n_e + e] = v[d];
+}
+
+// Relative Frobenius error of listed table rows against exact rows; one workgroup per design
+// (grid x), with per-design strides of the table and of the exact rows.
 __global__ __launch_bounds__(256) void rows_error_kernel(const double *__restrict__ table, int64_t Kp, int K,
                                                          const int32_t *__restrict__ rows, int n_rows, int64_t n_pairs,
                                                          const double *__restrict__ exact, double *__restrict__ err,
-                                                         double tol, int32_t *__restrict__ gate) {
+                                                         double tol, int32_t *__restrict__ gate,
+                                                         int64_t table_dstride) {
   __shared__ double num[256], den[256];
+  table += blockIdx.x * table_dstride;
+  exact += (int64_t)blockIdx.x * n_rows * K;
   double a = 0.0, b = 0.0;
   for (int64_t i = threadIdx.x; i < (int64_t)n_rows * K; i += 256) {
     const int64_t rr = i / K, c = i % K;
@@ -238,8 +282,8 @@ __global__ __launch_bounds__(256) void rows_error_kernel(const double *__restric
   }
   if (threadIdx.x == 0) {
     const double e = sqrt(num[0] / den[0]);
-    err[0] = e;
-    if (gate) gate[0] = e <= tol ? 0 : 1;   // NaN (bad row, empty reference) also asks for the exact table
+    err[blockIdx.x] = e;
+    if (gate) gate[blockIdx.x] = e <= tol ? 0 : 1;   // NaN (bad row, empty reference) also asks for the exact table
   }
 }
 
@@ -435,7 +479,7 @@ extern "C" igamt_status igamt_table_rows_error(const igamt_plan *P, const int32_
   if (!P || !d_rows || !d_exact || !d_err || n_rows < 1) { set_error("invalid argument"); return IGAMT_EINVAL; }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
   hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
-                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, 0.0, nullptr);
+                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, 0.0, nullptr, 0);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
@@ -449,7 +493,7 @@ extern "C" igamt_status igamt_table_rows_check(const igamt_plan *P, const int32_
   }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
   hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
-                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate);
+                     P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate, 0);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
@@ -552,4 +596,78 @@ extern "C" igamt_status igamt_table_learned(igamt_plan *P, const igamt_mlp_desc 
   if ((st = igamt_tables_build_rows(P, d_rows, n_rows, d_exact_rows, stream))) return st;
   if ((st = igamt_table_rows_check(P, d_rows, n_rows, d_exact_rows, tol, d_err, d_gate, stream))) return st;
   return igamt_tables_build_gated(P, d_gate, stream);
+}
+
+// ---- batches of designs ------------------------------------------------------------------
+static constexpr int kPodGroup = 16;   // designs per thread in the batched reconstruction
+
+extern "C" igamt_status igamt_tables_from_pod_batch(const igamt_plan *P, const float *d_mean, const float *d_basis,
+                                                    int32_t r, const float *d_coeffs, int32_t n_design,
+                                                    double coeff_scale, double *d_coef_work, double *d_tables,
+                                                    void *stream) {
+  if (!P || !d_mean || !d_basis || !d_coeffs || !d_coef_work || !d_tables || r < 1 || r > 256 || n_design < 1) {
+    set_error("invalid argument");
+    return IGAMT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int n_groups = (n_design + kPodGroup - 1) / kPodGroup, Bp = n_groups * kPodGroup;
+  const int64_t n_e = P->n_pairs * P->K;
+  hipLaunchKernelGGL(pod_coeffs_kernel, dim3(blocks_for((int64_t)r * Bp)), dim3(256), 0, s, d_coeffs, n_design, Bp, r,
+                     coeff_scale, d_coef_work);
+  IGAMT_LAUNCH_CHECK();
+  const int64_t nb = (int64_t)blocks_for(n_e) * n_groups;
+  if (nb > 0x7fffffffLL) { set_error("batch too large for one launch"); return IGAMT_EINVAL; }
+  hipLaunchKernelGGL(pod_reconstruct_batch_kernel<kPodGroup>, dim3((unsigned)nb), dim3(256), 0, s, d_mean, d_basis,
+                     r, d_coef_work, n_design, Bp, n_groups, n_e, d_tables);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+extern "C" int64_t igamt_pod_batch_work_doubles(int32_t r, int32_t n_design) {
+  if (r < 1 || n_design < 1) return -1;
+  return (int64_t)r * ((n_design + kPodGroup - 1) / kPodGroup) * kPodGroup;
+}
+
+extern "C" igamt_status igamt_tables_rows_check_batch(const igamt_plan *P, const double *d_tables, int32_t n_design,
+                                                      const int32_t *d_rows, int32_t n_rows, const double *d_exact,
+                                                      double tol, double *d_err, int32_t *d_gate, void *stream) {
+  if (!P || !d_tables || !d_rows || !d_exact || !d_err || !d_gate || n_rows < 1 || n_design < 1 ||
+      !(tol >= 0.0)) {
+    set_error("invalid argument");
+    return IGAMT_EINVAL;
+  }
+  hipLaunchKernelGGL(rows_error_kernel, dim3((unsigned)n_design), dim3(256), 0, (hipStream_t)stream, d_tables,
+                     (int64_t)P->K, P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate,
+                     P->n_pairs * P->K);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_tables_build_batch(igamt_plan *P, const double *d_ctrl, int32_t n_design,
+                                                 const int32_t *d_gate, double *d_tables, void *stream);
+extern "C" igamt_status igamt_tables_build_rows_batch(igamt_plan *P, const double *d_ctrl, int32_t n_design,
+                                                      const int32_t *d_rows, int32_t n_rows, double *d_out,
+                                                      void *stream);
+
+extern "C" igamt_status igamt_tables_learned_batch(igamt_plan *P, const igamt_mlp_desc *mlp, const float *d_params,
+                                                   const float *d_x, float *d_act, float *d_y, const float *d_mean,
+                                                   const float *d_basis, double coeff_scale, const double *d_ctrl,
+                                                   const int32_t *d_rows, int32_t n_rows, double *d_exact_rows,
+                                                   double tol, double *d_err, int32_t *d_gate, double *d_coef_work,
+                                                   double *d_tables, void *stream) {
+  if (!P || !mlp || !d_params || !d_x || !d_act || !d_y || !d_mean || !d_basis || !d_ctrl || !d_rows ||
+      !d_exact_rows || !d_err || !d_gate || !d_coef_work || !d_tables) {
+    set_error("NULL argument");
+    return IGAMT_EINVAL;
+  }
+  const int32_t B = mlp->batch;
+  igamt_status st;
+  if ((st = igamt_mlp_forward(mlp, d_params, d_x, d_act, d_y, stream))) return st;
+  if ((st = igamt_tables_from_pod_batch(P, d_mean, d_basis, mlp->widths[mlp->n_layers], d_y, B, coeff_scale,
+                                        d_coef_work, d_tables, stream)))
+    return st;
+  if ((st = igamt_tables_build_rows_batch(P, d_ctrl, B, d_rows, n_rows, d_exact_rows, stream))) return st;
+  if ((st = igamt_tables_rows_check_batch(P, d_tables, B, d_rows, n_rows, d_exact_rows, tol, d_err, d_gate, stream)))
+    return st;
+  return igamt_tables_build_batch(P, d_ctrl, B, d_gate, d_tables, stream);
 }

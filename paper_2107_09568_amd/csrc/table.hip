@@ -23,18 +23,21 @@ struct TableArgs {
   int64_t stride;        // doubles per point record
   double *pts;
   int32_t *flag;
-  const int32_t *gate;   // optional: do nothing unless *gate != 0
+  const int32_t *gate;   // optional: do nothing unless gate[design] != 0
+  int64_t ctrl_stride;   // batched designs (grid y): control points and point records per design
+  int64_t pts_stride;
 };
 
 template <int PT>
 __global__ __launch_bounds__(64) void table_points_kernel(TableArgs a) {
-  if (a.gate && *a.gate == 0) return;
+  if (a.gate && a.gate[blockIdx.y] == 0) return;
   const int G = a.ng * a.ng * a.ng;
   const int64_t id = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int64_t nE = (int64_t)a.eT[0] * a.eT[1] * a.eT[2];
   if (id >= nE * G) return;
   const int64_t e = id / G;
   const int g = (int)(id % G);
+  const double *ctrl = a.ctrl + blockIdx.y * a.ctrl_stride;
   const int ei[3] = {(int)(e % a.eT[0]), (int)((e / a.eT[0]) % a.eT[1]), (int)(e / ((int64_t)a.eT[0] * a.eT[1]))};
   const int gi[3] = {g % a.ng, (g / a.ng) % a.ng, g / (a.ng * a.ng)};
   double N[3][PT + 1], dN[3][PT + 1];
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(64) void table_points_kernel(TableArgs a) {
 #pragma unroll
       for (int rx = 0; rx <= PT; ++rx) {
         const int64_t A = (ei[0] + rx) + (int64_t)a.nT[0] * ((ei[1] + ry) + (int64_t)a.nT[1] * (ei[2] + rz));
-        const double *c = a.ctrl + 3 * A;
+        const double *c = ctrl + 3 * A;
         const double R = N[0][rx] * N[1][ry] * N[2][rz];
         const double d0 = dN[0][rx] * N[1][ry] * N[2][rz];
         const double d1 = N[0][rx] * dN[1][ry] * N[2][rz];
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(64) void table_points_kernel(TableArgs a) {
   double F[3][3];
   const double D = inv3(J, F);
   if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag + 1, (int32_t)e);
-  double *out = a.pts + id * a.stride;
+  double *out = a.pts + blockIdx.y * a.pts_stride + id * a.stride;
   out[0] = w * D;
   double B[3][kMaxQ + 1];
 #pragma unroll
@@ -102,21 +105,23 @@ struct TableSumArgs {
   const double *pts;
   double *out;
   int64_t out_stride;    // doubles per output row
-  const int32_t *gate;   // optional: do nothing unless *gate != 0
+  const int32_t *gate;   // optional: do nothing unless gate[design] != 0
+  int64_t pts_stride;    // batched designs (grid y): point records and output per design
+  int64_t out_dstride;
 };
 
 // One thread per table entry (row, C, ij): the sum over the shared micro elements and their
 // Gauss points runs in ascending element and point order, so every entry is bitwise
 // reproducible and the same whether the whole table or a row subset is built.
 __global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
-  if (a.gate && *a.gate == 0) return;
+  if (a.gate && a.gate[blockIdx.y] == 0) return;
   const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (id >= a.n_rows * a.npi * 9) return;
   const int ij = (int)(id % 9), i = ij / 3, j = ij - 3 * i;
   const int C = (int)((id / 9) % a.npi);
   const int64_t row = id / (9 * (int64_t)a.npi);
   const int64_t p = a.rows ? a.rows[row] : row;
-  double *o = a.out + row * a.out_stride + 9 * C + ij;
+  double *o = a.out + blockIdx.y * a.out_dstride + row * a.out_stride + 9 * C + ij;
   if (p < 0 || p >= a.n_pairs) {  // invalid row index: flag the output instead of reading out of bounds
     *o = __builtin_nan("");
     return;
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
         const int64_t e = ex + (int64_t)a.eT[0] * (ey + (int64_t)a.eT[1] * ez);
         const int la = (ai[0] - ex) + p1 * ((ai[1] - ey) + p1 * (ai[2] - ez));
         const int lb = (bi[0] - ex) + p1 * ((bi[1] - ey) + p1 * (bi[2] - ez));
-        const double *pd = a.pts + e * G * a.stride;
+        const double *pd = a.pts + blockIdx.y * a.pts_stride + e * G * a.stride;
         for (int g = 0; g < G; ++g, pd += a.stride) {
           const double wn = pd[0] * pd[1 + C];
           const double ga = wn * pd[1 + a.npi + 3 * la + i];
@@ -181,6 +186,8 @@ static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride, co
   a.pts = P->dev.point_data;
   a.flag = P->dev.flag;
   a.gate = gate;
+  a.ctrl_stride = 0;
+  a.pts_stride = 0;
   const dim3 grid((unsigned)((nE * G + 63) / 64)), block(64);
   switch (P->pT[0]) {
     case 1: hipLaunchKernelGGL(table_points_kernel<1>, grid, block, 0, s, a); break;
@@ -200,6 +207,8 @@ static TableSumArgs sum_args(const igamt_plan *P, int64_t stride) {
   b.pairs = P->dev.pairs;
   b.rows = nullptr;
   b.gate = nullptr;
+  b.pts_stride = 0;
+  b.out_dstride = 0;
   b.n_rows = P->n_pairs;
   b.n_pairs = P->n_pairs;
   for (int k = 0; k < 3; ++k) {
@@ -265,4 +274,119 @@ extern "C" igamt_status igamt_tables_build_rows(igamt_plan *P, const int32_t *d_
   hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
+}
+
+// ---- batched designs -------------------------------------------------------------------
+static __global__ void tile_boundary_batch_kernel(const double *__restrict__ ctrl, int64_t n_design, const double *grev,
+                                                  int nx, int ny, int nz, int32_t *flag) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (id >= n * n_design) return;
+  const int64_t pt = id % n;
+  const int i = (int)(pt % nx), j = (int)((pt / nx) % ny), k = (int)(pt / ((int64_t)nx * ny));
+  if (!(i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1)) return;
+  const double *c = ctrl + 3 * id;
+  const double e = fabs(c[0] - grev[i]) + fabs(c[1] - grev[nx + j]) + fabs(c[2] - grev[nx + ny + k]);
+  if (!(e <= 1e-12)) atomicMin(flag + 2, (int32_t)pt);
+}
+
+// Point records of n_design designs (tile control points d_ctrl [n_design][n_tile_ctrl][3])
+// into dev.batch_points, grown on demand; designs with gate[b] == 0 are skipped.
+static igamt_status run_points_batch(igamt_plan *P, hipStream_t s, const double *d_ctrl, int32_t n_design,
+                                     const int32_t *gate, int64_t &stride, int64_t &per) {
+  if (P->pT[0] != P->pT[1] || P->pT[0] != P->pT[2]) {
+    set_error("reference tiles with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  const int G = P->n_gauss * P->n_gauss * P->n_gauss;
+  const int64_t nE = (int64_t)P->eT[0] * P->eT[1] * P->eT[2];
+  const int nact = (P->pT[0] + 1) * (P->pT[1] + 1) * (P->pT[2] + 1);
+  stride = 1 + P->npi + 3 * nact;
+  per = nE * G * stride;
+  if (P->batch_points_cap < per * n_design) {
+    if (P->dev.batch_points) IGAMT_HIP(hipFree(P->dev.batch_points));
+    P->dev.batch_points = nullptr;
+    P->batch_points_cap = 0;
+    IGAMT_HIP(hipMalloc((void **)&P->dev.batch_points, per * n_design * sizeof(double)));
+    P->batch_points_cap = per * n_design;
+  }
+  hipLaunchKernelGGL(tile_boundary_batch_kernel, dim3((unsigned)((P->nTt * n_design + 255) / 256)), dim3(256), 0, s,
+                     d_ctrl, (int64_t)n_design, P->dev.tile_grev, P->nT[0], P->nT[1], P->nT[2], P->dev.flag);
+  IGAMT_LAUNCH_CHECK();
+  TableArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.knots[k] = P->dev.tile_knots[k];
+    a.nT[k] = P->nT[k];
+    a.eT[k] = P->eT[k];
+  }
+  a.ctrl = d_ctrl;
+  a.gx = P->dev.gauss_x;
+  a.gw = P->dev.gauss_w;
+  a.ng = P->n_gauss;
+  a.q = P->q;
+  a.npi = P->npi;
+  a.stride = stride;
+  a.pts = P->dev.batch_points;
+  a.flag = P->dev.flag;
+  a.gate = gate;
+  a.ctrl_stride = 3 * P->nTt;
+  a.pts_stride = per;
+  const dim3 grid((unsigned)((nE * G + 63) / 64), (unsigned)n_design), block(64);
+  switch (P->pT[0]) {
+    case 1: hipLaunchKernelGGL(table_points_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(table_points_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(table_points_kernel<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(table_points_kernel<4>, grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(table_points_kernel<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(table_points_kernel<6>, grid, block, 0, s, a); break;
+    default: set_error("unsupported tile degree"); return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+static igamt_status sum_batch(igamt_plan *P, hipStream_t s, int32_t n_design, const int32_t *gate,
+                              const int32_t *d_rows, int32_t n_rows, double *d_out, int64_t stride, int64_t per) {
+  TableSumArgs b = sum_args(P, stride);
+  b.pts = P->dev.batch_points;
+  b.pts_stride = per;
+  b.gate = gate;
+  b.rows = d_rows;
+  b.n_rows = d_rows ? n_rows : P->n_pairs;
+  b.out = d_out;
+  b.out_stride = P->K;
+  b.out_dstride = b.n_rows * P->K;
+  const int64_t n = b.n_rows * P->npi * 9;
+  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n_design), dim3(256), 0, s, b);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_tables_build_batch(igamt_plan *P, const double *d_ctrl, int32_t n_design,
+                                                 const int32_t *d_gate, double *d_tables, void *stream) {
+  if (!P || !d_ctrl || !d_tables || n_design <= 0 || n_design > 65535) {
+    set_error("invalid argument");
+    return IGAMT_EINVAL;
+  }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t stride = 0, per = 0;
+  if ((st = run_points_batch(P, s, d_ctrl, n_design, d_gate, stride, per))) return st;
+  return sum_batch(P, s, n_design, d_gate, nullptr, 0, d_tables, stride, per);
+}
+
+extern "C" igamt_status igamt_tables_build_rows_batch(igamt_plan *P, const double *d_ctrl, int32_t n_design,
+                                                      const int32_t *d_rows, int32_t n_rows, double *d_out,
+                                                      void *stream) {
+  if (!P || !d_ctrl || !d_rows || !d_out || n_rows <= 0 || n_design <= 0 || n_design > 65535) {
+    set_error("invalid argument");
+    return IGAMT_EINVAL;
+  }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t stride = 0, per = 0;
+  if ((st = run_points_batch(P, s, d_ctrl, n_design, nullptr, stride, per))) return st;
+  return sum_batch(P, s, n_design, nullptr, d_rows, n_rows, d_out, stride, per);
 }

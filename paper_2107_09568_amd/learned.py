@@ -198,10 +198,11 @@ class TableNet:
         """Exact FP64 tables of the given designs (device table builder), shape (n, n_e)."""
         torch = _torch()
         out = torch.empty((len(tile_ctrls), self.n_e), dtype=torch.float64, device="cuda")
-        for i, c in enumerate(tile_ctrls):
-            self.plan.set_tile_ctrl(c)
-            self.plan.tables_build()
-            out[i] = self.plan.tables_get().view(-1)
+        chunk = 64
+        for i in range(0, len(tile_ctrls), chunk):
+            c = np.stack([np.ascontiguousarray(t, dtype=np.float64) for t in tile_ctrls[i:i + chunk]])
+            c = torch.from_numpy(c.reshape(len(c), -1)).cuda()
+            self.plan.tables_build_batch(c, out=out[i:i + len(c)])
         self.plan.check()
         return out
 
@@ -255,6 +256,33 @@ class TableNet:
                                         _ptr(b["exact_rows"]), float(self.tol), _ptr(b["err"]), _ptr(b["gate"]),
                                         _stream()))
         return b["err"], b["gate"]
+
+    def tables_for_batch(self, params, tile_ctrls):
+        """Tables of a batch of designs (params [B, 4], tile control points as a device float64
+        tensor [B, n_tile_ctrl, 3]) into a dense [B, n_pairs, n_cols] tensor: one MLP forward over
+        the batch, one reconstruction that reads the POD basis once per group of designs, exact
+        check rows of every design, and exact tables for the designs whose estimated error
+        exceeds the tolerance, all queued on the stream.  Returns (tables, estimated relative
+        errors [B] float64, fallback flags [B] int32), all on the device."""
+        torch = _torch()
+        B = int(tile_ctrls.shape[0])
+        assert tile_ctrls.is_cuda and tile_ctrls.dtype == torch.float64 and tile_ctrls.is_contiguous()
+        rows = self._buffers()["rows"]
+        x = self.scale_inputs(np.atleast_2d(params))
+        assert x.shape[0] == B
+        self.mlp.set_batch(B)
+        r = self.rank
+        work = torch.empty(lib().igamt_pod_batch_work_doubles(r, B), dtype=torch.float64, device="cuda")
+        exact_rows = torch.empty((B, rows.numel(), self.plan.n_cols), dtype=torch.float64, device="cuda")
+        err = torch.empty(B, dtype=torch.float64, device="cuda")
+        gate = torch.empty(B, dtype=torch.int32, device="cuda")
+        tables = torch.empty((B, self.plan.n_pairs, self.plan.n_cols), dtype=torch.float64, device="cuda")
+        check(lib().igamt_tables_learned_batch(self.plan._h, C.byref(self.mlp.desc), _ptr(self.mlp.params), _ptr(x),
+                                               _ptr(self.mlp.act), _ptr(self.mlp.y), _ptr(self.mean),
+                                               _ptr(self.basis), float(self.coeff_scale), _ptr(tile_ctrls),
+                                               _ptr(rows), int(rows.numel()), _ptr(exact_rows), float(self.tol),
+                                               _ptr(err), _ptr(gate), _ptr(work), _ptr(tables), _stream()))
+        return tables, err, gate
 
     def table_for(self, p, tile_ctrl, force_exact=False):
         """Put the table of design p (tile control points tile_ctrl) into the plan.

@@ -196,3 +196,83 @@ def test_device_tile_ctrl_and_gated_build(env):
         plan.check()
     plan.set_tile_ctrl(ctrl_d)
     plan.check()
+
+
+# ---- batches of designs -------------------------------------------------------------------
+def _family_ctrls(torch, params):
+    c = np.stack([np.ascontiguousarray(W.tile_family(p).ctrl, dtype=np.float64) for p in params])
+    return torch.from_numpy(c.reshape(len(c), -1)).cuda()
+
+
+def test_batch_exact_tables_bit_identical(env):
+    """Exact tables of a batch of designs equal, bit for bit, the one-design builds; the gate
+    leaves the designs it switches off untouched; batch check rows are rows of the batch tables."""
+    torch, P, L = env
+    w = W.make("cfg5")
+    plan = P.Plan.from_workload(w)
+    params = W.family_params(77, 5)
+    ctrls = _family_ctrls(torch, params)
+    _say(f"batch exact tables: {len(params)} designs of the degree-2 tile family")
+    got = plan.tables_build_batch(ctrls)
+    for b in range(len(params)):
+        plan.set_tile_ctrl(ctrls[b])
+        plan.tables_build()
+        assert torch.equal(got[b], plan.tables_get()), b
+    plan.check()
+    gate = torch.tensor([1, 0, 1, 0, 0], dtype=torch.int32, device="cuda")
+    out = torch.full_like(got, 7.0)
+    plan.tables_build_batch(ctrls, gate=gate, out=out)
+    for b in range(len(params)):
+        assert torch.equal(out[b], got[b] if b in (0, 2) else torch.full_like(got[b], 7.0)), b
+    rows = torch.tensor([0, 5, 17, plan.n_pairs - 1, 5], dtype=torch.int32, device="cuda")
+    er = plan.tables_build_rows_batch(ctrls, rows)
+    assert torch.equal(er, got[:, rows.long()])
+    # a design whose boundary point moved is reported
+    bad = ctrls.clone()
+    bad[3, 0] += 0.01
+    plan.tables_build_batch(bad)
+    with pytest.raises(P.IgamtError, match="Greville"):
+        plan.check()
+
+
+def test_batch_pod_and_check_bit_identical(env):
+    """Batched reconstruction (ragged over the 16-design groups) and per-design row checks equal
+    the one-design kernels bit for bit."""
+    torch, P, L = env
+    w = W.make("cfg1")
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    n_e = plan.n_pairs * plan.n_cols
+    g = torch.Generator().manual_seed(5)
+    r, B = 24, 37
+    mean = torch.randn(n_e, generator=g).float().cuda()
+    basis = torch.randn((r, n_e), generator=g).float().cuda()
+    coeffs = torch.randn((B, r), generator=g).float().cuda()
+    _say(f"batch POD reconstruction: {B} designs, r={r}, {n_e} entries")
+    tabs = plan.tables_from_pod_batch(mean, basis, coeffs, 0.37)
+    rows = torch.arange(0, plan.n_pairs, 3, dtype=torch.int32, device="cuda")
+    exact = plan.tables_build_rows(rows)
+    exact_b = exact.unsqueeze(0).expand(B, -1, -1).contiguous()
+    err_b, gate_b = plan.tables_rows_check_batch(tabs, rows, exact_b, 1.5)
+    for b in range(B):
+        plan.table_from_pod(mean, basis, coeffs[b], 0.37)
+        assert torch.equal(tabs[b], plan.tables_get()), b
+        err, gate = plan.table_rows_check(rows, exact, 1.5)
+        assert torch.equal(err, err_b[b:b + 1]) and torch.equal(gate, gate_b[b:b + 1]), b
+
+
+def test_learned_batch_matches_per_design(family):
+    """The batched learned path gives every design the table, error estimate and fallback
+    decision of the one-design path, bit for bit."""
+    torch, P, L, w, plan, tn, p_test = family
+    params = np.concatenate([p_test[:20], np.array([[0.6, 0.6, 0.1, 0.55]])])   # the last one falls back
+    ctrls = _family_ctrls(torch, params)
+    tabs, err_b, gate_b = tn.tables_for_batch(params, ctrls)
+    assert int(gate_b[-1].item()) == 1
+    for b, p in enumerate(params):
+        err, gate = tn.table_for_async(p, W.tile_family(p).ctrl)
+        assert torch.equal(tabs[b], plan.tables_get()), b
+        assert torch.equal(err, err_b[b:b + 1]) and torch.equal(gate, gate_b[b:b + 1]), b
+    plan.check()
+    _say(f"learned batch: {len(params)} designs, {int(gate_b.sum())} fallbacks, "
+         f"estimated err max over learned {err_b[gate_b == 0].max().item():.2e}")
