@@ -98,6 +98,8 @@ constexpr int kMinGroups = MODE != IGAMT_F64 ? 2 : 1;   // workgroups per CU
 template <int MODE>
 constexpr int kBM = 16 * Mode<MODE>::WM * Mode<MODE>::NW;   // table rows per workgroup
 template <int MODE>
+constexpr bool kPersist = MODE == IGAMT_F64;   // one workgroup per CU: a persistent loop over items
+template <int MODE>
 constexpr int kChunkBytes =   // bytes of one B column per staged chunk (split modes: hi then lo half)
     Mode<MODE>::KCH * ((MODE == IGAMT_F64 || MODE == IGAMT_F32) ? (int)sizeof(typename Mode<MODE>::E) : 4);
 template <int MODE>
@@ -155,12 +157,11 @@ template <int MODE, bool SPLIT = (MODE == IGAMT_BF16X3 || MODE == IGAMT_F16X3)>
 struct Frag;
 template <int MODE>
 struct Frag<MODE, false> {
+  // A is prefetched a k-step ahead; B fragments are read from LDS inside mma, one k-slice ahead:
+  // two whole fragment sets do not fit the register file next to the accumulators.
   using E = typename Mode<MODE>::E;
-  // B fragments are read from LDS inside mma (one k-slice ahead) instead of a whole k-step ahead:
-  // two full fragment sets do not fit the register file next to the accumulators.
-  static constexpr bool JIT_B = true;
   static constexpr int WM = Mode<MODE>::WM;
-  E av[WM][4], bv[JIT_B ? 1 : 9][4];
+  E av[WM][4];
   __device__ inline void load_a(const ContractArgs &a, int64_t row0, int l16, int kq, int64_t k) {
 #pragma unroll
     for (int mi = 0; mi < WM; ++mi) {
@@ -169,52 +170,27 @@ struct Frag<MODE, false> {
       for (int s = 0; s < 4; ++s) av[mi][s] = src[s];
     }
   }
-  __device__ inline void load_b(const char *buf, int l16, int kq, int kk) {
-    if constexpr (!JIT_B) {
-#pragma unroll
-      for (int ni = 0; ni < 9; ++ni) {
-        const E *bp = (const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) bv[ni][s] = bp[s];
-      }
-    }
-  }
   // consecutive MFMAs update different accumulators (18 apart)
   __device__ inline void mma(typename Mode<MODE>::Acc (&acc)[WM][9], const char *buf, int l16, int kq, int kk) const {
-    if constexpr (JIT_B) {
-      E b[2][9];
+    E b[2][9];
 #pragma unroll
-      for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq);
+    for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        if (s + 1 < 4) {
+    for (int s = 0; s < 4; ++s) {
+      if (s + 1 < 4) {
 #pragma unroll
-          for (int ni = 0; ni < 9; ++ni)
-            b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq + s + 1);
-        }
-#pragma unroll
-        for (int mi = 0; mi < WM; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 9; ++ni)
-            {
-              if constexpr (MODE == IGAMT_F64)
-                acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
-              else
-                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
-            }
+        for (int ni = 0; ni < 9; ++ni)
+          b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq + s + 1);
       }
-    } else {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-        for (int mi = 0; mi < WM; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 9; ++ni) {
-            if constexpr (MODE == IGAMT_F64)
-              acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
-            else
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], bv[ni][s], acc[mi][ni], 0, 0, 0);
-          }
+        for (int ni = 0; ni < 9; ++ni) {
+          if constexpr (MODE == IGAMT_F64)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+          else
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+        }
     }
   }
 };
@@ -224,7 +200,6 @@ struct Frag<MODE, true> {
   // hi*hi.  Only the A fragment is prefetched a k-step ahead; B fragments are read from LDS two
   // column blocks at a time inside mma (the next pair while the current pair's MFMAs run), which
   // keeps a wave within the 256 registers that leave the accumulators in VGPRs.
-  static constexpr bool JIT_B = true;
   using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
   static constexpr int WM = Mode<MODE>::WM;
   V8 ah[WM], al[WM];
@@ -236,7 +211,6 @@ struct Frag<MODE, true> {
       al[mi] = *(const V8 *)((const uint16_t *)a.A2 + off);
     }
   }
-  __device__ inline void load_b(const char *, int, int, int) {}
   __device__ static inline void read_pair(const char *buf, int l16, int kq, int kk, int n0, V8 (&h)[2], V8 (&l)[2]) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -282,121 +256,171 @@ __global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_
   constexpr int SPC = M_::KCH / M_::KSTEP;       // k-steps per staged chunk
   __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
 
+  // Work items (row block mb, column group grp).  Item l of XCD x is (grp0 + 8 (l / n_mblk) + x,
+  // l % n_mblk): consecutive items of one XCD take all row blocks of one column group, which is
+  // then fetched from HBM once and reused from that XCD's L2.  Workgroup w runs items
+  // l = w / 8, w / 8 + S, w / 8 + 2 S, ... of XCD w % 8 (S = workgroups per XCD): one item each
+  // when the grid covers all items, or a persistent loop over items (FP64, one workgroup per CU),
+  // where the first B chunks and A fragment of the next item are loaded during the last k-steps
+  // of the current one and the epilogue's stores, so the item boundary costs no load latency.
   const int wg = blockIdx.x;
-  const int xcd = wg & 7, local = wg >> 3;
-  const int64_t grp = a.grp0 + (int64_t)(local / a.n_mblk) * 8 + xcd;
-  const int mb = local % a.n_mblk;
-  if (grp >= a.grp0 + a.n_groups) return;
+  const int xcd = wg & 7, slot = wg >> 3, n_slots = (int)(gridDim.x >> 3);
+  const int64_t groups_x = a.n_groups > xcd ? (a.n_groups - xcd + 7) / 8 : 0;   // groups of this XCD
+  const int64_t n_local = groups_x * a.n_mblk;
+  int64_t l = slot;
+  if (l >= n_local) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
   constexpr int BM = kBM<MODE>;
-  const int64_t row0 = (int64_t)mb * BM + wave * 16 * WM;
   const int n_chunks = (int)(a.Kp / M_::KCH);
-
-  Acc acc[WM][9];
-#pragma unroll
-  for (int mi = 0; mi < WM; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 9; ++ni) acc[mi][ni] = Acc{0, 0, 0, 0};
+  auto item_grp = [&](int64_t li) { return a.grp0 + (li / a.n_mblk) * 8 + xcd; };
+  auto item_mb = [&](int64_t li) { return (int)(li % a.n_mblk); };
 
   // Software pipeline: B chunks go global -> registers -> LDS one chunk ahead into alternating
-  // buffers (one barrier per chunk); the A fragment (and, except for FP64, the B fragment) of
-  // k-step t+1 is loaded while the MFMAs of k-step t run.
+  // buffers (one barrier per chunk); the A fragment of k-step t+1 is loaded while the MFMAs of
+  // k-step t run.  The chunk stream runs on across items: chunk c of an item sits in buffer
+  // (c + par) & 1, where par flips after every item when the chunk count is odd.
   using F = Frag<MODE>;
-  constexpr bool JIT = F::JIT_B;
   u32x4 pre[kPre<MODE>];
+  F f[2];
+  int64_t grp = item_grp(l);
+  int mb = item_mb(l);
+  int par = 0;
   load_chunk_regs<MODE>(a, grp, 0, tid, pre);
   store_chunk_lds<MODE>(lds, tid, pre);
   if (n_chunks > 1) load_chunk_regs<MODE>(a, grp, M_::KCH, tid, pre);
-  F f[2];
-  f[0].load_a(a, row0, l16, kq, 0);
-  if constexpr (!JIT) {
-    lds_barrier();
-    f[0].load_b(lds, l16, kq, 0);
-  }
+  f[0].load_a(a, (int64_t)mb * BM + wave * 16 * WM, l16, kq, 0);
 
-  // The loop body has no data-dependent branches (the compiler then tracks the outstanding loads
-  // exactly): prefetches past the last chunk re-read the last valid chunk and are not used.
-  const int64_t k_last = a.Kp - M_::KSTEP;
-  for (int c = 0; c < n_chunks; ++c) {
-    const char *cur = lds + (c & 1) * BUF;
-    char *nxt = lds + ((c + 1) & 1) * BUF;
-    const int64_t c2 = (int64_t)min(c + 2, n_chunks - 1) * M_::KCH;
-    if constexpr (JIT) {
+  constexpr int NW = kWaves<MODE>, WR = 16 * WM, NT = 64 * NW;
+  for (;;) {
+    const int64_t row0 = (int64_t)mb * BM + wave * 16 * WM;
+    const int64_t ln = l + n_slots;
+    const bool has_next = kPersist<MODE> && ln < n_local;
+    const int64_t grp_n = has_next ? item_grp(ln) : grp;
+    const int64_t row0_n = has_next ? (int64_t)item_mb(ln) * BM + wave * 16 * WM : row0;
+
+    Acc acc[WM][9];
+#pragma unroll
+    for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 9; ++ni) acc[mi][ni] = Acc{0, 0, 0, 0};
+
+    // The loop body has no data-dependent branches (the compiler then tracks the outstanding
+    // loads exactly): past the last chunk the prefetches read the next item's first chunks and A
+    // fragment, or, after the last item, re-read the last chunk (unused).
+    const int64_t k_last = a.Kp - M_::KSTEP;
+    for (int c = 0; c < n_chunks; ++c) {
+      const char *cur = lds + ((c + par) & 1) * BUF;
+      char *nxt = lds + ((c + 1 + par) & 1) * BUF;
+      const bool into_next = c + 2 >= n_chunks && has_next;
+      const int64_t g2 = into_next ? grp_n : grp;
+      const int64_t c2 = (int64_t)(into_next ? c + 2 - n_chunks : min(c + 2, n_chunks - 1)) * M_::KCH;
       // chunk c is visible and every wave has finished reading chunk c-1, whose buffer is refilled
       lds_barrier();
       store_chunk_lds<MODE>(nxt, tid, pre);
-      load_chunk_regs<MODE>(a, grp, c2, tid, pre);
-    }
+      load_chunk_regs<MODE>(a, g2, c2, tid, pre);
 #pragma unroll
-    for (int s = 0; s < SPC; ++s) {
-      const int64_t k = (int64_t)c * M_::KCH + s * M_::KSTEP;
-      F &now = f[s & 1], &next = f[(s + 1) & 1];
-      if (s + 1 < SPC) {
-        next.load_a(a, row0, l16, kq, k + M_::KSTEP);
-        next.load_b(cur, l16, kq, (s + 1) * M_::KSTEP);
-      } else {
-        if constexpr (!JIT) {
-          // every wave has passed the previous barrier, after its last read of chunk c-1
-          store_chunk_lds<MODE>(nxt, tid, pre);
-          load_chunk_regs<MODE>(a, grp, c2, tid, pre);
-          lds_barrier();
-          next.load_b(nxt, l16, kq, 0);
+      for (int s = 0; s < SPC; ++s) {
+        const int64_t k = (int64_t)c * M_::KCH + s * M_::KSTEP;
+        F &now = f[s & 1], &next = f[(s + 1) & 1];
+        if (s + 1 < SPC) {
+          next.load_a(a, row0, l16, kq, k + M_::KSTEP);
+        } else {
+          const bool last = c + 1 == n_chunks;
+          next.load_a(a, last ? row0_n : row0, l16, kq, last ? (has_next ? 0 : k_last) : k + M_::KSTEP);
         }
-        next.load_a(a, row0, l16, kq, min(k + M_::KSTEP, k_last));
+        // keep the prefetches ahead of this k-step's MFMAs (the scheduler would otherwise sink
+        // them towards their first use in the next k-step)
+        __builtin_amdgcn_sched_barrier(0);
+        now.mma(acc, cur, l16, kq, s * M_::KSTEP);
       }
-      // keep the prefetches ahead of this k-step's MFMAs (the scheduler would otherwise sink them
-      // towards their first use in the next k-step)
-      __builtin_amdgcn_sched_barrier(0);
-      now.mma(acc, cur, l16, kq, s * M_::KSTEP);
+      if constexpr (SPC % 2 == 1) f[0] = f[1];
     }
-    if constexpr (SPC % 2 == 1) f[0] = f[1];
-  }
 
-  // Epilogue.  Lane holds C[row][col l16] of each 16x16 block with row = 4 kq + r for the
-  // FP32-accumulating instructions and row = kq + 4 r for the FP64 one (measured layouts).
-  // The waves' tiles are transposed through LDS, several consecutive waves per round, so that
-  // each tile's rows x 9 values (contiguous in the block array) are written as whole lines.
-  constexpr int NW = kWaves<MODE>, WR = 16 * WM, NT = 64 * NW;
-  constexpr int PER_ROUND = (int)(sizeof(lds) / (WR * 144 * sizeof(O))) < NW
-                                ? (int)(sizeof(lds) / (WR * 144 * sizeof(O))) : NW;   // waves per round
-  constexpr int RR = PER_ROUND * WR;                                             // rows per round
-  O *out = (O *)a.out;
-  O *stage = (O *)lds;
-  for (int w0 = 0; w0 < NW; w0 += PER_ROUND) {
-    __syncthreads();
-    if (wave >= w0 && wave < w0 + PER_ROUND) {
-      const int rbase = (wave - w0) * WR;
+    // Epilogue.  Lane holds C[row][col l16] of each 16x16 block with row = 4 kq + r for the
+    // FP32-accumulating instructions and row = kq + 4 r for the FP64 one (measured layouts).
+    // The waves' tiles are transposed through LDS (in the item loop only through the buffer of
+    // the last chunk: the other one already holds the next item's first chunk), several
+    // consecutive waves per round, so that each tile's rows x 9 values (contiguous in the block
+    // array) are written as whole lines.
+    constexpr int STAGE = kPersist<MODE> ? BUF : 2 * BUF;   // LDS bytes the epilogue may use
+    constexpr int PER_ROUND = (int)(STAGE / (WR * 144 * sizeof(O))) < NW ? (int)(STAGE / (WR * 144 * sizeof(O))) : NW;
+    constexpr int RR = PER_ROUND * WR;   // rows per round
+    static_assert(PER_ROUND >= 1 && NW % PER_ROUND == 0, "epilogue rounds");
+    O *out = (O *)a.out;
+    O *stage = (O *)(kPersist<MODE> ? lds + ((n_chunks - 1 + par) & 1) * BUF : lds);
+#pragma unroll 1
+    for (int w0 = 0; w0 < NW; w0 += PER_ROUND) {
+      __syncthreads();
+      if (wave >= w0 && wave < w0 + PER_ROUND) {
+        const int rbase = (wave - w0) * WR;
 #pragma unroll
-      for (int ni = 0; ni < 9; ++ni) {
-        const int n = ni * 16 + l16;
-        const int tl = n / 9, ab = n - 9 * tl;
-        float cs = 1.0f;
-        if constexpr (MODE == IGAMT_F16X3) cs = a.Bscale[(grp * 16 + tl) * 9 + ab];
+        for (int ni = 0; ni < 9; ++ni) {
+          const int n = ni * 16 + l16;
+          const int tl = n / 9, ab = n - 9 * tl;
+          float cs = 1.0f;
+          if constexpr (MODE == IGAMT_F16X3) cs = a.Bscale[(grp * 16 + tl) * 9 + ab];
 #pragma unroll
-        for (int mi = 0; mi < WM; ++mi)
+          for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ml = mi * 16 + (MODE == IGAMT_F64 ? kq + 4 * r : 4 * kq + r);
-            O v = (O)acc[mi][ni][r];
-            if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[mb * BM + wave * WR + ml] * cs);
-            stage[(tl * RR + rbase + ml) * 9 + ab] = v;
+            for (int r = 0; r < 4; ++r) {
+              const int ml = mi * 16 + (MODE == IGAMT_F64 ? kq + 4 * r : 4 * kq + r);
+              O v = (O)acc[mi][ni][r];
+              if constexpr (MODE == IGAMT_F16X3) v = v * (a.Ascale[mb * BM + wave * WR + ml] * cs);
+              stage[(tl * RR + rbase + ml) * 9 + ab] = v;
+            }
+        }
+      }
+      __syncthreads();
+      const int64_t r0 = (int64_t)mb * BM + w0 * WR;
+      const int rows = (int)min((int64_t)RR, a.M - r0);
+      if (rows > 0) {
+        if constexpr (kPersist<MODE>) {
+          // a fixed number of stores per thread, so that the next item's prefetches (issued before
+          // them) are waited for with an exact count instead of after every store has completed
+          constexpr int PER_T = (16 * RR * 9 + NT - 1) / NT;
+          O *base = out + (grp * 16 * a.M + r0) * 9;                     // tile grp * 16, row r0
+          const int n_tl = (int)min((int64_t)16, a.n_tiles - grp * 16);   // tiles of this group
+          const int tstride = (int)(a.M * 9);
+#pragma unroll
+          for (int it = 0; it < PER_T; ++it) {
+            const int e = tid + it * NT;
+            const int tl = e / (RR * 9), jj = e - RR * 9 * tl;
+            if (e < 16 * RR * 9 && tl < n_tl && jj < rows * 9) base[tl * tstride + jj] = stage[e];
           }
+        } else {
+          for (int e = tid; e < 16 * RR * 9; e += NT) {
+            const int tl = e / (RR * 9), jj = e - RR * 9 * tl;
+            const int64_t t = grp * 16 + tl;
+            if (t < a.n_tiles && jj < rows * 9) out[(t * a.M + r0) * 9 + jj] = stage[tl * RR * 9 + jj];
+          }
+        }
       }
     }
-    __syncthreads();
-    const int64_t r0 = (int64_t)mb * BM + w0 * WR;
-    const int rows = (int)min((int64_t)RR, a.M - r0);
-    if (rows > 0) {
-      for (int e = tid; e < 16 * RR * 9; e += NT) {
-        const int tl = e / (RR * 9), jj = e - RR * 9 * tl;
-        const int64_t t = grp * 16 + tl;
-        if (t < a.n_tiles && jj < rows * 9) out[(t * a.M + r0) * 9 + jj] = stage[tl * RR * 9 + jj];
-      }
-    }
+    if (!has_next) break;
+    l = ln;
+    grp = grp_n;
+    mb = item_mb(ln);
+    par ^= n_chunks & 1;
   }
+}
+
+// Grid of the contraction: 8 x (items of the busiest XCD) workgroups, one item each, or for
+// FP64 (one workgroup per CU) a persistent grid of one workgroup per CU, each looping over items.
+static unsigned contract_grid(igamt_precision prec, const ContractArgs &a) {
+  const int64_t items_x = (int64_t)(a.n_groups + 7) / 8 * a.n_mblk;
+  int64_t slots = items_x;
+  if (prec == IGAMT_F64 && kPersist<IGAMT_F64> && a.Kp / Mode<IGAMT_F64>::KCH >= 2) {   // two chunks per item
+    static int cus[64] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int &n = cus[dev & 63];
+    if (n == 0 && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 256;
+    slots = std::min<int64_t>(items_x, std::max(1, n / 8));
+  }
+  return (unsigned)(8 * slots);
 }
 
 igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_coef, void *d_blocks, void *stream,
@@ -438,8 +462,7 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
   const int bm = prec == IGAMT_F64 ? kBM<IGAMT_F64> : prec == IGAMT_F32 ? kBM<IGAMT_F32> : kBM<IGAMT_BF16X3>;
   if (P->Mp % bm != 0) { set_error("padded table rows are not a multiple of the row block"); return IGAMT_EINVAL; }
   a.n_mblk = (int)(P->Mp / bm);
-  const int64_t groups8 = (int64_t)(a.n_groups + 7) / 8 * 8;
-  const dim3 grid((unsigned)(a.n_mblk * groups8));
+  const dim3 grid(contract_grid(prec, a));
   hipStream_t s = (hipStream_t)stream;
   switch (prec) {
     case IGAMT_F64: hipLaunchKernelGGL(contract_kernel<IGAMT_F64>, grid, dim3(64 * kWaves<IGAMT_F64>), 0, s, a); break;
@@ -478,8 +501,7 @@ igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *
   a.n_mblk = (int)(rows_pad / bm);
   a.n_groups = (int)n_groups;
   a.grp0 = 0;
-  const int64_t groups8 = (n_groups + 7) / 8 * 8;
-  const dim3 grid((unsigned)(a.n_mblk * groups8));
+  const dim3 grid(contract_grid(prec, a));
   hipStream_t s = (hipStream_t)stream;
   if (prec == IGAMT_F64)
     hipLaunchKernelGGL(contract_kernel<IGAMT_F64>, grid, dim3(64 * kWaves<IGAMT_F64>), 0, s, a);

@@ -120,13 +120,14 @@ def test_device_csr_structure_cfg1(cfg1, torch):
     np.testing.assert_array_equal(ci_d.cpu().numpy(), ci)
 
 
-def test_stage_entry_points_compose(cfg1, torch):
-    """fit -> contract -> scatter through the stage entry points equals assemble."""
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_stage_entry_points_compose(cfg1, torch, prec):
+    """fit -> contract -> scatter through the stage entry points equals assemble bit for bit."""
     w, oc, plan = cfg1
-    coef = plan.fit(w.E, w.nu, "f64")
-    blocks = plan.contract(coef, "f64")
-    vals = plan.scatter(blocks, "f64")
-    ref = plan.assemble(w.E, w.nu, "f64")
+    coef = plan.fit(w.E, w.nu, prec)
+    blocks = plan.contract(coef, prec)
+    vals = plan.scatter(blocks, prec)
+    ref = plan.assemble(w.E, w.nu, prec)
     torch.cuda.synchronize()
     assert torch.equal(vals, ref)
 
@@ -253,23 +254,26 @@ def test_small_and_flat_tile_grids(P, torch, grid):
     plan = P.Plan.from_workload(w)
     plan.tables_build()
     rp, ci, v = assembly.assemble_csr(w, oc.pairs, oc.blocks)
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "bf16x3"):
         vals = plan.assemble(w.E, w.nu, prec)
         plan.check()
         err = np.linalg.norm(vals.double().cpu().numpy() - v) / np.linalg.norm(v)
         _say(f"grid {grid} {prec} CSR rel err {err:.2e}")
         assert err < TOL[prec]
         assert torch.equal(vals, plan.assemble(w.E, w.nu, prec))
+        assert torch.equal(vals, plan.scatter(plan.contract(plan.fit(w.E, w.nu, prec), prec), prec))
 
 
-def test_pipelined_assembly_partial_last_slab(P, torch):
-    """16x16x20 tiles: the assembly runs in slabs of 3 z-planes with a partial last slab; the
-    result equals the three stages run one after the other."""
+@pytest.mark.parametrize("tiles", [(16, 16, 20), (7, 5, 3)])
+def test_assembly_equals_stages(P, torch, tiles):
+    """16x16x20 tiles (the slab pipeline, slabs of 3 z-planes with a partial last slab) and 7x5x3
+    (a partial last tile group, no pipeline): assemble equals the three stages run one after the
+    other, bit for bit."""
     import dataclasses
-    w = dataclasses.replace(W.make("cfg4", n_boxes=16), tiles=(16, 16, 20))
+    w = dataclasses.replace(W.make("cfg4", n_boxes=16), tiles=tiles)
     plan = P.Plan.from_workload(w)
     plan.tables_build()
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "bf16x3", "f16x3"):
         cb, bb = plan.workspace_bytes(prec)
         ws = plan.workspace(prec)
         v_pipe = plan.assemble(w.E, w.nu, prec, workspace=ws)

@@ -82,7 +82,7 @@ def test_cfg3_sampled_blocks_and_rows(case, prec):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
 def test_cfg3_pipelined_assembly_bit_identical(case, prec):
     """igamt_assemble (fit/contraction and scatter of consecutive tile slabs on two streams) gives
     the same bits as the three stages run one after the other on one stream."""
