@@ -79,8 +79,7 @@ def time_stages(torch, plan, w, prec, steps, warmup, ws):
     wall = time.perf_counter() - t0
     plan.check()
     st = np.array([[ev[s][i].elapsed_time(ev[s][i + 1]) for i in range(3)] for s in range(steps)])
-    # the step proper: igamt_assemble, which overlaps the scatter of one slab of tiles with the
-    # contraction of the next (a second stream inside the library; joined on this stream)
+    # the step proper: igamt_assemble (the three stages in one call)
     for _ in range(warmup):
         plan.assemble(w.E, w.nu, prec, values=vals, workspace=ws)
     torch.cuda.synchronize()

@@ -182,13 +182,10 @@ igamt_status igamt_contract(igamt_plan *plan, igamt_precision prec, const void *
  * pair: [p][3a+b]; lower: [p(B,A)][3b+a]).  d_values double (F64) or float. */
 igamt_status igamt_scatter(igamt_plan *plan, igamt_precision prec, const void *d_blocks,
                            void *d_values, void *stream);
-/* All three stages; d_workspace must hold coef_bytes + blocks_bytes (256-byte
- * aligned sub-buffers, coef first).  On large tile grids the scatter of one
- * slab of z-planes of tiles runs on a second stream of the plan (default
- * priority) while the next slab is fitted and contracted; the call joins it
- * back into `stream`, so work queued on `stream` afterwards sees the finished
- * CSR values, and the result is bitwise the same as the three stages in turn.
- * Calls on one plan from different streams must be ordered by the caller.     */
+/* All three stages in turn on `stream`; d_workspace must hold coef_bytes +
+ * blocks_bytes (256-byte aligned sub-buffers, coef first).  The result is
+ * bitwise the same as the three stage calls.  Calls on one plan from
+ * different streams must be ordered by the caller.                            */
 igamt_status igamt_assemble(igamt_plan *plan, double E, double nu, igamt_precision prec,
                             void *d_values, void *d_workspace, void *stream);
 /* Synchronises the stream and reports a degenerate tile seen since the last

@@ -99,6 +99,10 @@ template <int MODE>
 constexpr int kBM = 16 * Mode<MODE>::WM * Mode<MODE>::NW;   // table rows per workgroup
 template <int MODE>
 constexpr bool kPersist = MODE == IGAMT_F64;   // one workgroup per CU: a persistent loop over items
+#ifndef IGAMT_SUPER
+#define IGAMT_SUPER 8
+#endif
+constexpr int kSuper = IGAMT_SUPER;            // column groups per super-group of the item order
 template <int MODE>
 constexpr int kChunkBytes =   // bytes of one B column per staged chunk (split modes: hi then lo half)
     Mode<MODE>::KCH * ((MODE == IGAMT_F64 || MODE == IGAMT_F32) ? (int)sizeof(typename Mode<MODE>::E) : 4);
@@ -148,9 +152,6 @@ __device__ inline void store_chunk_lds(char *lds, int tid, const u32x4 (&r)[kPre
   }
 }
 
-// Wait for this wave's LDS operations, then synchronise the workgroup.  Unlike __syncthreads this
-// does not wait for outstanding global loads, so the register prefetches stay in flight.
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Operand fragments of one k-step of one wave: 2 row blocks of A (global) and 9 column blocks of B (LDS).
 template <int MODE, bool SPLIT = (MODE == IGAMT_BF16X3 || MODE == IGAMT_F16X3)>
@@ -256,9 +257,8 @@ __global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_
   constexpr int SPC = M_::KCH / M_::KSTEP;       // k-steps per staged chunk
   __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
 
-  // Work items (row block mb, column group grp).  Item l of XCD x is (grp0 + 8 (l / n_mblk) + x,
-  // l % n_mblk): consecutive items of one XCD take all row blocks of one column group, which is
-  // then fetched from HBM once and reused from that XCD's L2.  Workgroup w runs items
+  // Work items (row block mb, column group grp): the column groups grp0 + 8 j + x belong to XCD x
+  // and are visited in the order below.  Workgroup w runs items
   // l = w / 8, w / 8 + S, w / 8 + 2 S, ... of XCD w % 8 (S = workgroups per XCD): one item each
   // when the grid covers all items, or a persistent loop over items (FP64, one workgroup per CU),
   // where the first B chunks and A fragment of the next item are loaded during the last k-steps
@@ -275,8 +275,20 @@ __global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_
   const int l16 = lane & 15, kq = lane >> 4;
   constexpr int BM = kBM<MODE>;
   const int n_chunks = (int)(a.Kp / M_::KCH);
-  auto item_grp = [&](int64_t li) { return a.grp0 + (li / a.n_mblk) * 8 + xcd; };
-  auto item_mb = [&](int64_t li) { return (int)(li % a.n_mblk); };
+  // Items of an XCD in super-groups of kSuper column groups: row block after row block, each over
+  // the super-group's column groups, so that the XCD's L2 holds the B columns of the super-group
+  // and the A rows of the few row blocks in flight at once (instead of the whole table streaming
+  // through it for every column group).
+  auto item_grp = [&](int64_t li) {
+    const int64_t sg = li / (kSuper * a.n_mblk), rem = li - sg * kSuper * a.n_mblk;
+    const int64_t width = min((int64_t)kSuper, groups_x - sg * kSuper);
+    return a.grp0 + (sg * kSuper + rem % width) * 8 + xcd;
+  };
+  auto item_mb = [&](int64_t li) {
+    const int64_t sg = li / (kSuper * a.n_mblk), rem = li - sg * kSuper * a.n_mblk;
+    const int64_t width = min((int64_t)kSuper, groups_x - sg * kSuper);
+    return (int)(rem / width);
+  };
 
   // Software pipeline: B chunks go global -> registers -> LDS one chunk ahead into alternating
   // buffers (one barrier per chunk); the A fragment of k-step t+1 is loaded while the MFMAs of
@@ -353,7 +365,9 @@ __global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_
     O *stage = (O *)(kPersist<MODE> ? lds + ((n_chunks - 1 + par) & 1) * BUF : lds);
 #pragma unroll 1
     for (int w0 = 0; w0 < NW; w0 += PER_ROUND) {
-      __syncthreads();
+      // LDS-only barriers: the stage is the only shared data, and a full __syncthreads would also
+      // wait for the previous round's global stores and the next item's prefetches
+      lds_barrier();
       if (wave >= w0 && wave < w0 + PER_ROUND) {
         const int rbase = (wave - w0) * WR;
 #pragma unroll
@@ -373,7 +387,7 @@ __global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_
             }
         }
       }
-      __syncthreads();
+      lds_barrier();
       const int64_t r0 = (int64_t)mb * BM + w0 * WR;
       const int rows = (int)min((int64_t)RR, a.M - r0);
       if (rows > 0) {
@@ -534,37 +548,10 @@ extern "C" igamt_status igamt_assemble(igamt_plan *P, double E, double nu, igamt
   char *ws = (char *)d_workspace;
   void *coef = ws;
   void *blocks = ws + coef_bytes(P, prec);
-  // Slab pipeline: the tile grid is cut into slabs of whole z-planes of tiles; fit and
-  // contraction run slab after slab on the caller's stream, and the scatter of slab k runs on
-  // the plan's second stream once slab k+1 is contracted (its owner records read the blocks of
-  // the next z-plane of tiles).  The memory-bound scatter then overlaps the MFMA-bound
-  // contraction.  Each kernel computes the same values in either order, so the result is the
-  // same bits as the serial path.
-  const int64_t plane = (int64_t)P->tiles[0] * P->tiles[1];
-  const int nz = P->tiles[2];
-  if (plane % kTileGroup != 0 || nz < 4 || P->n_tiles < 4096 || P->n_tiles != P->n_tiles_pad) {
-    if ((st = launch_fit(P, E, nu, prec, coef, stream))) return st;
-    if ((st = launch_contract(P, prec, coef, blocks, stream))) return st;
-    return launch_scatter(P, prec, blocks, d_values, stream);
-  }
-  if ((st = pipeline_resources(P))) return st;
-  hipStream_t s = (hipStream_t)stream, aux = (hipStream_t)P->dev.aux_stream;
-  const int per = (nz + 7) / 8;                 // z-planes per slab (at most 8 slabs)
-  const int n_slab = (nz + per - 1) / per;
-  auto slab_t0 = [&](int k) { return (int64_t)std::min(nz, k * per) * plane; };
-  for (int k = 0; k <= n_slab; ++k) {
-    if (k < n_slab) {
-      const int64_t t0 = slab_t0(k), t1 = slab_t0(k + 1);
-      if ((st = launch_fit(P, E, nu, prec, coef, stream, t0, t1))) return st;
-      if ((st = launch_contract(P, prec, coef, blocks, stream, t0 / kTileGroup, t1 / kTileGroup))) return st;
-      IGAMT_HIP(hipEventRecord((hipEvent_t)P->dev.events[k], s));
-    }
-    if (k >= 1) {   // scatter of slab k-1 after the contraction of slab k (or of the last slab)
-      IGAMT_HIP(hipStreamWaitEvent(aux, (hipEvent_t)P->dev.events[std::min(k, n_slab - 1)], 0));
-      if ((st = launch_scatter(P, prec, blocks, d_values, aux, slab_t0(k - 1), slab_t0(k)))) return st;
-    }
-  }
-  IGAMT_HIP(hipEventRecord((hipEvent_t)P->dev.events[16], aux));
-  IGAMT_HIP(hipStreamWaitEvent(s, (hipEvent_t)P->dev.events[16], 0));
-  return IGAMT_OK;
+  // The three stages in turn on the caller's stream.  (Running the scatter of one slab of tiles
+  // beside the contraction of the next on a second stream gains nothing: the FP64 contraction
+  // holds every CU's registers, and the scatter needs most CUs to reach its speed.)
+  if ((st = launch_fit(P, E, nu, prec, coef, stream))) return st;
+  if ((st = launch_contract(P, prec, coef, blocks, stream))) return st;
+  return launch_scatter(P, prec, blocks, d_values, stream);
 }

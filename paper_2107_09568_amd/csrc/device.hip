@@ -95,28 +95,9 @@ void free_device(igamt_plan *P) {
     for (void *p : q)
       if (p) (void)hipFree(p);
   }
-  for (void *e : d.events)
-    if (e) (void)hipEventDestroy((hipEvent_t)e);
-  if (d.aux_stream) (void)hipStreamDestroy((hipStream_t)d.aux_stream);
   (void)hipSetDevice(cur);
   d = DevicePtrs();
   P->batch_points_cap = 0;
-}
-
-igamt_status pipeline_resources(igamt_plan *P) {
-  DevicePtrs &d = P->dev;
-  if (!d.aux_stream) {
-    hipStream_t st;
-    IGAMT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));   // default priority
-    d.aux_stream = st;
-  }
-  for (void *&e : d.events)
-    if (!e) {
-      hipEvent_t ev;
-      IGAMT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      e = ev;
-    }
-  return IGAMT_OK;
 }
 
 igamt_status upload_tile_ctrl(igamt_plan *P) {

@@ -39,6 +39,11 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Knot span containing x: the largest i in [p, n-1] with U[i] <= x (x = 1 goes
 // to the last non-empty span).  U has n + p + 1 entries.
+// Wait for this wave's LDS operations, then synchronise the workgroup.  Unlike __syncthreads this
+// does not wait for outstanding global loads or stores (register prefetches stay in flight, stores
+// drain in the background); it orders LDS accesses only.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ inline int find_span(const double *__restrict__ U, int n, int p, double x) {
   if (x >= U[n]) return n - 1;
   if (x <= U[p]) return p;

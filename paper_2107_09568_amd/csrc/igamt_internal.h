@@ -68,8 +68,6 @@ struct DevicePtrs {
   int32_t *ctrl_tiles_off[3] = {nullptr, nullptr, nullptr};  // per macro ctrl index: tiles touching it
   int32_t *ctrl_tiles[3] = {nullptr, nullptr, nullptr};      // (tile, local offset) pairs
   int32_t *flag = nullptr;           // smallest degenerate tile index (INT32_MAX = none)
-  void *aux_stream = nullptr;        // second stream of the slab pipeline (hipStream_t, default priority)
-  void *events[17] = {};             // hipEvent_t: slab contractions done (16) and the pipeline's end
   // tables
   double *table = nullptr;           // [Mp][Kp] FP64, zero padded
   double *table_t = nullptr;         // [transposed_rows][Mp] FP64 (transposed, zero padded, for the adjoint)
@@ -138,8 +136,6 @@ igamt_status upload_macro_ctrl(igamt_plan *plan, const double *ctrl, int on_devi
 igamt_status derive_table_copies(igamt_plan *plan, void *stream, const int32_t *gate = nullptr);
 // synchronous upload of the host tile control points
 igamt_status upload_tile_ctrl(igamt_plan *plan);
-// the plan's second stream and events for the slab pipeline (created on first use)
-igamt_status pipeline_resources(igamt_plan *plan);
 // stage launchers (fit.hip, contract.hip, scatter.hip)
 int64_t coef_bytes(const igamt_plan *plan, igamt_precision prec);
 int64_t blocks_bytes(const igamt_plan *plan, igamt_precision prec);

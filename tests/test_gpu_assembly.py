@@ -266,9 +266,8 @@ def test_small_and_flat_tile_grids(P, torch, grid):
 
 @pytest.mark.parametrize("tiles", [(16, 16, 20), (7, 5, 3)])
 def test_assembly_equals_stages(P, torch, tiles):
-    """16x16x20 tiles (the slab pipeline, slabs of 3 z-planes with a partial last slab) and 7x5x3
-    (a partial last tile group, no pipeline): assemble equals the three stages run one after the
-    other, bit for bit."""
+    """16x16x20 tiles and 7x5x3 (a partial last tile group): assemble equals the three stages run
+    one after the other, bit for bit."""
     import dataclasses
     w = dataclasses.replace(W.make("cfg4", n_boxes=16), tiles=tiles)
     plan = P.Plan.from_workload(w)

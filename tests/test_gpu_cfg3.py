@@ -83,9 +83,8 @@ def test_cfg3_sampled_blocks_and_rows(case, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
-def test_cfg3_pipelined_assembly_bit_identical(case, prec):
-    """igamt_assemble (fit/contraction and scatter of consecutive tile slabs on two streams) gives
-    the same bits as the three stages run one after the other on one stream."""
+def test_cfg3_assembly_bit_identical(case, prec):
+    """igamt_assemble gives the same bits as the three stage entry points called in turn."""
     torch, P, w, plan, pairs, table, ref_table, sample = case
     cb, bb = plan.workspace_bytes(prec)
     ws = plan.workspace(prec)
