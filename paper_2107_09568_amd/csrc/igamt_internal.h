@@ -16,7 +16,7 @@ constexpr int kMaxGauss = 8;       // table quadrature points per direction
 constexpr int kTileGroup = 16;     // tiles per contraction column group (144 columns)
 constexpr int kColPad = 64;        // table columns padded to a multiple of this
 #ifndef IGAMT_SCATTER_CHUNK
-#define IGAMT_SCATTER_CHUNK 256
+#define IGAMT_SCATTER_CHUNK 512
 #endif
 constexpr int kScatterChunk = IGAMT_SCATTER_CHUNK;   // block records per scatter workgroup
 constexpr int kDescWords = 12;                        // ints per scatter pair descriptor

@@ -1,7 +1,7 @@
 // Stage 3 of the assembly: deterministic scatter of the tile blocks into the
 // fixed CSR structure (step 4 of Section 3.2.4).
 //
-// A workgroup takes kScatterChunk (256) consecutive block records of one tile (pairs p = (A, B),
+// A workgroup takes kScatterChunk (512) consecutive block records of one tile (pairs p = (A, B),
 // A <= B tile-local), loads them into LDS with coalesced loads, and gives one
 // thread to each record.
 // The record's global pair {G_A, G_B} may be shared with neighbouring tiles:
