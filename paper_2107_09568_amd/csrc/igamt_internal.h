@@ -145,9 +145,9 @@ igamt_status launch_fit(igamt_plan *plan, double E, double nu, igamt_precision p
 // tile groups [g0, g1) of kTileGroup tiles; g1 < 0 means all groups
 igamt_status launch_contract(igamt_plan *plan, igamt_precision prec, const void *d_coef, void *d_blocks,
                              void *stream, int64_t g0 = 0, int64_t g1 = -1);
-// owner records of the tiles [t0, t1); t1 < 0 means all tiles
+// owner records of all tiles
 igamt_status launch_scatter(igamt_plan *plan, igamt_precision prec, const void *d_blocks, void *d_values,
-                            void *stream, int64_t t0 = 0, int64_t t1 = -1);
+                            void *stream);
 // C (rows x 9 n_tiles) = A (rows_pad x kdim, row-major) B (kdim per column, 9 n_tiles_pad columns),
 // written as out[t][row][ab] for row < rows; FP64 or FP32 operands (contract.hip)
 igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *B, void *out, int64_t rows,

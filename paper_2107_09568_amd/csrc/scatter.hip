@@ -42,7 +42,6 @@ struct ScatterArgs {
   int nT[3], tiles[3];
   int chunks;                // record chunks per tile
   int64_t M, n_tiles, per_xcd, SX, SY;
-  int64_t t0, t1;            // tiles of this launch
   const void *blocks;        // [n_tiles][M][9]
   void *values;              // [nnz]
 };
@@ -58,9 +57,9 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(ScatterArgs a)
   __shared__ int32_t sl[3][kMaxTileN];
   const int64_t w = blockIdx.x;
   const int64_t item = (w & 7) * a.per_xcd + (w >> 3);
-  const int64_t tile = a.t0 + item / a.chunks;
-  if (tile >= a.t1) return;
-  const int chunk = (int)(item - (tile - a.t0) * a.chunks);
+  const int64_t tile = item / a.chunks;
+  if (tile >= a.n_tiles) return;
+  const int chunk = (int)(item - tile * a.chunks);
   const int64_t p0 = (int64_t)chunk * NT;
   const int nrec = (int)min((int64_t)NT, a.M - p0);
   const int tid = threadIdx.x;
@@ -191,10 +190,7 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(ScatterArgs a)
   }
 }
 
-igamt_status launch_scatter(igamt_plan *P, igamt_precision prec, const void *d_blocks, void *d_values, void *stream,
-                            int64_t t0, int64_t t1) {
-  if (t1 < 0) t1 = P->n_tiles;
-  if (t0 < 0 || t1 > P->n_tiles || t0 >= t1) { set_error("invalid tile range"); return IGAMT_EINVAL; }
+igamt_status launch_scatter(igamt_plan *P, igamt_precision prec, const void *d_blocks, void *d_values, void *stream) {
   ScatterArgs a;
   for (int k = 0; k < 3; ++k) {
     if (P->nT[k] > kMaxTileN || P->nT[k] > 255) {
@@ -211,9 +207,7 @@ igamt_status launch_scatter(igamt_plan *P, igamt_precision prec, const void *d_b
   a.M = P->n_pairs;
   a.n_tiles = P->n_tiles;
   a.chunks = (int)((P->n_pairs + kScatterThreads - 1) / kScatterThreads);
-  a.t0 = t0;
-  a.t1 = t1;
-  const int64_t items = (t1 - t0) * a.chunks;
+  const int64_t items = P->n_tiles * a.chunks;
   a.per_xcd = (items + 7) / 8;
   a.SX = P->dir[0].pre[P->dir[0].NG];
   a.SY = P->dir[1].pre[P->dir[1].NG];

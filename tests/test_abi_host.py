@@ -119,3 +119,40 @@ def test_error_codes(P):
     with pytest.raises(P.IgamtError) as e:
         P.Plan(w.macro, t2, w.tiles, 0, 2, 3, 3)
     assert e.value.code in (-1, -6)
+
+
+def test_argument_checks_before_device_work(P):
+    """Entry points reject invalid arguments with IGAMT_EINVAL before any device work (these
+    calls return on a host without a GPU)."""
+    from paper_2107_09568_amd import _lib
+    L = _lib.lib()
+    w = W.make("cfg1")
+    plan = P.Plan.from_workload(w)
+    h, vp, EINVAL = plan._h, ctypes.c_void_p, -1
+    null = vp(0)
+    fake = vp(16)   # never dereferenced: the checks below fail first
+    # NULL pointers and bad sizes
+    assert L.igamt_fit(None, 1.0, 0.3, 0, fake, null) == EINVAL
+    assert L.igamt_contract(h, 0, null, fake, null) == EINVAL
+    assert L.igamt_contract(h, 7, fake, fake, null) == EINVAL            # unknown precision
+    assert L.igamt_scatter(h, 0, fake, null, null) == EINVAL
+    assert L.igamt_assemble(h, 1.0, 0.3, 0, null, fake, null) == EINVAL
+    assert L.igamt_tables_build_rows(h, fake, 0, fake, null) == EINVAL   # no rows
+    assert L.igamt_tables_build_batch(h, fake, 0, null, fake, null) == EINVAL        # no designs
+    assert L.igamt_tables_build_batch(h, fake, 65536, null, fake, null) == EINVAL    # grid y limit
+    assert L.igamt_tables_build_rows_batch(h, fake, 2, fake, 0, fake, null) == EINVAL
+    assert L.igamt_tables_from_pod_batch(h, fake, fake, 0, fake, 4, 1.0, fake, fake, null) == EINVAL   # r = 0
+    assert L.igamt_tables_from_pod_batch(h, fake, fake, 257, fake, 4, 1.0, fake, fake, null) == EINVAL
+    assert L.igamt_tables_rows_check_batch(h, fake, 3, fake, 2, fake, -1.0, fake, fake, null) == EINVAL  # tol < 0
+    assert L.igamt_pod_batch_work_doubles(0, 4) == -1
+    assert L.igamt_pod_batch_work_doubles(64, 17) == 64 * 32      # designs padded to groups of 16
+    assert L.igamt_adam_step(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, null) == EINVAL  # step 0
+    bad = _lib.MlpDesc()
+    bad.n_layers = 0
+    assert L.igamt_mlp_n_params(ctypes.byref(bad)) == -1
+    good = _lib.MlpDesc()
+    good.n_layers, good.batch = 2, 3
+    good.widths[0], good.widths[1], good.widths[2] = 4, 8, 5
+    assert L.igamt_mlp_n_params(ctypes.byref(good)) == 4 * 8 + 8 + 8 * 5 + 5
+    assert b"invalid" in L.igamt_last_error().lower() or len(L.igamt_last_error()) > 0
+    plan.close()
