@@ -194,6 +194,15 @@ def bench_learned(torch, W, P, n_designs=32):
         torch.cuda.synchronize()
         t_est.append(time.perf_counter() - t0)
         fallbacks += int(gate_t.item())
+    # the same per-design path replayed from a HIP graph (captured on the first call)
+    tn.table_for_graph(p_test[0], ctrls[0])
+    torch.cuda.synchronize()
+    t_graph = []
+    for p, c in zip(p_test, ctrls):
+        t0 = time.perf_counter()
+        tn.table_for_graph(p, c)
+        torch.cuda.synchronize()
+        t_graph.append(time.perf_counter() - t0)
     med = lambda x: float(np.median(x)) * 1e3
     # a batch of designs: exact tables of all of them, against the batched learned path
     # (one MLP forward, one reconstruction, exact check rows, exact tables where the gate is set)
@@ -222,6 +231,8 @@ def bench_learned(torch, W, P, n_designs=32):
             "designs_timed": len(p_test), "exact_table_ms": med(t_exact), "learned_table_ms": med(t_learn),
             "learned_with_estimate_ms": med(t_est), "speedup_learned_vs_exact": med(t_exact) / med(t_learn),
             "speedup_with_estimate_vs_exact": med(t_exact) / med(t_est),
+            "learned_with_estimate_graph_ms": med(t_graph),
+            "speedup_with_estimate_graph_vs_exact": med(t_exact) / med(t_graph),
             "table_rel_err_max": float(max(errs)), "table_rel_err_median": float(np.median(errs)),
             "fallbacks": fallbacks, "offline_s": {"exact_tables_512": t_snap, "pod": t_pod,
                                                  "train_8000_steps": tn.train_seconds},

@@ -23,6 +23,7 @@
 // reused from that XCD's L2 while the whole table stays resident in the
 // last-level cache.
 #include <algorithm>
+#include <atomic>
 
 #include "device_common.h"
 
@@ -427,11 +428,14 @@ static unsigned contract_grid(igamt_precision prec, const ContractArgs &a) {
   const int64_t items_x = (int64_t)(a.n_groups + 7) / 8 * a.n_mblk;
   int64_t slots = items_x;
   if (prec == IGAMT_F64 && kPersist<IGAMT_F64> && a.Kp / Mode<IGAMT_F64>::KCH >= 2) {   // two chunks per item
-    static int cus[64] = {};
+    static std::atomic<int> cus[64];   // CU count per device, queried once (0: not yet)
     int dev = 0;
     (void)hipGetDevice(&dev);
-    int &n = cus[dev & 63];
-    if (n == 0 && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 256;
+    int n = cus[dev & 63].load(std::memory_order_relaxed);
+    if (n == 0) {
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+      cus[dev & 63].store(n, std::memory_order_relaxed);
+    }
     slots = std::min<int64_t>(items_x, std::max(1, n / 8));
   }
   return (unsigned)(8 * slots);

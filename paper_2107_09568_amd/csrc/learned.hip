@@ -255,28 +255,41 @@ __global__ __launch_bounds__(256) void pod_reconstruct_batch_kernel(const float 
 }
 
 // Relative Frobenius error of listed table rows against exact rows; one workgroup per design
-// (grid x), with per-design strides of the table and of the exact rows.
-__global__ __launch_bounds__(256) void rows_error_kernel(const double *__restrict__ table, int64_t Kp, int K,
-                                                         const int32_t *__restrict__ rows, int n_rows, int64_t n_pairs,
-                                                         const double *__restrict__ exact, double *__restrict__ err,
-                                                         double tol, int32_t *__restrict__ gate,
-                                                         int64_t table_dstride) {
-  __shared__ double num[256], den[256];
+// (grid x), with per-design strides of the table and of the exact rows.  Each thread keeps four
+// partial sums (elements i, i + T, i + 2T, i + 3T of every stride of 4T), combined in a fixed
+// order and then over a fixed tree, so the error is bitwise reproducible.
+constexpr int kRowsErrThreads = 1024;
+__global__ __launch_bounds__(kRowsErrThreads) void rows_error_kernel(const double *__restrict__ table, int64_t Kp,
+                                                                     int K, const int32_t *__restrict__ rows,
+                                                                     int n_rows, int64_t n_pairs,
+                                                                     const double *__restrict__ exact,
+                                                                     double *__restrict__ err, double tol,
+                                                                     int32_t *__restrict__ gate,
+                                                                     int64_t table_dstride) {
+  constexpr int T = kRowsErrThreads;
+  __shared__ double num[T], den[T];
   table += blockIdx.x * table_dstride;
   exact += (int64_t)blockIdx.x * n_rows * K;
-  double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < (int64_t)n_rows * K; i += 256) {
-    const int64_t rr = i / K, c = i % K;
-    const int64_t p = rows[rr];
-    const double x = exact[i];
-    const double y = (p >= 0 && p < n_pairs) ? table[p * Kp + c] : __builtin_nan("");
-    a += (y - x) * (y - x);
-    b += x * x;
+  const int64_t n = (int64_t)n_rows * K;
+  double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 4 * T) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + (int64_t)u * T;
+      if (i < n) {
+        const int64_t rr = i / K, c = i - rr * K;
+        const int64_t p = rows[rr];
+        const double x = exact[i];
+        const double y = (p >= 0 && p < n_pairs) ? table[p * Kp + c] : __builtin_nan("");
+        a[u] += (y - x) * (y - x);
+        b[u] += x * x;
+      }
+    }
   }
-  num[threadIdx.x] = a;
-  den[threadIdx.x] = b;
+  num[threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
+  den[threadIdx.x] = (b[0] + b[1]) + (b[2] + b[3]);
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = T / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) { num[threadIdx.x] += num[threadIdx.x + s]; den[threadIdx.x] += den[threadIdx.x + s]; }
     __syncthreads();
   }
@@ -293,19 +306,23 @@ __device__ inline float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-// Z[b][o] = bias[o] + sum_i H[b][i] W[i][o], H = x (layer 0) or GELU(previous Z)
+// Z[b][o] = bias[o] + sum_i H[b][i] W[i][o], H = x (layer 0) or GELU(previous Z).  One workgroup
+// per batch row and block of outputs: the row's inputs (through GELU) are computed once into LDS,
+// then every thread sums its output in ascending i.
+constexpr int kMlpMaxWidth = 4096;
 __global__ __launch_bounds__(256) void mlp_layer_fwd(const float *__restrict__ in, int in_gelu, int batch, int fi,
                                                      int fo, const float *__restrict__ W, const float *__restrict__ bias,
                                                      float *__restrict__ Z, float *__restrict__ Y) {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= (int64_t)batch * fo) return;
-  const int b = (int)(id / fo), o = (int)(id % fo);
-  float z = bias[o];
+  __shared__ float hs[kMlpMaxWidth];
+  const int b = blockIdx.x;
   const float *h = in + (int64_t)b * fi;
-  for (int i = 0; i < fi; ++i) {
-    const float x = in_gelu ? gelu(h[i]) : h[i];
-    z += x * W[(int64_t)i * fo + o];
-  }
+  for (int i = threadIdx.x; i < fi; i += blockDim.x) hs[i] = in_gelu ? gelu(h[i]) : h[i];
+  __syncthreads();
+  const int o = blockIdx.y * blockDim.x + threadIdx.x;
+  if (o >= fo) return;
+  float z = bias[o];
+  for (int i = 0; i < fi; ++i) z += hs[i] * W[(int64_t)i * fo + o];
+  const int64_t id = (int64_t)b * fo + o;
   Z[id] = z;
   if (Y) Y[id] = z;
 }
@@ -384,7 +401,7 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
 static bool mlp_ok(const igamt_mlp_desc *d) {
   if (!d || d->n_layers < 1 || d->n_layers > 8 || d->batch < 1) return false;
   for (int l = 0; l <= d->n_layers; ++l)
-    if (d->widths[l] < 1 || d->widths[l] > 4096) return false;
+    if (d->widths[l] < 1 || d->widths[l] > kMlpMaxWidth) return false;
   return true;
 }
 
@@ -478,7 +495,7 @@ extern "C" igamt_status igamt_table_rows_error(const igamt_plan *P, const int32_
                                                const double *d_exact, double *d_err, void *stream) {
   if (!P || !d_rows || !d_exact || !d_err || n_rows < 1) { set_error("invalid argument"); return IGAMT_EINVAL; }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
-  hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
+  hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(kRowsErrThreads), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
                      P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, 0.0, nullptr, 0);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
@@ -492,7 +509,7 @@ extern "C" igamt_status igamt_table_rows_check(const igamt_plan *P, const int32_
     return IGAMT_EINVAL;
   }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
-  hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
+  hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(kRowsErrThreads), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
                      P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate, 0);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
@@ -513,8 +530,9 @@ extern "C" igamt_status igamt_mlp_forward(const igamt_mlp_desc *d, const float *
     const float *b = W + (int64_t)fi * fo;
     const float *in = l == 0 ? d_x : d_act + act_offset(d, l - 1);
     float *Z = d_act + act_offset(d, l);
-    hipLaunchKernelGGL(mlp_layer_fwd, dim3(blocks_for((int64_t)d->batch * fo)), dim3(256), 0, s, in, l > 0 ? 1 : 0,
-                       d->batch, fi, fo, W, b, Z, l == d->n_layers - 1 ? d_y : nullptr);
+    const int block = fo <= 64 ? 64 : fo <= 128 ? 128 : 256;
+    hipLaunchKernelGGL(mlp_layer_fwd, dim3((unsigned)d->batch, (unsigned)((fo + block - 1) / block)), dim3(block), 0, s,
+                       in, l > 0 ? 1 : 0, d->batch, fi, fo, W, b, Z, l == d->n_layers - 1 ? d_y : nullptr);
     IGAMT_LAUNCH_CHECK();
   }
   return IGAMT_OK;
@@ -636,7 +654,7 @@ extern "C" igamt_status igamt_tables_rows_check_batch(const igamt_plan *P, const
     set_error("invalid argument");
     return IGAMT_EINVAL;
   }
-  hipLaunchKernelGGL(rows_error_kernel, dim3((unsigned)n_design), dim3(256), 0, (hipStream_t)stream, d_tables,
+  hipLaunchKernelGGL(rows_error_kernel, dim3((unsigned)n_design), dim3(kRowsErrThreads), 0, (hipStream_t)stream, d_tables,
                      (int64_t)P->K, P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate,
                      P->n_pairs * P->K);
   IGAMT_LAUNCH_CHECK();

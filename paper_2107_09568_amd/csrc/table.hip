@@ -6,10 +6,10 @@
 //
 // Pass 1 (one thread per micro element x Gauss point) evaluates the tile map
 // and stores, per point, w det J_T, the Bernstein values N_C(T^r(theta)) and the
-// mapped gradients of the (p+1)^3 active functions.  Pass 2 (one thread per
-// table entry: row, Bernstein index C, (i, j)) sums over the micro elements
-// shared by A and B in ascending element and point order, so the table is
-// bitwise reproducible.
+// mapped gradients of the (p+1)^3 active functions.  Pass 2 (one wave per
+// row and Bernstein index C) sums the nine (i, j) integrals over the micro
+// elements shared by A and B and their points, in a fixed order, so the table
+// is bitwise reproducible.
 #include "device_common.h"
 
 namespace igamt {
@@ -110,48 +110,64 @@ struct TableSumArgs {
   int64_t out_dstride;
 };
 
-// One thread per table entry (row, C, ij): the sum over the shared micro elements and their
-// Gauss points runs in ascending element and point order, so every entry is bitwise
-// reproducible and the same whether the whole table or a row subset is built.
+// One wave per (row, C): the terms of the nine sums (i, j), one per (shared micro element, Gauss
+// point), are split over the lanes (lane l takes terms l, l + 64, ... in ascending element and
+// point order), then combined by a butterfly across the wave, whose every step adds the same two
+// operands on both lanes: the order is fixed, so every entry is bitwise reproducible and the same
+// whether the whole table or a row subset is built.
 __global__ __launch_bounds__(256) void table_sum_kernel(TableSumArgs a) {
   if (a.gate && a.gate[blockIdx.y] == 0) return;
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= a.n_rows * a.npi * 9) return;
-  const int ij = (int)(id % 9), i = ij / 3, j = ij - 3 * i;
-  const int C = (int)((id / 9) % a.npi);
-  const int64_t row = id / (9 * (int64_t)a.npi);
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // (row, C), uniform per wave
+  if (wv >= a.n_rows * a.npi) return;
+  const int C = (int)(wv % a.npi);
+  const int64_t row = wv / a.npi;
   const int64_t p = a.rows ? a.rows[row] : row;
-  double *o = a.out + blockIdx.y * a.out_dstride + row * a.out_stride + 9 * C + ij;
+  double *o = a.out + blockIdx.y * a.out_dstride + row * a.out_stride + 9 * C;
   if (p < 0 || p >= a.n_pairs) {  // invalid row index: flag the output instead of reading out of bounds
-    *o = __builtin_nan("");
+    if (lane < 9) o[lane] = __builtin_nan("");
     return;
   }
   const int A = a.pairs[2 * p], B = a.pairs[2 * p + 1];
   const int ai[3] = {A % a.nT[0], (A / a.nT[0]) % a.nT[1], A / (a.nT[0] * a.nT[1])};
   const int bi[3] = {B % a.nT[0], (B / a.nT[0]) % a.nT[1], B / (a.nT[0] * a.nT[1])};
-  int lo[3], hi[3];
+  int lo[3], n[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     lo[k] = max(max(ai[k], bi[k]) - a.pT, 0);
-    hi[k] = min(min(ai[k], bi[k]), a.eT[k] - 1);
+    n[k] = max(0, min(min(ai[k], bi[k]), a.eT[k] - 1) - lo[k] + 1);
   }
   const int G = a.ng * a.ng * a.ng;
   const int p1 = a.pT + 1;
-  double acc = 0.0;
-  for (int ez = lo[2]; ez <= hi[2]; ++ez)
-    for (int ey = lo[1]; ey <= hi[1]; ++ey)
-      for (int ex = lo[0]; ex <= hi[0]; ++ex) {
-        const int64_t e = ex + (int64_t)a.eT[0] * (ey + (int64_t)a.eT[1] * ez);
-        const int la = (ai[0] - ex) + p1 * ((ai[1] - ey) + p1 * (ai[2] - ez));
-        const int lb = (bi[0] - ex) + p1 * ((bi[1] - ey) + p1 * (bi[2] - ez));
-        const double *pd = a.pts + blockIdx.y * a.pts_stride + e * G * a.stride;
-        for (int g = 0; g < G; ++g, pd += a.stride) {
-          const double wn = pd[0] * pd[1 + C];
-          const double ga = wn * pd[1 + a.npi + 3 * la + i];
-          acc += ga * pd[1 + a.npi + 3 * lb + j];
-        }
-      }
-  *o = acc;
+  const int nt = n[0] * n[1] * n[2] * G;
+  const double *pts = a.pts + blockIdx.y * a.pts_stride;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (int t = lane; t < nt; t += 64) {
+    const int sl = t / G, g = t - sl * G;
+    const int ex = lo[0] + sl % n[0], ey = lo[1] + (sl / n[0]) % n[1], ez = lo[2] + sl / (n[0] * n[1]);
+    const int64_t e = ex + (int64_t)a.eT[0] * (ey + (int64_t)a.eT[1] * ez);
+    const int la = (ai[0] - ex) + p1 * ((ai[1] - ey) + p1 * (ai[2] - ez));
+    const int lb = (bi[0] - ex) + p1 * ((bi[1] - ey) + p1 * (bi[2] - ez));
+    const double *pd = pts + (e * G + g) * a.stride;
+    const double wn = pd[0] * pd[1 + C];
+    const double *gA = pd + 1 + a.npi + 3 * la, *gB = pd + 1 + a.npi + 3 * lb;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double ga = wn * gA[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc[3 * i + j] += ga * gB[j];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o[k] = acc[k];
+  }
 }
 
 static __global__ void zero_f64(const int32_t *gate, double *p, int64_t n) {
@@ -240,8 +256,8 @@ static igamt_status build_tables(igamt_plan *P, void *stream, const int32_t *gat
   b.out = P->dev.table;
   b.out_stride = P->Kp;
   b.gate = gate;
-  const int64_t n = P->n_pairs * P->npi * 9;
-  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
+  const int64_t nw = P->n_pairs * P->npi;   // one wave per (row, C)
+  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, s, b);
   IGAMT_LAUNCH_CHECK();
   return derive_table_copies(P, stream, gate);
 }
@@ -270,8 +286,8 @@ extern "C" igamt_status igamt_tables_build_rows(igamt_plan *P, const int32_t *d_
   b.n_rows = n_rows;
   b.out = d_out;
   b.out_stride = P->K;
-  const int64_t n = (int64_t)n_rows * P->npi * 9;
-  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b);
+  const int64_t nw = (int64_t)n_rows * P->npi;
+  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, s, b);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
@@ -356,8 +372,8 @@ static igamt_status sum_batch(igamt_plan *P, hipStream_t s, int32_t n_design, co
   b.out = d_out;
   b.out_stride = P->K;
   b.out_dstride = b.n_rows * P->K;
-  const int64_t n = b.n_rows * P->npi * 9;
-  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n_design), dim3(256), 0, s, b);
+  const int64_t nw = b.n_rows * P->npi;
+  hipLaunchKernelGGL(table_sum_kernel, dim3((unsigned)((nw + 3) / 4), (unsigned)n_design), dim3(256), 0, s, b);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }

@@ -208,6 +208,7 @@ class TableNet:
 
     def fit_pod(self, snaps):
         torch = _torch()
+        self._graph = None        # a captured graph reads the old mean and basis
         n_s = snaps.shape[0]
         self.mean = torch.empty(self.n_e, dtype=torch.float32, device="cuda")
         self.basis = torch.empty((self.rank, self.n_e), dtype=torch.float32, device="cuda")
@@ -229,6 +230,9 @@ class TableNet:
         x = self.scale_inputs(params)
         t = torch.from_numpy((self.train_coeffs / self.coeff_scale).astype(np.float32)).cuda()
         self.mlp = MLP([x.shape[1], *self.hidden, self.rank], batch=x.shape[0], seed=self.seed)
+        self._graph = None        # a captured graph reads the old network's parameters
+        if getattr(self, "_dev", None) is not None:
+            self._dev.pop("desc1", None)
         tr = Trainer(self.mlp, x, t, lr=lr, lr_min=lr_min)
         t0 = time.perf_counter()
         hist = tr.run(steps, log_every)
@@ -247,14 +251,9 @@ class TableNet:
         place of the learned one when the estimate exceeds the tolerance -- the decision is taken
         on the device, nothing waits on the host.  Returns device tensors (estimated relative
         error [1] float64, fallback flag [1] int32)."""
-        b = self._upload(p, tile_ctrl)
-        self.plan.set_tile_ctrl(b["ctrl"])
-        self.mlp.set_batch(1)
-        check(lib().igamt_table_learned(self.plan._h, C.byref(self.mlp.desc), _ptr(self.mlp.params), _ptr(b["x"]),
-                                        _ptr(self.mlp.act), _ptr(self.mlp.y), _ptr(self.mean), _ptr(self.basis),
-                                        float(self.coeff_scale), _ptr(b["rows"]), int(b["rows"].numel()),
-                                        _ptr(b["exact_rows"]), float(self.tol), _ptr(b["err"]), _ptr(b["gate"]),
-                                        _stream()))
+        self._upload(p, tile_ctrl)
+        self._enqueue_learned()
+        b = self._buffers()
         return b["err"], b["gate"]
 
     def tables_for_batch(self, params, tile_ctrls):
@@ -283,6 +282,48 @@ class TableNet:
                                                _ptr(rows), int(rows.numel()), _ptr(exact_rows), float(self.tol),
                                                _ptr(err), _ptr(gate), _ptr(work), _ptr(tables), _stream()))
         return tables, err, gate
+
+    def _enqueue_learned(self):
+        """Queue the per-design learned path on the current stream, reading the design from the
+        device buffers x and ctrl (no host work, no allocation): the MLP runs with a batch-1
+        descriptor and activation buffers of its own, which no later call reallocates."""
+        b = self._buffers()
+        if "desc1" not in b:
+            torch = _torch()
+            b["desc1"] = _lib.MlpDesc()
+            b["desc1"].n_layers = self.mlp.desc.n_layers
+            for i in range(len(self.mlp.widths)):
+                b["desc1"].widths[i] = self.mlp.widths[i]
+            b["desc1"].batch = 1
+            b["act1"] = torch.empty(sum(self.mlp.widths[1:]), dtype=torch.float32, device="cuda")
+            b["y1"] = torch.empty((1, self.mlp.widths[-1]), dtype=torch.float32, device="cuda")
+        self.plan.set_tile_ctrl(b["ctrl"])
+        check(lib().igamt_table_learned(self.plan._h, C.byref(b["desc1"]), _ptr(self.mlp.params), _ptr(b["x"]),
+                                        _ptr(b["act1"]), _ptr(b["y1"]), _ptr(self.mean), _ptr(self.basis),
+                                        float(self.coeff_scale), _ptr(b["rows"]), int(b["rows"].numel()),
+                                        _ptr(b["exact_rows"]), float(self.tol), _ptr(b["err"]), _ptr(b["gate"]),
+                                        _stream()))
+
+    def table_for_graph(self, p, tile_ctrl):
+        """The per-design path of table_for_async replayed from a HIP graph: the dozen kernel
+        launches are captured once (on the first call, after one eager run that allocates the
+        scratch buffers) and replayed for every design, so a design costs one graph launch.
+        Returns the same device tensors (estimated error [1], fallback flag [1])."""
+        torch = _torch()
+        b = self._upload(p, tile_ctrl)
+        if getattr(self, "_graph", None) is None:
+            self._enqueue_learned()                    # eager: allocates the scratch buffers
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()                 # default priority
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side):
+                    self._enqueue_learned()
+            torch.cuda.current_stream().wait_stream(side)
+            self._graph = g
+        self._graph.replay()
+        return b["err"], b["gate"]
 
     def table_for(self, p, tile_ctrl, force_exact=False):
         """Put the table of design p (tile control points tile_ctrl) into the plan.

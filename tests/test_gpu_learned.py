@@ -276,3 +276,26 @@ def test_learned_batch_matches_per_design(family):
     plan.check()
     _say(f"learned batch: {len(params)} designs, {int(gate_b.sum())} fallbacks, "
          f"estimated err max over learned {err_b[gate_b == 0].max().item():.2e}")
+
+
+def test_learned_graph_replay_matches_eager(family):
+    """The per-design learned path replayed from a HIP graph gives, design after design, the
+    eager path's table, error estimate and fallback flag bit for bit, with eager work and
+    synchronisations between the replays (a design that falls back included)."""
+    torch, P, L, w, plan, tn, p_test = family
+    designs = list(p_test[:4]) + [np.array([0.6, 0.6, 0.1, 0.55]), p_test[0]]
+    for i, p in enumerate(designs):
+        ctrl = W.tile_family(p).ctrl
+        err_e, gate_e = tn.table_for_async(p, ctrl)
+        ref = plan.tables_get().clone()
+        ref_err, ref_gate = err_e.clone(), gate_e.clone()
+        scratch = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        err_g, gate_g = tn.table_for_graph(p, ctrl)
+        got = plan.tables_get()
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), i
+        assert torch.equal(err_g, ref_err) and torch.equal(gate_g, ref_gate), i
+        assert bool(torch.isfinite(scratch))
+    assert int(gate_g.item()) == 0 and int(ref_gate.item()) == 0
+    plan.check()
