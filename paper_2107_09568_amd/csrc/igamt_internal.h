@@ -21,6 +21,7 @@ constexpr int kColPad = 64;        // table columns padded to a multiple of this
 constexpr int kScatterChunk = IGAMT_SCATTER_CHUNK;   // block records per scatter workgroup
 constexpr int kDescWords = 12;                        // ints per scatter pair descriptor
 constexpr int kRowPad = 128;       // table rows padded to a multiple of this
+constexpr int kMaxTileControl = 16;   // tile control points per direction
 
 void set_error(const std::string &msg);
 

@@ -183,6 +183,10 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
         return IGAMT_EUNSUPPORTED;
       }
     P->eT[d] = n - p;
+    if (n > kMaxTileControl) {   // the scatter keeps a tile's slice of the 1-D tables in LDS
+      set_error("tiles with more than 16 control points per direction are not supported");
+      return IGAMT_EUNSUPPORTED;
+    }
   }
   // tile boundary control points at the identity (Greville) positions
   {

@@ -32,7 +32,7 @@ namespace igamt {
 
 constexpr int kScatterThreads = kScatterChunk;
 
-constexpr int kMaxTileN = 16;   // tile control points per direction the LDS slices hold
+constexpr int kMaxTileN = kMaxTileControl;   // tile control points per direction the LDS slices hold
 
 struct ScatterArgs {
   const int32_t *desc;       // [M][kDescWords] pair descriptors

@@ -156,3 +156,17 @@ def test_argument_checks_before_device_work(P):
     assert L.igamt_mlp_n_params(ctypes.byref(good)) == 4 * 8 + 8 + 8 * 5 + 5
     assert b"invalid" in L.igamt_last_error().lower() or len(L.igamt_last_error()) > 0
     plan.close()
+
+
+def test_plan_limits(P):
+    """Empty tile grids and tiles beyond the supported size are rejected when the plan is made."""
+    w = W.make("cfg1")
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, w.tile, (0, 2, 2), 1, 2, 3, 3)
+    assert e.value.code == -1
+    big = W.identity_spline((2, 2, 2), (15, 2, 2))        # 17 control points along x
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, big, w.tiles, 0, 2, 3, 3)
+    assert e.value.code == -6
+    ok = W.identity_spline((2, 2, 2), (14, 2, 2))         # 16: the largest supported
+    P.Plan(w.macro, ok, w.tiles, 0, 2, 3, 3).close()
