@@ -282,6 +282,35 @@ igamt_status igamt_table_learned(igamt_plan *plan, const igamt_mlp_desc *desc, c
                                  int32_t n_rows, double *d_exact_rows, double tol, double *d_err,
                                  int32_t *d_gate, void *stream);
 
+/* --- load vector (Section 3.2.2-3.2.3, eq. (39)-(41), (44)-(45), (53)-(55)) --
+ * External loads: a constant body force b (3 doubles, force per unit volume)
+ * and a constant traction t_f on each of the six macro faces f = 2 d + side
+ * (xi_d = 0 for side 0, xi_d = 1 for side 1; 18 doubles, force per unit area;
+ * zeros where there is none).  Host arrays, read during the call.
+ *
+ * igamt_load_table_build: the lookup table of eq. (54)-(55) for the plan's tile,
+ *   F[A][C][0] = int R_A N_C (volume) and F[A][C][1 + f] = int over tile face f
+ *   of R_A N_C, kept on the device; rebuild after igamt_set_tile_ctrl.
+ * igamt_load_table_get: copy it to d_out double [n_tile_ctrl][n_pi][7].
+ * igamt_load_fit: the projection coefficients of bbar = b |det J_M| (eq. (40),
+ *   (44)) and, on the macro faces a tile touches, of tbar_f = t_f times the
+ *   face's area element (eq. (41), (45), (87)-(88)) into d_coef double
+ *   [n_tiles][7][3][n_pi] (slot 0 the body, 1 + f face f; zero where a tile
+ *   does not touch f).  A det J <= 0 at a sample raises the degeneracy flag.
+ * igamt_load_gather: f[3 G + a] = sum over the tiles holding G, in ascending
+ *   tile index, of sum_slot sum_C coef[t][slot][a][C] F[A][C][slot] (eq. (53)),
+ *   into d_f double [n_dofs]; every entry is written, bitwise reproducibly.
+ * igamt_load_assemble: fit then gather, with d_workspace of
+ *   igamt_load_workspace_bytes holding the coefficients.                      */
+igamt_status igamt_load_table_build(igamt_plan *plan, void *stream);
+igamt_status igamt_load_table_get(const igamt_plan *plan, double *d_out, void *stream);
+igamt_status igamt_load_workspace_bytes(const igamt_plan *plan, int64_t *bytes);
+igamt_status igamt_load_fit(igamt_plan *plan, const double *body, const double *traction, double *d_coef,
+                            void *stream);
+igamt_status igamt_load_gather(igamt_plan *plan, const double *d_coef, double *d_f, void *stream);
+igamt_status igamt_load_assemble(igamt_plan *plan, const double *body, const double *traction, double *d_f,
+                                 void *d_workspace, void *stream);
+
 /* --- batches of designs ----------------------------------------------------
  * The same table steps for n_design designs of one tile family at once (same
  * knots, degree and pair set as the plan's reference tile, different control

@@ -273,6 +273,54 @@ class Plan:
                                            _stream()))
         return err
 
+    # ---- load vector ----------------------------------------------------------------------
+    @staticmethod
+    def _loads(body, traction):
+        b = np.ascontiguousarray(body, dtype=np.float64).reshape(3)
+        t = np.zeros((6, 3)) if traction is None else np.ascontiguousarray(traction, dtype=np.float64)
+        assert t.shape == (6, 3), "traction: one 3-vector per macro face 2 d + side"
+        return b, np.ascontiguousarray(t)
+
+    def load_table_build(self):
+        check(lib().igamt_load_table_build(self._h, _stream()))
+
+    def load_table_get(self):
+        torch = _torch()
+        out = torch.empty((self.n_tile_ctrl, (self.q + 1) ** 3, 7), dtype=torch.float64, device="cuda")
+        check(lib().igamt_load_table_get(self._h, _ptr(out), _stream()))
+        return out
+
+    def load_workspace(self):
+        nb = C.c_int64()
+        check(lib().igamt_load_workspace_bytes(self._h, C.byref(nb)))
+        return self._empty_bytes(nb.value)
+
+    def load_fit(self, body, traction=None, out=None):
+        """Projection coefficients [n_tiles, 7, 3, n_pi] of the body force and the face tractions."""
+        torch = _torch()
+        b, t = self._loads(body, traction)
+        if out is None:
+            out = torch.empty((self.n_tiles, 7, 3, (self.q + 1) ** 3), dtype=torch.float64, device="cuda")
+        check(lib().igamt_load_fit(self._h, b.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                   _ptr(out), _stream()))
+        return out
+
+    def load_gather(self, coef, out=None):
+        torch = _torch()
+        out = torch.empty(self.n_dofs, dtype=torch.float64, device="cuda") if out is None else out
+        check(lib().igamt_load_gather(self._h, _ptr(coef), _ptr(out), _stream()))
+        return out
+
+    def load_assemble(self, body, traction=None, out=None, workspace=None):
+        """The global load vector f^pi [n_dofs] (eq. (53)) on the device."""
+        torch = _torch()
+        b, t = self._loads(body, traction)
+        out = torch.empty(self.n_dofs, dtype=torch.float64, device="cuda") if out is None else out
+        workspace = self.load_workspace() if workspace is None else workspace
+        check(lib().igamt_load_assemble(self._h, b.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                        _ptr(out), _ptr(workspace), _stream()))
+        return out
+
     # ---- batches of designs of the plan's tile family -------------------------------------
     def _batch_ctrl(self, ctrls):
         torch = _torch()

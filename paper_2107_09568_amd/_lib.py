@@ -66,6 +66,12 @@ SIGNATURES = {
     "igamt_table_rows_check": (status, [vp, vp, i32, vp, f64, vp, vp, vp]),
     "igamt_table_learned": (status, [vp, C.POINTER(MlpDesc), vp, vp, vp, vp, vp, vp, f64, vp, i32, vp, f64, vp, vp,
                                      vp]),
+    "igamt_load_table_build": (status, [vp, vp]),
+    "igamt_load_table_get": (status, [vp, vp, vp]),
+    "igamt_load_workspace_bytes": (status, [vp, P_i64]),
+    "igamt_load_fit": (status, [vp, vp, vp, vp, vp]),
+    "igamt_load_gather": (status, [vp, vp, vp, vp]),
+    "igamt_load_assemble": (status, [vp, vp, vp, vp, vp, vp]),
     "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),
     "igamt_tables_from_pod_batch": (status, [vp, vp, vp, i32, vp, i32, f64, vp, vp, vp]),

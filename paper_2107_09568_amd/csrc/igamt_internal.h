@@ -79,6 +79,7 @@ struct DevicePtrs {
   float *table_h_scale = nullptr;    // [Mp] inverse row scale
   double *point_data = nullptr;      // table builder scratch
   double *batch_points = nullptr;    // point records of batched designs (grown on demand)
+  double *load_table = nullptr;      // [nTt][npi][7] load-vector table (volume, six faces)
 };
 
 }  // namespace igamt
@@ -122,6 +123,7 @@ struct igamt_plan {
   // state
   bool tables_ready = false;
   int64_t batch_points_cap = 0;       // doubles allocated in dev.batch_points
+  bool load_table_ready = false;
   igamt::DevicePtrs dev;
 };
 
@@ -135,6 +137,9 @@ void free_device(igamt_plan *plan);
 igamt_status upload_macro_ctrl(igamt_plan *plan, const double *ctrl, int on_device, void *stream);
 // copies for the other precisions; with a gate, the kernels do nothing unless *gate != 0
 igamt_status derive_table_copies(igamt_plan *plan, void *stream, const int32_t *gate = nullptr);
+// point records of the tile's micro elements (w det J_T, Bernstein values, mapped gradients) into
+// dev.point_data for the current tile control points (table.hip)
+igamt_status table_point_records(igamt_plan *plan, void *stream, int64_t &stride);
 // synchronous upload of the host tile control points
 igamt_status upload_tile_ctrl(igamt_plan *plan);
 // stage launchers (fit.hip, contract.hip, scatter.hip)

@@ -1,0 +1,397 @@
+// Load vector of the multiscale assembly (Section 3.2.2-3.2.3, eq. (39)-(41), (44)-(45),
+// (53)-(55); Appendix A.1, eq. (85)-(88)).
+//
+// Table (eq. (54)-(55)), per tile control point A and Bernstein index C, seven slots:
+//   F[A][C][0]     = int R_A(theta) N_C(T^r(theta)) det J_T(theta) dtheta     (volume)
+//   F[A][C][1 + f] = int over tile face f of R_A N_C dGamma                     (faces)
+// pulled back to the tile parameter domain; faces f = 2 d + side (side 0: theta_d = 0).  The
+// tile's boundary control points sit at the identity positions, so T^r is the identity on its
+// faces and dGamma is the unit-square measure.  The volume slot reuses the point records of the
+// stiffness table builder (w det J_T and N_C at every micro element's Gauss points).
+//
+// Fit, per tile (box coordinates xi in [0,1]^3, J = J_M(a + h xi) diag(h)):
+//   body:     bbar(xi) = b |det J|, projected onto Q_q (eq. (40), (44));
+//   traction: on every macro face f the tile's box touches, tbar_f = t_f |J e_u x J e_v|
+//             (the area element of eq. (87)-(88) for a face xi_d = const), projected onto the
+//             face's (q+1)^2 Bernstein functions (eq. (41), (45)).
+// The projections are the 1-D operator of eq. (23)-(24) applied per direction (the 2-D and 3-D
+// operators are its Kronecker products).  Coefficients: coef[t][slot][a][C], slot 0 the body,
+// 1 + f the faces (zero where the tile does not touch face f).
+//
+// Gather (eq. (53) and the conforming gluing): one thread per global dof 3 G + a sums, over the
+// tiles holding G in ascending tile index, sum_slot sum_C coef[t][slot][a][C] F[A][C][slot]
+// (slots of faces the tile does not touch skipped); no atomics, bitwise reproducible.
+#include "device_common.h"
+
+namespace igamt {
+
+constexpr int kLoadSlots = 7;
+
+struct LoadTableArgs {
+  const double *knots[3];
+  int nT[3], eT[3];
+  const double *gx, *gw;
+  int ng, q, npi;
+  int64_t stride;            // doubles per point record
+  const double *pts;         // point records of the table builder
+  double *table;             // [nTt][npi][7]
+};
+
+template <int PT>
+__global__ __launch_bounds__(64) void load_table_kernel(LoadTableArgs a) {
+  const int64_t id = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t nTt = (int64_t)a.nT[0] * a.nT[1] * a.nT[2];
+  if (id >= nTt * a.npi) return;
+  const int C = (int)(id % a.npi);
+  const int64_t A = id / a.npi;
+  const int ai[3] = {(int)(A % a.nT[0]), (int)((A / a.nT[0]) % a.nT[1]), (int)(A / ((int64_t)a.nT[0] * a.nT[1]))};
+  const int q1 = a.q + 1;
+  const int ci[3] = {C % q1, (C / q1) % q1, C / (q1 * q1)};
+  const int G = a.ng * a.ng * a.ng;
+  double *out = a.table + id * kLoadSlots;
+  // volume: the micro elements in the support of R_A, Gauss points in ascending order
+  int lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = max(ai[k] - PT, 0);
+    hi[k] = min(ai[k], a.eT[k] - 1);
+  }
+  double vol = 0.0;
+  for (int ez = lo[2]; ez <= hi[2]; ++ez)
+    for (int ey = lo[1]; ey <= hi[1]; ++ey)
+      for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+        const int e[3] = {ex, ey, ez};
+        const int64_t el = ex + (int64_t)a.eT[0] * (ey + (int64_t)a.eT[1] * ez);
+        for (int g = 0; g < G; ++g) {
+          const int gi[3] = {g % a.ng, (g / a.ng) % a.ng, g / (a.ng * a.ng)};
+          double R = 1.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int span = e[k] + PT;
+            const double l = a.knots[k][span], h = a.knots[k][span + 1];
+            double N[PT + 1], dN[PT + 1];
+            bspline_ders<PT>(a.knots[k], span, l + (h - l) * a.gx[gi[k]], N, dN);
+            R *= N[ai[k] - e[k]];
+          }
+          const double *pd = a.pts + (el * G + g) * a.stride;
+          vol += pd[0] * pd[1 + C] * R;
+        }
+      }
+  out[0] = vol;
+  // faces: A on face f, C in I_f; R_A and N_C are products of 1-D functions on the face
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, side = f & 1;
+    const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
+    double s = 0.0;
+    if (ai[d] == (side ? a.nT[d] - 1 : 0) && ci[d] == (side ? a.q : 0)) {
+      for (int ev = max(ai[v] - PT, 0); ev <= min(ai[v], a.eT[v] - 1); ++ev)
+        for (int eu = max(ai[u] - PT, 0); eu <= min(ai[u], a.eT[u] - 1); ++eu)
+          for (int gv = 0; gv < a.ng; ++gv)
+            for (int gu = 0; gu < a.ng; ++gu) {
+              double val = 1.0, wt = 1.0;
+              const int ee[2] = {eu, ev}, gg[2] = {gu, gv}, kk[2] = {u, v};
+#pragma unroll
+              for (int m = 0; m < 2; ++m) {
+                const int k = kk[m], span = ee[m] + PT;
+                const double l = a.knots[k][span], h = a.knots[k][span + 1];
+                const double th = l + (h - l) * a.gx[gg[m]];
+                double N[PT + 1], dN[PT + 1];
+                bspline_ders<PT>(a.knots[k], span, th, N, dN);
+                double B[kMaxQ + 1];
+                bernstein(a.q, th, B);
+                val *= N[ai[k] - ee[m]] * B[ci[k]];
+                wt *= (h - l) * a.gw[gg[m]];
+              }
+              s += wt * val;   // the end functions are 1 on the face, as are their Bernstein partners
+            }
+    }
+    out[1 + f] = s;
+  }
+}
+
+struct LoadFitArgs {
+  const double *knots[3];
+  int nM[3];
+  const double *ctrl;
+  const double *box_a[3];
+  const double *box_h[3];
+  int tiles[3];
+  int64_t n_tiles;
+  const double *fx;
+  const double *fP;          // [q1][n_fit] 1-D projection operator
+  int q, nf, npi;
+  double body[3];
+  double traction[6][3];
+  double *coef;              // [n_tiles][7][3][npi]
+  int32_t *flag;
+};
+
+template <int PM>
+__global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
+  __shared__ double vals[kMaxFit * kMaxFit * kMaxFit];   // |det J| at the body samples / face areas
+  const int64_t t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nf = a.nf, q1 = a.q + 1, npi = a.npi;
+  const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
+                     (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
+  const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
+  const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
+  double *co = a.coef + t * (int64_t)kLoadSlots * 3 * npi;
+  // body samples
+  const int ns = nf * nf * nf;
+  for (int s = tid; s < ns; s += 64) {
+    const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
+    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
+    double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+    int span[3];
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) J[c][k] *= hx[k];
+    const double D = det3(J);
+    if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag, (int32_t)t);
+    vals[s] = fabs(D);
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * npi; e += 64) {
+    const int comp = e / npi, C = e - comp * npi;
+    const int c1 = C % q1, c2 = (C / q1) % q1, c3 = C / (q1 * q1);
+    double v = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      const int s1 = s % nf, s2 = (s / nf) % nf, s3 = s / (nf * nf);
+      v += a.fP[c1 * nf + s1] * a.fP[c2 * nf + s2] * a.fP[c3 * nf + s3] * vals[s];
+    }
+    co[e] = a.body[comp] * v;
+  }
+  // faces
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, side = f & 1;
+    const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
+    double *cf = co + (int64_t)(1 + f) * 3 * npi;
+    const bool touched = tt[d] == (side ? a.tiles[d] - 1 : 0);
+    __syncthreads();   // vals is reused
+    if (touched) {
+      for (int s = tid; s < nf * nf; s += 64) {
+        const int su = s % nf, sv = s / nf;
+        double xh[3];
+        xh[d] = ax[d] + hx[d] * side;
+        xh[u] = ax[u] + hx[u] * a.fx[su];
+        xh[v] = ax[v] + hx[v] * a.fx[sv];
+        double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+        int span[3];
+        spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+        const double gu[3] = {J[0][u] * hx[u], J[1][u] * hx[u], J[2][u] * hx[u]};
+        const double gv[3] = {J[0][v] * hx[v], J[1][v] * hx[v], J[2][v] * hx[v]};
+        const double n0 = gu[1] * gv[2] - gu[2] * gv[1], n1 = gu[2] * gv[0] - gu[0] * gv[2],
+                     n2 = gu[0] * gv[1] - gu[1] * gv[0];
+        vals[s] = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < 3 * npi; e += 64) {
+      const int comp = e / npi, C = e - comp * npi;
+      const int c[3] = {C % q1, (C / q1) % q1, C / (q1 * q1)};
+      double r = 0.0;
+      if (touched && c[d] == (side ? a.q : 0)) {
+        for (int s = 0; s < nf * nf; ++s) {
+          const int su = s % nf, sv = s / nf;
+          r += a.fP[c[u] * nf + su] * a.fP[c[v] * nf + sv] * vals[s];
+        }
+        r *= a.traction[f][comp];
+      }
+      cf[e] = r;
+    }
+  }
+}
+
+struct LoadGatherArgs {
+  const double *table;       // [nTt][npi][7]
+  const double *coef;        // [n_tiles][7][3][npi]
+  int nT[3], tiles[3], npi;
+  int64_t n_global;
+  int GX, GY;
+  double *f;                 // [3 n_global]
+};
+
+__global__ __launch_bounds__(256) void load_gather_kernel(LoadGatherArgs a) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= 3 * a.n_global) return;
+  const int comp = (int)(id % 3);
+  const int64_t G = id / 3;
+  const int g[3] = {(int)(G % a.GX), (int)((G / a.GX) % a.GY), (int)(G / ((int64_t)a.GX * a.GY))};
+  int tlo[3], thi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int m = a.nT[k] - 1;   // tile t holds global indices t m .. t m + m along k
+    thi[k] = min(g[k] / m, a.tiles[k] - 1);
+    tlo[k] = g[k] > 0 ? (g[k] - 1) / m : 0;
+  }
+  double sum = 0.0;
+  for (int tz = tlo[2]; tz <= thi[2]; ++tz)
+    for (int ty = tlo[1]; ty <= thi[1]; ++ty)
+      for (int tx = tlo[0]; tx <= thi[0]; ++tx) {
+        const int tt[3] = {tx, ty, tz};
+        const int64_t t = tx + (int64_t)a.tiles[0] * (ty + (int64_t)a.tiles[1] * tz);
+        const int li[3] = {g[0] - tx * (a.nT[0] - 1), g[1] - ty * (a.nT[1] - 1), g[2] - tz * (a.nT[2] - 1)};
+        const int64_t A = li[0] + (int64_t)a.nT[0] * (li[1] + (int64_t)a.nT[1] * li[2]);
+        const double *tb = a.table + A * a.npi * kLoadSlots;
+        const double *co = a.coef + t * (int64_t)kLoadSlots * 3 * a.npi + (int64_t)comp * a.npi;
+        for (int slot = 0; slot < kLoadSlots; ++slot) {
+          if (slot > 0) {
+            const int f = slot - 1, d = f >> 1, side = f & 1;
+            if (tt[d] != (side ? a.tiles[d] - 1 : 0)) continue;   // the tile does not touch face f
+          }
+          const double *cs = co + (int64_t)slot * 3 * a.npi;
+          for (int C = 0; C < a.npi; ++C) sum += cs[C] * tb[C * kLoadSlots + slot];
+        }
+      }
+  a.f[id] = sum;
+}
+
+}  // namespace igamt
+
+using namespace igamt;
+
+static igamt_status load_fit_launch(igamt_plan *P, const double *body, const double *traction, double *d_coef,
+                                    hipStream_t s) {
+  LoadFitArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.knots[k] = P->dev.macro_knots[k];
+    a.nM[k] = P->nM[k];
+    a.box_a[k] = P->dev.box_a[k];
+    a.box_h[k] = P->dev.box_h[k];
+    a.tiles[k] = P->tiles[k];
+    a.body[k] = body[k];
+  }
+  for (int f = 0; f < 6; ++f)
+    for (int k = 0; k < 3; ++k) a.traction[f][k] = traction[3 * f + k];
+  a.ctrl = P->dev.macro_ctrl;
+  a.n_tiles = P->n_tiles;
+  a.fx = P->dev.fit_x;
+  a.fP = P->dev.fit_P;
+  a.q = P->q;
+  a.nf = P->n_fit;
+  a.npi = P->npi;
+  a.coef = d_coef;
+  a.flag = P->dev.flag;
+  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
+    set_error("macro maps with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  const dim3 grid((unsigned)P->n_tiles), block(64);
+  switch (P->pM[0]) {
+    case 1: hipLaunchKernelGGL(load_fit_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(load_fit_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(load_fit_kernel<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(load_fit_kernel<4>, grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(load_fit_kernel<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(load_fit_kernel<6>, grid, block, 0, s, a); break;
+    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+static bool finite_loads(const double *body, const double *traction) {
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(body[k])) return false;
+  for (int k = 0; k < 18; ++k)
+    if (!std::isfinite(traction[k])) return false;
+  return true;
+}
+
+extern "C" igamt_status igamt_load_table_build(igamt_plan *P, void *stream) {
+  if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  if (P->pT[0] != P->pT[1] || P->pT[0] != P->pT[2]) {
+    set_error("reference tiles with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int64_t stride = 0;
+  if ((st = table_point_records(P, s, stride))) return st;
+  if (!P->dev.load_table) IGAMT_HIP(hipMalloc((void **)&P->dev.load_table, P->nTt * P->npi * kLoadSlots * sizeof(double)));
+  LoadTableArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.knots[k] = P->dev.tile_knots[k];
+    a.nT[k] = P->nT[k];
+    a.eT[k] = P->eT[k];
+  }
+  a.gx = P->dev.gauss_x;
+  a.gw = P->dev.gauss_w;
+  a.ng = P->n_gauss;
+  a.q = P->q;
+  a.npi = P->npi;
+  a.stride = stride;
+  a.pts = P->dev.point_data;
+  a.table = P->dev.load_table;
+  const dim3 grid((unsigned)((P->nTt * P->npi + 63) / 64)), block(64);
+  switch (P->pT[0]) {
+    case 1: hipLaunchKernelGGL(load_table_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(load_table_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(load_table_kernel<3>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(load_table_kernel<4>, grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL(load_table_kernel<5>, grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL(load_table_kernel<6>, grid, block, 0, s, a); break;
+    default: set_error("unsupported tile degree"); return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  P->load_table_ready = true;
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_load_table_get(const igamt_plan *P, double *d_out, void *stream) {
+  if (!P || !d_out) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (!P->dev.ready || !P->load_table_ready) { set_error("load table not built"); return IGAMT_ESTATE; }
+  IGAMT_HIP(hipMemcpyAsync(d_out, P->dev.load_table, P->nTt * P->npi * kLoadSlots * sizeof(double),
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_load_workspace_bytes(const igamt_plan *P, int64_t *bytes) {
+  if (!P || !bytes) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  *bytes = align256(P->n_tiles * kLoadSlots * 3 * P->npi * (int64_t)sizeof(double));
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_load_fit(igamt_plan *P, const double *body, const double *traction, double *d_coef,
+                                       void *stream) {
+  if (!P || !body || !traction || !d_coef) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (!finite_loads(body, traction)) { set_error("non-finite body force or traction"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  return load_fit_launch(P, body, traction, d_coef, (hipStream_t)stream);
+}
+
+extern "C" igamt_status igamt_load_gather(igamt_plan *P, const double *d_coef, double *d_f, void *stream) {
+  if (!P || !d_coef || !d_f) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  if (!P->load_table_ready) { set_error("load table not built"); return IGAMT_ESTATE; }
+  LoadGatherArgs a;
+  a.table = P->dev.load_table;
+  a.coef = d_coef;
+  for (int k = 0; k < 3; ++k) {
+    a.nT[k] = P->nT[k];
+    a.tiles[k] = P->tiles[k];
+  }
+  a.npi = P->npi;
+  a.n_global = P->n_global;
+  a.GX = P->dir[0].NG;
+  a.GY = P->dir[1].NG;
+  a.f = d_f;
+  hipLaunchKernelGGL(load_gather_kernel, dim3((unsigned)((3 * P->n_global + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, a);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_load_assemble(igamt_plan *P, const double *body, const double *traction, double *d_f,
+                                            void *d_workspace, void *stream) {
+  if (!P || !body || !traction || !d_f || !d_workspace) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  igamt_status st;
+  if ((st = igamt_load_fit(P, body, traction, (double *)d_workspace, stream))) return st;
+  return igamt_load_gather(P, (const double *)d_workspace, d_f, stream);
+}

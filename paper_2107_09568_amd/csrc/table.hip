@@ -218,6 +218,10 @@ static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride, co
   return IGAMT_OK;
 }
 
+igamt_status table_point_records(igamt_plan *P, void *stream, int64_t &stride) {
+  return run_points(P, (hipStream_t)stream, stride, nullptr);
+}
+
 static TableSumArgs sum_args(const igamt_plan *P, int64_t stride) {
   TableSumArgs b;
   b.pairs = P->dev.pairs;
