@@ -54,6 +54,19 @@ def pmc_traffic(kernel_src, config, prec):
     return float(b.group(1))
 
 
+def _timed(torch, steps, calls):
+    """Run `calls` (callables) `steps` times with HIP events between them on torch's stream;
+    returns per-step durations [steps, len(calls)] in ms."""
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        for i, c in enumerate(calls):
+            c()
+            ev[k][i + 1].record()
+    torch.cuda.synchronize()
+    return np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(len(calls))] for k in range(steps)])
+
+
 def time_stages(torch, plan, w, prec, steps, warmup, ws):
     cb, bb = plan.workspace_bytes(prec)
     coef = ws
@@ -97,8 +110,15 @@ def time_stages(torch, plan, w, prec, steps, warmup, ws):
             "serial_step_ms": st.sum(axis=1), "step_ms": step}, vals, blocks
 
 
-def cpu_baseline(w, n_sample, seed=11):
-    """The CPU oracle on a seeded sample of tiles: fit + table contraction + CSR scatter of the sample."""
+def cpu_baseline(w, n_sample, seed=11, one_thread=False):
+    """The CPU oracle on a seeded sample of tiles: fit + table contraction + CSR scatter of the sample
+    (with all host threads, or with one BLAS thread)."""
+    if one_thread:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            r = cpu_baseline(w, n_sample, seed)
+        r["cores"] = 1
+        return r
     from oracle import assembly, projection, tables
     try:
         from threadpoolctl import threadpool_info
@@ -119,6 +139,29 @@ def cpu_baseline(w, n_sample, seed=11):
     return {"value": n_sample / dt, "unit": "tile blocks/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_sample} seeded tiles of the same workload (fit + contraction + CSR of the sample), "
                       f"{dt:.1f} s; host has {os.cpu_count()} logical CPUs"}
+
+
+def bench_load(torch, plan, steps, warmup):
+    """Load vector f^pi (body force and face tractions) on the assembly workload: the projection
+    coefficients of every tile, then the gather into the global vector (table prebuilt)."""
+    body = np.array([0.0, 0.0, -1.0])
+    traction = np.zeros((6, 3))
+    traction[1] = [0.0, 0.5, 0.0]
+    traction[5] = [0.2, 0.0, -0.3]
+    plan.load_table_build()
+    coef = plan.load_fit(body, traction)
+    f = plan.load_gather(coef)
+    for _ in range(warmup):
+        plan.load_fit(body, traction, out=coef)
+        plan.load_gather(coef, out=f)
+    st = _timed(torch, steps, [lambda: plan.load_fit(body, traction, out=coef), lambda: plan.load_gather(coef, out=f)])
+    plan.check()
+    fit_ms, gather_ms = float(np.median(st[:, 0])), float(np.median(st[:, 1]))
+    coef_bytes = coef.numel() * 8
+    return {"workload": "assembly workload, body force (0, 0, -1), tractions on faces xi_1 = 1 and xi_3 = 1",
+            "n_dofs": int(f.numel()), "fit_ms": fit_ms, "gather_ms": gather_ms, "step_ms": fit_ms + gather_ms,
+            "tiles_per_s": plan.n_tiles / ((fit_ms + gather_ms) * 1e-3),
+            "bytes": {"coef_written": coef_bytes, "f_written": int(f.numel()) * 8}}
 
 
 def bench_adjoint(torch, W, P, steps):
@@ -337,6 +380,10 @@ def main():
                           "scatter_ms": float(np.median(rr["scatter_ms"])), "fit_ms": float(np.median(rr["fit_ms"])),
                           "max_block_rel_err_vs_f64": err}
     out["variants"] = variants
+    out["blocks_3x3_per_s"] = plan.n_pairs * out["value"]
+    out["ms_per_step_min"] = float(np.min(r["step_ms"]))
+    log("bench: load vector")
+    out["load_vector"] = bench_load(torch, plan, args.steps, args.warmup)
     if not args.no_extras:
         log("bench: shape gradient")
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)
@@ -345,6 +392,8 @@ def main():
     if not args.no_cpu:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_tiles)
+        log("bench: cpu baseline, one thread")
+        out["cpu_baseline_1thread"] = cpu_baseline(w, max(256, args.cpu_tiles // 8), one_thread=True)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
