@@ -139,3 +139,16 @@ def dense_global(w, pairs, blocks):
         d = tile_dofs(w, t)
         K[np.ix_(d, d)] += tile_dense(pairs, blocks[t], nT)
     return K
+
+
+def linop_apply(w, pairs: np.ndarray, blocks: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Matrix-free product of Section 4.2, eq. (74): K u = sum_t scatter(K^(t) u^(t)), with the
+    tile matrices K^(t) built from the tile blocks (never the global matrix); tile products
+    summed into the global vector in ascending tile order."""
+    nT = int(np.prod(w.tile.n_ctrl))
+    y = np.zeros(n_global_dofs(w))
+    for t in range(len(blocks)):
+        dofs = tile_dofs(w, t)
+        yt = tile_dense(pairs, blocks[t], nT) @ u[dofs]
+        np.add.at(y, dofs, yt)
+    return y

@@ -171,3 +171,23 @@ def test_quadrature_convergence_single_tile():
     assert np.linalg.norm(k8 - k3) / np.linalg.norm(k8) < 1e-3
     _, blocks = _fast_blocks(w, pairs)
     assert np.linalg.norm(blocks[3] - k3) / np.linalg.norm(k3) < 1e-3
+
+
+def test_linop_equals_assembled_matrix(cfg1_global):
+    """Eq. (74): the tile-by-tile product equals the assembled CSR matrix times u, and for an
+    affine map the standard Gauss-quadrature matrix times u."""
+    w, pairs, blocks, _ = cfg1_global
+    rp, ci, vals = assembly.assemble_csr(w, pairs, blocks)
+    u = W.random_displacement(geometry.n_global_dofs(w), 3)
+    y = assembly.linop_apply(w, pairs, blocks, u)
+    ref = assembly.spmv(rp, ci, vals, u)
+    assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+    wa = _affine_workload(2, tiles=(2, 1, 2), box_mode=1)
+    pa, ba = _fast_blocks(wa)
+    ua = W.random_displacement(geometry.n_global_dofs(wa), 4)
+    ya = assembly.linop_apply(wa, pa, ba, ua)
+    Kstd = np.zeros((geometry.n_global_dofs(wa),) * 2)
+    for t in range(wa.n_tiles):
+        d = geometry.tile_dofs(wa, t)
+        Kstd[np.ix_(d, d)] += standard.tile_matrix_standard(wa, t)
+    assert np.linalg.norm(ya - Kstd @ ua) <= 1e-12 * np.linalg.norm(Kstd @ ua)
