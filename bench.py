@@ -164,6 +164,61 @@ def bench_load(torch, plan, steps, warmup):
             "bytes": {"coef_written": coef_bytes, "f_written": int(f.numel()) * 8}}
 
 
+def bench_linop(torch, W, P, plan, w, steps, warmup):
+    """Matrix-free product K u (eq. (74)) on the assembly workload: from stored tile blocks (FP64
+    and FP32 blocks), on the fly per slab of tiles from the table and the coefficients (FP64), and
+    the CSR product of the assembled FP64 matrix beside them."""
+    u = torch.from_numpy(W.random_displacement(plan.n_dofs, 3)).cuda()
+    y = torch.empty_like(u)
+    ws0 = plan.linop_workspace("f64", 0)
+    coef = plan.fit(w.E, w.nu, "f64")
+    blocks = plan.contract(coef, "f64")
+    coef32 = plan.fit(w.E, w.nu, "f32")
+    blocks32 = plan.contract(coef32, "f32")
+    del coef32
+    ytile_b = plan.n_tiles * 3 * plan.n_tile_ctrl * 8
+    vec_b = 2 * plan.n_dofs * 8
+    calls = {"apply_blocks_f64": (lambda: plan.apply_blocks(blocks, u, "f64", out=y, workspace=ws0),
+                                  blocks.numel() * 8 + 2 * ytile_b + vec_b),
+             "apply_blocks_f32": (lambda: plan.apply_blocks(blocks32, u, "f32", out=y, workspace=ws0),
+                                  blocks32.numel() * 4 + 2 * ytile_b + vec_b)}
+    for slab in (256, 512, 1024, 2048):
+        wsl = plan.linop_workspace("f64", slab)
+        calls[f"linop_f64_slab{slab}"] = (
+            lambda wsl=wsl, slab=slab: plan.linop(coef, u, "f64", slab_tiles=slab, out=y, workspace=wsl), None)
+    out = {"workload": "assembly workload, seeded random u", "n_dofs": plan.n_dofs}
+    ys = {}
+    for name, (fn, nbytes) in calls.items():
+        for _ in range(warmup):
+            fn()
+        st = _timed(torch, steps, [fn])
+        ms = float(np.median(st[:, 0]))
+        ys[name] = y.clone()
+        out[name] = {"ms": ms, "products_per_s": 1e3 / ms}
+        if nbytes:
+            out[name]["bytes"] = int(nbytes)
+            out[name]["effective_GBps"] = nbytes / (ms * 1e-3) / 1e9
+    del blocks32
+    torch.cuda.empty_cache()
+    vals = plan.scatter(blocks, "f64")
+    rp, ci = plan.csr_device()
+    del blocks
+    torch.cuda.empty_cache()
+    fn = lambda: P.spmv(rp, ci, vals, u, out=y)
+    for _ in range(warmup):
+        fn()
+    ms = float(np.median(_timed(torch, steps, [fn])[:, 0]))
+    nb = plan.nnz * 12 + (plan.n_dofs + 1) * 8 + 2 * plan.n_dofs * 8
+    out["csr_spmv_f64"] = {"ms": ms, "products_per_s": 1e3 / ms, "bytes": int(nb),
+                           "effective_GBps": nb / (ms * 1e-3) / 1e9}
+    ref = y.clone()
+    out["rel_err_vs_csr"] = {k: ((v - ref).norm() / ref.norm()).item() for k, v in ys.items()}
+    out["onthefly_equals_stored_bitwise"] = all(torch.equal(ys["apply_blocks_f64"], ys[k])
+                                                for k in ys if k.startswith("linop_f64"))
+    plan.check()
+    return out
+
+
 def bench_adjoint(torch, W, P, steps):
     """Shape gradient of u^T K u on the differentiation workload (16^3 uniform boxes, cubic macro net)."""
     w = W.make("cfg4")
@@ -384,6 +439,8 @@ def main():
     out["ms_per_step_min"] = float(np.min(r["step_ms"]))
     log("bench: load vector")
     out["load_vector"] = bench_load(torch, plan, args.steps, args.warmup)
+    log("bench: matrix-free product")
+    out["linop"] = bench_linop(torch, W, P, plan, w, args.steps, args.warmup)
     if not args.no_extras:
         log("bench: shape gradient")
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)

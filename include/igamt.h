@@ -311,6 +311,35 @@ igamt_status igamt_load_gather(igamt_plan *plan, const double *d_coef, double *d
 igamt_status igamt_load_assemble(igamt_plan *plan, const double *body, const double *traction, double *d_f,
                                  void *d_workspace, void *stream);
 
+/* --- matrix-free product (Section 4.2, eq. (74)) ------------------------------
+ * y = K u for the full symmetric stiffness matrix K (the CSR matrix igamt_assemble
+ * would produce), as the sum over tiles of K^(t) u^(t) glued at shared control
+ * points, without the global matrix.  d_u and d_y are double [n_dofs] (dof
+ * 3 G + a) on the device; every entry of d_y is written.  The tile products
+ * accumulate in FP64 from blocks in the precision's storage type (double for
+ * IGAMT_F64, float otherwise); per dof, the tiles are summed in ascending tile
+ * index: no atomics, bitwise reproducible.  Tiles with more control points than
+ * the kernel's LDS holds (about 700 for FP64 blocks) give IGAMT_EUNSUPPORTED.
+ *
+ * igamt_linop_workspace_bytes: workspace of igamt_apply_blocks (slab_tiles = 0:
+ *   the tile products, 24 n_tile_ctrl bytes per tile) or of igamt_linop
+ *   (slab_tiles > 0, a multiple of 16: the tile products plus the blocks of one
+ *   slab of slab_tiles tiles); IGAMT_EINVAL for other slab_tiles.
+ * igamt_apply_blocks: from the tile blocks of igamt_contract in d_blocks
+ *   [n_tiles][n_pairs][9] (the matrix is formed once, then applied many times).
+ * igamt_linop: on the fly, from the table and the projection coefficients of
+ *   igamt_fit (d_coef) only: per slab of slab_tiles tiles, the contraction of
+ *   eq. (58) into the workspace, then the slab's tile products; the tile
+ *   matrices of the whole mesh never exist at once.  Requires tables
+ *   (IGAMT_ESTATE).  The result equals igamt_apply_blocks on the blocks of
+ *   igamt_contract bit for bit, whatever the slab size.                       */
+igamt_status igamt_linop_workspace_bytes(const igamt_plan *plan, igamt_precision prec, int64_t slab_tiles,
+                                         int64_t *bytes);
+igamt_status igamt_apply_blocks(igamt_plan *plan, igamt_precision prec, const void *d_blocks, const double *d_u,
+                                double *d_y, void *d_workspace, void *stream);
+igamt_status igamt_linop(igamt_plan *plan, igamt_precision prec, int64_t slab_tiles, const void *d_coef,
+                         const double *d_u, double *d_y, void *d_workspace, void *stream);
+
 /* --- batches of designs ----------------------------------------------------
  * The same table steps for n_design designs of one tile family at once (same
  * knots, degree and pair set as the plan's reference tile, different control

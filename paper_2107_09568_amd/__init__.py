@@ -321,6 +321,37 @@ class Plan:
                                         _ptr(out), _ptr(workspace), _stream()))
         return out
 
+    # ---- matrix-free product K u (eq. (74)) -----------------------------------------------
+    def linop_workspace(self, prec="f64", slab_tiles=0):
+        nb = C.c_int64()
+        check(lib().igamt_linop_workspace_bytes(self._h, _prec(prec), int(slab_tiles), C.byref(nb)))
+        return self._empty_bytes(nb.value)
+
+    def _vec(self, u):
+        torch = _torch()
+        assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous() and u.numel() == self.n_dofs
+        return u
+
+    def apply_blocks(self, blocks, u, prec="f64", out=None, workspace=None):
+        """y = K u from the tile blocks of contract() (the global matrix is never formed)."""
+        torch = _torch()
+        u = self._vec(u)
+        out = torch.empty(self.n_dofs, dtype=torch.float64, device="cuda") if out is None else out
+        workspace = self.linop_workspace(prec) if workspace is None else workspace
+        check(lib().igamt_apply_blocks(self._h, _prec(prec), _ptr(blocks), _ptr(u), _ptr(out), _ptr(workspace),
+                                       _stream()))
+        return out
+
+    def linop(self, coef, u, prec="f64", slab_tiles=512, out=None, workspace=None):
+        """y = K u on the fly from the table and the coefficients of fit(), slab by slab."""
+        torch = _torch()
+        u = self._vec(u)
+        out = torch.empty(self.n_dofs, dtype=torch.float64, device="cuda") if out is None else out
+        workspace = self.linop_workspace(prec, slab_tiles) if workspace is None else workspace
+        check(lib().igamt_linop(self._h, _prec(prec), int(slab_tiles), _ptr(coef), _ptr(u), _ptr(out),
+                                _ptr(workspace), _stream()))
+        return out
+
     # ---- batches of designs of the plan's tile family -------------------------------------
     def _batch_ctrl(self, ctrls):
         torch = _torch()

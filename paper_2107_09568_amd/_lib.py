@@ -72,6 +72,9 @@ SIGNATURES = {
     "igamt_load_fit": (status, [vp, vp, vp, vp, vp]),
     "igamt_load_gather": (status, [vp, vp, vp, vp]),
     "igamt_load_assemble": (status, [vp, vp, vp, vp, vp, vp]),
+    "igamt_linop_workspace_bytes": (status, [vp, i32, i64, P_i64]),
+    "igamt_apply_blocks": (status, [vp, i32, vp, vp, vp, vp, vp]),
+    "igamt_linop": (status, [vp, i32, i64, vp, vp, vp, vp, vp]),
     "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),
     "igamt_tables_from_pod_batch": (status, [vp, vp, vp, i32, vp, i32, f64, vp, vp, vp]),

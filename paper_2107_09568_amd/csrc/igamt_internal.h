@@ -80,6 +80,11 @@ struct DevicePtrs {
   double *point_data = nullptr;      // table builder scratch
   double *batch_points = nullptr;    // point records of batched designs (grown on demand)
   double *load_table = nullptr;      // [nTt][npi][7] load-vector table (volume, six faces)
+  // matrix-free tile product schedule (one allocation at apply_rec; the others point into it)
+  int32_t *apply_rec = nullptr;      // [n_pairs] A | B << 16
+  int32_t *apply_row_off = nullptr;  // [nTt + 1]
+  int32_t *apply_mirror = nullptr;   // records (B, A), B < A, grouped by A, ascending
+  int32_t *apply_mirror_chunk = nullptr;  // [(chunks + 1) * nTt]
 };
 
 }  // namespace igamt

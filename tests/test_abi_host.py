@@ -144,6 +144,16 @@ def test_argument_checks_before_device_work(P):
     assert L.igamt_tables_from_pod_batch(h, fake, fake, 0, fake, 4, 1.0, fake, fake, null) == EINVAL   # r = 0
     assert L.igamt_tables_from_pod_batch(h, fake, fake, 257, fake, 4, 1.0, fake, fake, null) == EINVAL
     assert L.igamt_tables_rows_check_batch(h, fake, 3, fake, 2, fake, -1.0, fake, fake, null) == EINVAL  # tol < 0
+    assert L.igamt_apply_blocks(h, 0, null, fake, fake, fake, null) == EINVAL
+    assert L.igamt_apply_blocks(h, 9, fake, fake, fake, fake, null) == EINVAL          # unknown precision
+    assert L.igamt_linop(h, 0, 0, fake, fake, fake, fake, null) == EINVAL              # slab of 0 tiles
+    assert L.igamt_linop(h, 0, 24, fake, fake, fake, fake, null) == EINVAL             # not a multiple of 16
+    nb = ctypes.c_int64()
+    assert L.igamt_linop_workspace_bytes(h, 0, 8, ctypes.byref(nb)) == EINVAL
+    assert L.igamt_linop_workspace_bytes(h, 0, 0, ctypes.byref(nb)) == 0
+    assert nb.value == 8 * 3 * 64 * 8                                                 # tile products only
+    assert L.igamt_linop_workspace_bytes(h, 1, 32, ctypes.byref(nb)) == 0
+    assert nb.value == 8 * 3 * 64 * 8 + 16 * plan.n_pairs * 9 * 4                     # slab clamped to 16 tiles
     assert L.igamt_pod_batch_work_doubles(0, 4) == -1
     assert L.igamt_pod_batch_work_doubles(64, 17) == 64 * 32      # designs padded to groups of 16
     assert L.igamt_adam_step(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, null) == EINVAL  # step 0
@@ -170,3 +180,9 @@ def test_plan_limits(P):
     assert e.value.code == -6
     ok = W.identity_spline((2, 2, 2), (14, 2, 2))         # 16: the largest supported
     P.Plan(w.macro, ok, w.tiles, 0, 2, 3, 3).close()
+    # a tile whose displacements do not fit the matrix-free product's LDS (1024 control points)
+    from paper_2107_09568_amd import _lib
+    wide = P.Plan(w.macro, W.identity_spline((2, 2, 2), (14, 14, 2)), w.tiles, 0, 2, 3, 3)
+    fake = ctypes.c_void_p(16)
+    assert _lib.lib().igamt_apply_blocks(wide._h, 0, fake, fake, fake, fake, None) == -6
+    wide.close()
