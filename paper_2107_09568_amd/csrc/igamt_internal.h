@@ -82,9 +82,8 @@ struct DevicePtrs {
   double *load_table = nullptr;      // [nTt][npi][7] load-vector table (volume, six faces)
   // matrix-free tile product schedule (one allocation at apply_rec; the others point into it)
   int32_t *apply_rec = nullptr;      // [n_pairs] A | B << 16
-  int32_t *apply_row_off = nullptr;  // [nTt + 1]
-  int32_t *apply_mirror = nullptr;   // records (B, A), B < A, grouped by A, ascending
-  int32_t *apply_mirror_chunk = nullptr;  // [(chunks + 1) * nTt]
+  int32_t *apply_perm = nullptr;     // per chunk: slots sorted by destination row (16 bits each)
+  int32_t *apply_seg = nullptr;      // per chunk: row | segment end << 16
 };
 
 }  // namespace igamt

@@ -16,11 +16,14 @@
 // Tile product kernel: one workgroup of 256 threads per tile.  The tile's displacements u^(t)
 // go to LDS; the block records stream through LDS in chunks of kApplyChunk records (coalesced
 // loads, the next chunk's loads in flight while the current one is used).  Per chunk, thread j
-// forms record j's two 3-vectors K_p u_B (for row A) and K_p^T u_A (for row B, A != B); then the
-// thread owning row A adds, in ascending record order, its upper records of the chunk and its
-// mirror records (pairs (B, A)) of the chunk.  The per-row order is fixed by the plan: no atomics,
-// bitwise reproducible.  Tile results go to ytile[t][3 A + a]; a gather then sums, per global dof,
-// over the tiles holding it in ascending tile index.
+// forms record j's two 3-vectors K_p u_B (for row A) and K_p^T u_A (for row B, A != B), and the
+// wave sums the K_p u_B of each row's run of consecutive records (segmented scan); then the
+// chunk's program, built once per plan, sums them per destination row: a list of the chunk's
+// 3-vector slots sorted by (row, kind, record) and, per row present, the end of its segment in
+// that list (one thread per segment; at most one segment per row and chunk).  The program is
+// prefetched with the blocks, so the row sums use LDS only.  Rows add their chunk sums in
+// ascending chunk order: no atomics, bitwise reproducible.  Tile results go to ytile[t][3 A + a];
+// a gather then sums, per global dof, over the tiles holding it in ascending tile index.
 #include <algorithm>
 
 #include "device_common.h"
@@ -30,10 +33,12 @@ namespace igamt {
 constexpr int kApplyChunk = 256;        // block records per chunk (one per thread)
 constexpr int kApplyThreads = 256;
 constexpr int kApplyLdsMax = 64 * 1024;
+static_assert(kApplyChunk == kApplyThreads && kApplyChunk % 64 == 0, "one record per thread, whole waves");
 
 // Dynamic LDS of the tile product kernel for block element type of `eb` bytes.
 inline int64_t apply_lds_bytes(int64_t nTt, int eb) {
-  return (int64_t)kApplyChunk * 9 * eb + (int64_t)kApplyChunk * 6 * 8 + 6 * nTt * 8;
+  return (int64_t)kApplyChunk * 9 * eb + (int64_t)kApplyChunk * 6 * 8 + (int64_t)kApplyChunk * (2 * (2 + 4) + 4) +
+         6 * nTt * 8;
 }
 
 struct ApplyArgs {
@@ -41,9 +46,9 @@ struct ApplyArgs {
   const double *u;            // [3 n_global]
   double *ytile;              // [n_tiles][3 nTt]
   const int32_t *rec;         // [n_pairs] A | B << 16
-  const int32_t *row_off;     // [nTt + 1] first record of row A
-  const int32_t *mirror_p;    // records (B, A), B < A, grouped by A, ascending
-  const int32_t *mirror_chunk;// [(n_chunks + 1) * nTt] first mirror entry of A at or after chunk c
+  const int32_t *perm;        // [n_chunks][kApplyChunk]: two 16-bit slots each (slot s < kApplyChunk:
+                              // K_p u_B of record c0 + s, else K_p^T u_A of record c0 + s - kApplyChunk)
+  const int32_t *seg;         // [n_chunks][2 kApplyChunk]: row | end << 16 (row 0xffff: unused)
   int64_t n_pairs, t0;
   int nTt, n_chunks;
   int nT[3], tiles[3];
@@ -53,31 +58,40 @@ struct ApplyArgs {
 template <typename BT>
 __global__ __launch_bounds__(kApplyThreads) void tile_apply_kernel(ApplyArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  BT *kb = (BT *)lds_raw;                                                   // [kApplyChunk][9]
-  double *upc = (double *)(lds_raw + (size_t)kApplyChunk * 9 * sizeof(BT));  // [kApplyChunk][3]
-  double *loc = upc + kApplyChunk * 3;                                      // [kApplyChunk][3]
-  double *us = loc + kApplyChunk * 3;                                       // [3 nTt]
-  double *ys = us + 3 * a.nTt;                                              // [3 nTt]
+  BT *kb = (BT *)lds_raw;                                                    // [kApplyChunk][9]
+  double *vals = (double *)(lds_raw + (size_t)kApplyChunk * 9 * sizeof(BT)); // [2 kApplyChunk][3]
+  double *us = vals + kApplyChunk * 6;                                       // [3 nTt]
+  double *ys = us + 3 * a.nTt;                                               // [3 nTt]
+  int32_t *segs = (int32_t *)(ys + 3 * a.nTt);                               // [2 kApplyChunk]
+  uint16_t *perm = (uint16_t *)(segs + 2 * kApplyChunk);                     // [2 kApplyChunk]
+  int32_t *recs = (int32_t *)(perm + 2 * kApplyChunk);                       // [kApplyChunk]
   const int tid = threadIdx.x;
   const int64_t t = a.t0 + blockIdx.x;
   const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
                      (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
   const BT *blk = (const BT *)a.blocks + (int64_t)blockIdx.x * a.n_pairs * 9;
-  // chunk 0 loads in flight while u^(t) is gathered
-  BT reg[9];
-  int32_t rec_next = 0;
-  auto load_chunk = [&](int c) {
-    const int64_t c0 = (int64_t)c * kApplyChunk;
+  // Register prefetch, two chunks ahead in two alternating sets: a chunk's block entries, record
+  // descriptors and program.  Loads past the last chunk re-read the last chunk (clamped addresses,
+  // so every set always issues the same loads); their data is never used.
+  struct Pref {
+    BT r[9];
+    int32_t rec, perm, seg0, seg1;
+  };
+  auto load = [&](Pref &f, int c) {
+    const int cc = min(c, a.n_chunks - 1);
+    const int64_t c0 = (int64_t)cc * kApplyChunk;
     const int64_t n = min((int64_t)kApplyChunk, a.n_pairs - c0) * 9;
     const BT *src = blk + c0 * 9;
+    f.rec = a.rec[min(c0 + tid, a.n_pairs - 1)];
+    f.perm = a.perm[(int64_t)cc * kApplyChunk + tid];
+    f.seg0 = a.seg[(int64_t)cc * 2 * kApplyChunk + tid];
+    f.seg1 = a.seg[(int64_t)cc * 2 * kApplyChunk + kApplyThreads + tid];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const int64_t e = tid + (int64_t)i * kApplyThreads;
-      reg[i] = e < n ? src[e] : BT(0);
-    }
-    rec_next = c0 + tid < a.n_pairs ? a.rec[c0 + tid] : 0;
+    for (int i = 0; i < 9; ++i) f.r[i] = src[min(tid + (int64_t)i * kApplyThreads, n - 1)];
   };
-  load_chunk(0);
+  Pref f0, f1;
+  load(f0, 0);
+  load(f1, 1);
   for (int i = tid; i < 3 * a.nTt; i += kApplyThreads) {
     const int A = i / 3, comp = i - 3 * A;
     const int l[3] = {A % a.nT[0], (A / a.nT[0]) % a.nT[1], A / (a.nT[0] * a.nT[1])};
@@ -86,52 +100,92 @@ __global__ __launch_bounds__(kApplyThreads) void tile_apply_kernel(ApplyArgs a) 
     us[i] = a.u[3 * G + comp];
     ys[i] = 0.0;
   }
-  for (int c = 0; c < a.n_chunks; ++c) {
+  // one chunk from set f, then the load of chunk c + 2 into f
+  auto step = [&](Pref &f, int c) {
     const int64_t c0 = (int64_t)c * kApplyChunk;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) kb[tid + i * kApplyThreads] = reg[i];
-    const int32_t rc = rec_next;
+    for (int i = 0; i < 9; ++i) kb[tid + i * kApplyThreads] = f.r[i];
+    ((int32_t *)perm)[tid] = f.perm;
+    segs[tid] = f.seg0;
+    segs[kApplyThreads + tid] = f.seg1;
+    recs[tid] = f.rec;   // through LDS: no register of f stays live across its reload
     lds_barrier();
-    if (c + 1 < a.n_chunks) load_chunk(c + 1);
-    if (c0 + tid < a.n_pairs) {
-      const int A = rc & 0xffff, B = rc >> 16;
+    load(f, c + 2);
+    const int32_t rc = recs[tid];
+    {
+      const bool valid = c0 + tid < a.n_pairs;
+      const int A = valid ? rc & 0xffff : 0xffff, B = valid ? rc >> 16 : 0;
       double K[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) K[i] = (double)kb[tid * 9 + i];
+      for (int i = 0; i < 9; ++i) K[i] = valid ? (double)kb[tid * 9 + i] : 0.0;
       const double uB0 = us[3 * B], uB1 = us[3 * B + 1], uB2 = us[3 * B + 2];
-      upc[3 * tid + 0] = K[0] * uB0 + K[1] * uB1 + K[2] * uB2;
-      upc[3 * tid + 1] = K[3] * uB0 + K[4] * uB1 + K[5] * uB2;
-      upc[3 * tid + 2] = K[6] * uB0 + K[7] * uB1 + K[8] * uB2;
-      if (A != B) {
+      double up0 = K[0] * uB0 + K[1] * uB1 + K[2] * uB2;
+      double up1 = K[3] * uB0 + K[4] * uB1 + K[5] * uB2;
+      double up2 = K[6] * uB0 + K[7] * uB1 + K[8] * uB2;
+      if (valid && A != B) {
         const double uA0 = us[3 * A], uA1 = us[3 * A + 1], uA2 = us[3 * A + 2];
-        loc[3 * tid + 0] = K[0] * uA0 + K[3] * uA1 + K[6] * uA2;
-        loc[3 * tid + 1] = K[1] * uA0 + K[4] * uA1 + K[7] * uA2;
-        loc[3 * tid + 2] = K[2] * uA0 + K[5] * uA1 + K[8] * uA2;
+        double *lo = vals + 3 * (kApplyChunk + tid);
+        lo[0] = K[0] * uA0 + K[3] * uA1 + K[6] * uA2;
+        lo[1] = K[1] * uA0 + K[4] * uA1 + K[7] * uA2;
+        lo[2] = K[2] * uA0 + K[5] * uA1 + K[8] * uA2;
+      }
+      // a row's upper records are consecutive: inclusive scan of K_p u_B over the wave, segmented
+      // by row (offsets 1, 2, ..., 32); the last lane of each row's run in the wave holds the run's
+      // sum, and the chunk's program lists exactly those lanes
+      const int lane = tid & 63;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int Ad = __shfl_up(A, d, 64);
+        const double t0 = __shfl_up(up0, d, 64), t1 = __shfl_up(up1, d, 64), t2 = __shfl_up(up2, d, 64);
+        if (lane >= d && Ad == A) {
+          up0 += t0;
+          up1 += t1;
+          up2 += t2;
+        }
+      }
+      const int An = __shfl_down(A, 1, 64);
+      if (valid && (lane == 63 || An != A)) {
+        double *up = vals + 3 * tid;
+        up[0] = up0;
+        up[1] = up1;
+        up[2] = up2;
       }
     }
     lds_barrier();
-    const int64_t c1 = min(c0 + kApplyChunk, a.n_pairs);
-    for (int A = tid; A < a.nTt; A += kApplyThreads) {
-      double y0 = ys[3 * A], y1 = ys[3 * A + 1], y2 = ys[3 * A + 2];
-      const int64_t p0 = max((int64_t)a.row_off[A], c0), p1 = min((int64_t)a.row_off[A + 1], c1);
-      for (int64_t p = p0; p < p1; ++p) {
-        const int j = (int)(p - c0);
-        y0 += upc[3 * j];
-        y1 += upc[3 * j + 1];
-        y2 += upc[3 * j + 2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = tid + h * kApplyThreads;
+      const int32_t sg = segs[i];
+      const int row = sg & 0xffff;
+      if (c < a.n_chunks && row != 0xffff) {
+        const int end = sg >> 16, start = i > 0 ? segs[i - 1] >> 16 : 0;
+        // two independent partial sums (entries start + 2 m + r go to partial r), added at the end
+        double y[2][3] = {};
+        int k = start;
+        for (; k + 2 <= end; k += 2) {
+          const double *v0 = vals + 3 * perm[k], *v1 = vals + 3 * perm[k + 1];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            y[0][d] += v0[d];
+            y[1][d] += v1[d];
+          }
+        }
+        if (k < end) {
+          const double *v = vals + 3 * perm[k];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) y[0][d] += v[d];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ys[3 * row + d] += y[0][d] + y[1][d];
       }
-      const int m0 = a.mirror_chunk[(int64_t)c * a.nTt + A], m1 = a.mirror_chunk[(int64_t)(c + 1) * a.nTt + A];
-      for (int m = m0; m < m1; ++m) {
-        const int j = (int)(a.mirror_p[m] - c0);
-        y0 += loc[3 * j];
-        y1 += loc[3 * j + 1];
-        y2 += loc[3 * j + 2];
-      }
-      ys[3 * A] = y0;
-      ys[3 * A + 1] = y1;
-      ys[3 * A + 2] = y2;
     }
     lds_barrier();
+  };
+  // both steps unconditional (the same loads on every path); with an odd number of chunks the
+  // last step is empty: no valid record, no row sums
+  for (int c = 0; c < a.n_chunks; c += 2) {
+    step(f0, c);
+    step(f1, c + 1);
   }
   double *out = a.ytile + t * 3 * a.nTt;
   for (int i = tid; i < 3 * a.nTt; i += kApplyThreads) out[i] = ys[i];
@@ -170,54 +224,55 @@ __global__ __launch_bounds__(256) void apply_gather_kernel(ApplyGatherArgs a) {
   a.y[id] = sum;
 }
 
-// Record descriptors and the row and mirror schedules of the tile product (built once per plan
+// Record descriptors and the per-chunk row-sum programs of the tile product (built once per plan
 // from the pair list; they do not depend on the tile's control points).
 static igamt_status ensure_apply_schedule(igamt_plan *P) {
   if (P->dev.apply_rec) return IGAMT_OK;
-  const int64_t np = P->n_pairs, nTt = P->nTt;
+  const int64_t np = P->n_pairs;
   const int n_chunks = (int)((np + kApplyChunk - 1) / kApplyChunk);
-  std::vector<int32_t> rec(np), row_off(nTt + 1, 0), mcount(nTt + 1, 0);
-  for (int64_t p = 0; p < np; ++p) {
-    const int A = P->pairs[2 * p], B = P->pairs[2 * p + 1];
-    rec[p] = A | B << 16;
-    ++row_off[A + 1];
-    if (A != B) ++mcount[B + 1];
-  }
-  for (int64_t A = 0; A < nTt; ++A) {
-    row_off[A + 1] += row_off[A];
-    mcount[A + 1] += mcount[A];
-  }
-  std::vector<int32_t> mirror(std::max<int64_t>(mcount[nTt], 1)), fill(mcount.begin(), mcount.end() - 1);
-  for (int64_t p = 0; p < np; ++p) {   // ascending p within each row's mirror list
-    const int A = P->pairs[2 * p], B = P->pairs[2 * p + 1];
-    if (A != B) mirror[fill[B]++] = (int32_t)p;
-  }
-  std::vector<int32_t> mchunk((int64_t)(n_chunks + 1) * nTt);
-  for (int64_t A = 0; A < nTt; ++A) {
-    int m = mcount[A];
-    for (int c = 0; c <= n_chunks; ++c) {
-      const int64_t c0 = (int64_t)c * kApplyChunk;
-      while (m < mcount[A + 1] && mirror[m] < c0) ++m;
-      mchunk[(int64_t)c * nTt + A] = m;
+  std::vector<int32_t> rec(np);
+  std::vector<uint16_t> perm((int64_t)n_chunks * 2 * kApplyChunk, 0);
+  std::vector<int32_t> seg((int64_t)n_chunks * 2 * kApplyChunk, 0xffff);
+  for (int64_t p = 0; p < np; ++p) rec[p] = P->pairs[2 * p] | P->pairs[2 * p + 1] << 16;
+  struct Entry { int32_t row, kind, p, slot; };
+  std::vector<Entry> ent;
+  for (int c = 0; c < n_chunks; ++c) {
+    const int64_t c0 = (int64_t)c * kApplyChunk, c1 = std::min(c0 + kApplyChunk, np);
+    ent.clear();
+    for (int64_t p = c0; p < c1; ++p) {
+      const int A = P->pairs[2 * p], B = P->pairs[2 * p + 1];
+      // upper records: only the last record of the row's run within its wave (kernel-side scan)
+      const bool run_end = (p - c0) % 64 == 63 || p + 1 == c1 || P->pairs[2 * (p + 1)] != A;
+      if (run_end) ent.push_back({A, 0, (int32_t)p, (int32_t)(p - c0)});
+      if (A != B) ent.push_back({B, 1, (int32_t)p, (int32_t)(kApplyChunk + p - c0)});
     }
+    std::sort(ent.begin(), ent.end(), [](const Entry &x, const Entry &y) {
+      return x.row != y.row ? x.row < y.row : x.kind != y.kind ? x.kind < y.kind : x.p < y.p;
+    });
+    uint16_t *pc = &perm[(int64_t)c * 2 * kApplyChunk];
+    int32_t *sc = &seg[(int64_t)c * 2 * kApplyChunk];
+    int ns = 0;
+    for (size_t k = 0; k < ent.size(); ++k) {
+      pc[k] = (uint16_t)ent[k].slot;
+      if (k + 1 == ent.size() || ent[k + 1].row != ent[k].row) sc[ns++] = ent[k].row | (int32_t)(k + 1) << 16;
+    }
+    for (int i = ns; i < 2 * kApplyChunk; ++i) sc[i] = 0xffff | (int32_t)ent.size() << 16;
   }
-  std::vector<int32_t> all;
-  all.reserve(rec.size() + row_off.size() + mirror.size() + mchunk.size());
-  all.insert(all.end(), rec.begin(), rec.end());
-  all.insert(all.end(), row_off.begin(), row_off.end());
-  all.insert(all.end(), mirror.begin(), mirror.end());
-  all.insert(all.end(), mchunk.begin(), mchunk.end());
+  const size_t n_words = rec.size() + perm.size() / 2 + seg.size();
   int32_t *d = nullptr;
-  IGAMT_HIP(hipMalloc((void **)&d, all.size() * sizeof(int32_t)));
-  if (hipMemcpy(d, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+  IGAMT_HIP(hipMalloc((void **)&d, n_words * sizeof(int32_t)));
+  bool ok = hipMemcpy(d, rec.data(), rec.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d + rec.size(), perm.data(), perm.size() * 2, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d + rec.size() + perm.size() / 2, seg.data(), seg.size() * 4, hipMemcpyHostToDevice) ==
+                hipSuccess;
+  if (!ok) {
     (void)hipFree(d);
     set_error("upload of the tile product schedule failed");
     return IGAMT_EHIP;
   }
   P->dev.apply_rec = d;
-  P->dev.apply_row_off = d + rec.size();
-  P->dev.apply_mirror = P->dev.apply_row_off + row_off.size();
-  P->dev.apply_mirror_chunk = P->dev.apply_mirror + mirror.size();
+  P->dev.apply_perm = d + rec.size();
+  P->dev.apply_seg = P->dev.apply_perm + perm.size() / 2;
   return IGAMT_OK;
 }
 
@@ -244,9 +299,8 @@ static igamt_status launch_tile_apply(igamt_plan *P, igamt_precision prec, const
   a.u = u;
   a.ytile = ytile;
   a.rec = P->dev.apply_rec;
-  a.row_off = P->dev.apply_row_off;
-  a.mirror_p = P->dev.apply_mirror;
-  a.mirror_chunk = P->dev.apply_mirror_chunk;
+  a.perm = P->dev.apply_perm;
+  a.seg = P->dev.apply_seg;
   a.n_pairs = P->n_pairs;
   a.t0 = t0;
   a.nTt = (int)P->nTt;
