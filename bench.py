@@ -219,6 +219,47 @@ def bench_linop(torch, W, P, plan, w, steps, warmup):
     return out
 
 
+def bench_solve(torch, W, P, plan, w):
+    """Krylov solve of K u = f (Jacobi CG with the matrix-free product of the FP64 tile blocks),
+    clamped on xi_3 = 0, body force and a traction on xi_3 = 1: the cost per iteration on the
+    assembly workload, and a solve to 1e-8 on the 16^3-tile uniform-box workload."""
+    import time
+    body = np.array([0.0, 0.0, -1.0])
+    traction = np.zeros((6, 3))
+    traction[5] = [0.2, 0.0, 0.5]
+
+    def setup(pl, wl):
+        pl.load_table_build()
+        f = pl.load_assemble(body, traction)
+        blocks = pl.contract(pl.fit(wl.E, wl.nu, "f64"), "f64")
+        return f, blocks, pl.face_mask([4])
+
+    def run(pl, f, blocks, fixed, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, it, res = pl.pcg(blocks, f, fixed, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, it, res
+
+    f, blocks, fixed = setup(plan, w)
+    run(plan, f, blocks, fixed, rtol=1e-30, max_iter=3)
+    t10, _, _ = run(plan, f, blocks, fixed, rtol=1e-30, max_iter=10)
+    t40, it40, res40 = run(plan, f, blocks, fixed, rtol=1e-30, max_iter=40)
+    out = {"assembly_workload": {"n_dofs": plan.n_dofs, "ms_per_iteration": (t40 - t10) / 30 * 1e3,
+                                 "rel_residual_after_40": res40}}
+    del blocks
+    torch.cuda.empty_cache()
+    w4 = W.make("cfg4", n_boxes=16)
+    p4 = P.Plan.from_workload(w4)
+    p4.tables_build()
+    f4, b4, fx4 = setup(p4, w4)
+    run(p4, f4, b4, fx4, rtol=1e-8, max_iter=2)
+    dt, it, res = run(p4, f4, b4, fx4, rtol=1e-8, max_iter=20000)
+    out["uniform_boxes_16^3"] = {"n_dofs": p4.n_dofs, "iterations": it, "rel_residual": res, "solve_s": dt,
+                                 "ms_per_iteration": dt / max(it, 1) * 1e3}
+    return out
+
+
 def bench_adjoint(torch, W, P, steps):
     """Shape gradient of u^T K u on the differentiation workload (16^3 uniform boxes, cubic macro net)."""
     w = W.make("cfg4")
@@ -441,6 +482,8 @@ def main():
     out["load_vector"] = bench_load(torch, plan, args.steps, args.warmup)
     log("bench: matrix-free product")
     out["linop"] = bench_linop(torch, W, P, plan, w, args.steps, args.warmup)
+    log("bench: Krylov solve")
+    out["solve"] = bench_solve(torch, W, P, plan, w)
     if not args.no_extras:
         log("bench: shape gradient")
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)

@@ -340,6 +340,25 @@ igamt_status igamt_apply_blocks(igamt_plan *plan, igamt_precision prec, const vo
 igamt_status igamt_linop(igamt_plan *plan, igamt_precision prec, int64_t slab_tiles, const void *d_coef,
                          const double *d_u, double *d_y, void *d_workspace, void *stream);
 
+/* --- Krylov solve (eq. (30) with the product of eq. (74), Section 4.2) ---------
+ * K u = f with homogeneous Dirichlet conditions: d_fixed uint8 [n_dofs], 1 on
+ * clamped dofs (u = 0 there), 0 on free ones; K_ff must be positive definite
+ * (at least one clamped face).  Jacobi-preconditioned conjugate gradients on
+ * the free dofs with the matrix-free product of igamt_apply_blocks (d_blocks as
+ * there), until |f - K u|_f <= rtol |f|_f by the updated residual, or max_iter
+ * iterations.  d_u double [n_dofs]: initial guess in, solution out (clamped
+ * entries set to 0).  d_f double [n_dofs].  d_workspace of
+ * igamt_pcg_workspace_bytes.  The call synchronises the stream once per
+ * iteration (host stopping test).  *iterations = iterations done;
+ * *rel_residual = |f - K u|_f / |f|_f recomputed from the final u (0 when f
+ * vanishes on the free dofs, where u = 0 is returned).  Reductions run in a
+ * fixed order: a solve is bitwise reproducible.  IGAMT_EINVAL for rtol <= 0,
+ * max_iter < 0, or a search direction with p.Kp <= 0.                        */
+igamt_status igamt_pcg_workspace_bytes(const igamt_plan *plan, int64_t *bytes);
+igamt_status igamt_pcg(igamt_plan *plan, igamt_precision prec, const void *d_blocks, const double *d_f,
+                       const uint8_t *d_fixed, double *d_u, double rtol, int32_t max_iter, void *d_workspace,
+                       void *stream, int32_t *iterations, double *rel_residual);
+
 /* --- batches of designs ----------------------------------------------------
  * The same table steps for n_design designs of one tile family at once (same
  * knots, degree and pair set as the plan's reference tile, different control

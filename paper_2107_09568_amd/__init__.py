@@ -76,6 +76,8 @@ class Plan:
         self._h = h
         self.macro_ctrl_shape = np.asarray(macro.ctrl).shape
         self.tile_ctrl_shape = np.asarray(tile.ctrl).shape
+        nz, ny, nx = self.tile_ctrl_shape[:3]
+        self.grid = tuple(int(tiles[k]) * (n - 1) + 1 for k, n in enumerate((nx, ny, nz)))   # global ctrl, x y z
         s = _lib.Sizes()
         check(lib().igamt_plan_sizes(h, C.byref(s)))
         self.sizes = {f: getattr(s, f) for f, _ in _lib.Sizes._fields_}
@@ -351,6 +353,35 @@ class Plan:
         check(lib().igamt_linop(self._h, _prec(prec), int(slab_tiles), _ptr(coef), _ptr(u), _ptr(out),
                                 _ptr(workspace), _stream()))
         return out
+
+    def face_mask(self, faces):
+        """uint8 [n_dofs] on the device, 1 on the dofs of the control points on the given macro
+        faces (2 d + side; side 0: xi_d = 0)."""
+        torch = _torch()
+        GX, GY, GZ = self.grid
+        idx = np.indices((GZ, GY, GX))
+        on = np.zeros(GX * GY * GZ, bool)
+        for face in faces:
+            d, side = divmod(int(face), 2)
+            along = (idx[2], idx[1], idx[0])[d].reshape(-1)
+            on |= along == ((GX, GY, GZ)[d] - 1 if side else 0)
+        return torch.from_numpy(np.repeat(on, 3).astype(np.uint8)).cuda()
+
+    def pcg(self, blocks, f, fixed, prec="f64", rtol=1e-10, max_iter=10000, u0=None, workspace=None):
+        """Jacobi-preconditioned CG on K u = f with u = 0 on the dofs where fixed != 0, using the
+        matrix-free product of the tile blocks; returns (u, iterations, relative residual)."""
+        torch = _torch()
+        f = self._vec(f)
+        assert fixed.is_cuda and fixed.dtype == torch.uint8 and fixed.numel() == self.n_dofs
+        u = torch.zeros_like(f) if u0 is None else self._vec(u0).clone()
+        if workspace is None:
+            nb = C.c_int64()
+            check(lib().igamt_pcg_workspace_bytes(self._h, C.byref(nb)))
+            workspace = self._empty_bytes(nb.value)
+        it, res = C.c_int32(), C.c_double()
+        check(lib().igamt_pcg(self._h, _prec(prec), _ptr(blocks), _ptr(f), _ptr(fixed), _ptr(u), float(rtol),
+                              int(max_iter), _ptr(workspace), _stream(), C.byref(it), C.byref(res)))
+        return u, it.value, res.value
 
     # ---- batches of designs of the plan's tile family -------------------------------------
     def _batch_ctrl(self, ctrls):

@@ -75,6 +75,8 @@ SIGNATURES = {
     "igamt_linop_workspace_bytes": (status, [vp, i32, i64, P_i64]),
     "igamt_apply_blocks": (status, [vp, i32, vp, vp, vp, vp, vp]),
     "igamt_linop": (status, [vp, i32, i64, vp, vp, vp, vp, vp]),
+    "igamt_pcg_workspace_bytes": (status, [vp, P_i64]),
+    "igamt_pcg": (status, [vp, i32, vp, vp, vp, vp, f64, i32, vp, vp, C.POINTER(i32), C.POINTER(f64)]),
     "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),
     "igamt_tables_from_pod_batch": (status, [vp, vp, vp, i32, vp, i32, f64, vp, vp, vp]),
