@@ -260,6 +260,21 @@ def bench_solve(torch, W, P, plan, w):
     return out
 
 
+def bench_volume(torch, plan, steps, warmup):
+    """Volume of the assembly workload and its gradient with respect to the macro control points
+    (table prebuilt): one pass over the tiles' fit samples, the fixed-order sums."""
+    plan.volume_table_build()
+    ws = plan.volume_workspace()
+    v, tv, g = plan.volume(grad=True, workspace=ws)
+    for _ in range(warmup):
+        plan.volume(grad=True, workspace=ws)
+    st = _timed(torch, steps, [lambda: plan.volume(grad=False, workspace=ws),
+                               lambda: plan.volume(grad=True, workspace=ws)])
+    plan.check()
+    return {"workload": "assembly workload", "volume": v.item(), "volume_ms": float(np.median(st[:, 0])),
+            "volume_and_gradient_ms": float(np.median(st[:, 1])), "n_macro_ctrl": int(g.shape[0])}
+
+
 def bench_adjoint(torch, W, P, steps):
     """Shape gradient of u^T K u on the differentiation workload (16^3 uniform boxes, cubic macro net)."""
     w = W.make("cfg4")
@@ -484,6 +499,8 @@ def main():
     out["linop"] = bench_linop(torch, W, P, plan, w, args.steps, args.warmup)
     log("bench: Krylov solve")
     out["solve"] = bench_solve(torch, W, P, plan, w)
+    log("bench: volume")
+    out["volume"] = bench_volume(torch, plan, args.steps, args.warmup)
     if not args.no_extras:
         log("bench: shape gradient")
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)

@@ -359,6 +359,29 @@ igamt_status igamt_pcg(igamt_plan *plan, igamt_precision prec, const void *d_blo
                        const uint8_t *d_fixed, double *d_u, double rtol, int32_t max_iter, void *d_workspace,
                        void *stream, int32_t *iterations, double *rel_residual);
 
+/* --- volume and its shape sensitivity (Section 3.1, eq. (14)-(19), (25)-(26);
+ *     Section 4.1.1, eq. (66)-(67)) -------------------------------------------
+ * igamt_volume_table_build: the table t^h[C] = int |det J_T| (N_C o T) (eq. (18))
+ *   by the stiffness table's micro-element Gauss points, its fold t_pi =
+ *   M_pi^-1 t^h (eq. (26)), and the per-sample weights of the fit, kept on the
+ *   device; rebuild after igamt_set_tile_ctrl.
+ * igamt_volume_table_get: copy t^h and/or t_pi (either pointer may be NULL) to
+ *   double [n_pi] device buffers.
+ * igamt_volume: per tile V^(t) = t^h . d^(t) (eq. (17)), d^(t) the projection of
+ *   det J_M^(t) (eq. (15), (23)) on the plan's fit samples, into d_tile_volumes
+ *   double [n_tiles] (NULL: kept in the workspace); V = sum of the tile volumes
+ *   in a fixed order into d_volume double [1]; if d_grad is not NULL, dV/dm
+ *   (eq. (66) with the adjoint field of eq. (67), under the fit's Gauss rule:
+ *   the exact derivative of the discrete V) into d_grad double
+ *   [n_macro_ctrl][3] (control points x fastest).  d_workspace of
+ *   igamt_volume_workspace_bytes.  det J_M <= 0 at a sample raises the
+ *   degeneracy flag (igamt_check).  Requires the table (IGAMT_ESTATE).        */
+igamt_status igamt_volume_table_build(igamt_plan *plan, void *stream);
+igamt_status igamt_volume_table_get(const igamt_plan *plan, double *d_table, double *d_folded, void *stream);
+igamt_status igamt_volume_workspace_bytes(const igamt_plan *plan, int64_t *bytes);
+igamt_status igamt_volume(igamt_plan *plan, double *d_tile_volumes, double *d_volume, double *d_grad,
+                          void *d_workspace, void *stream);
+
 /* --- batches of designs ----------------------------------------------------
  * The same table steps for n_design designs of one tile family at once (same
  * knots, degree and pair set as the plan's reference tile, different control

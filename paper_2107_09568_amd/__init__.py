@@ -383,6 +383,35 @@ class Plan:
                               int(max_iter), _ptr(workspace), _stream(), C.byref(it), C.byref(res)))
         return u, it.value, res.value
 
+    # ---- volume and its sensitivity (eq. (14)-(19), (25)-(26), (66)-(67)) ----------------
+    def volume_table_build(self):
+        check(lib().igamt_volume_table_build(self._h, _stream()))
+
+    def volume_table_get(self):
+        """(t^h, t_pi) as float64 [n_pi] device tensors."""
+        torch = _torch()
+        n = (self.q + 1) ** 3
+        t = torch.empty(n, dtype=torch.float64, device="cuda")
+        tp = torch.empty(n, dtype=torch.float64, device="cuda")
+        check(lib().igamt_volume_table_get(self._h, _ptr(t), _ptr(tp), _stream()))
+        return t, tp
+
+    def volume_workspace(self):
+        nb = C.c_int64()
+        check(lib().igamt_volume_workspace_bytes(self._h, C.byref(nb)))
+        return self._empty_bytes(nb.value)
+
+    def volume(self, grad=False, workspace=None):
+        """(V [1], tile volumes [n_tiles], dV/dm [n_macro_ctrl, 3] or None) on the device."""
+        torch = _torch()
+        workspace = self.volume_workspace() if workspace is None else workspace
+        v = torch.empty(1, dtype=torch.float64, device="cuda")
+        tv = torch.empty(self.n_tiles, dtype=torch.float64, device="cuda")
+        g = torch.empty((self.n_macro_ctrl, 3), dtype=torch.float64, device="cuda") if grad else None
+        check(lib().igamt_volume(self._h, _ptr(tv), _ptr(v), _ptr(g) if grad else None, _ptr(workspace),
+                                 _stream()))
+        return v, tv, g
+
     # ---- batches of designs of the plan's tile family -------------------------------------
     def _batch_ctrl(self, ctrls):
         torch = _torch()

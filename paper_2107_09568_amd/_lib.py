@@ -76,6 +76,10 @@ SIGNATURES = {
     "igamt_apply_blocks": (status, [vp, i32, vp, vp, vp, vp, vp]),
     "igamt_linop": (status, [vp, i32, i64, vp, vp, vp, vp, vp]),
     "igamt_pcg_workspace_bytes": (status, [vp, P_i64]),
+    "igamt_volume_table_build": (status, [vp, vp]),
+    "igamt_volume_table_get": (status, [vp, vp, vp, vp]),
+    "igamt_volume_workspace_bytes": (status, [vp, P_i64]),
+    "igamt_volume": (status, [vp, vp, vp, vp, vp, vp]),
     "igamt_pcg": (status, [vp, i32, vp, vp, vp, vp, f64, i32, vp, vp, C.POINTER(i32), C.POINTER(f64)]),
     "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),

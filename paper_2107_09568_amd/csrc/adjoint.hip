@@ -323,6 +323,29 @@ __global__ __launch_bounds__(256) void sum_kernel(const double *x, int64_t n, do
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+igamt_status launch_grad_reduce(igamt_plan *P, const double *local_grad, double *grad, void *stream) {
+  GradReduceArgs g;
+  for (int k = 0; k < 3; ++k) {
+    g.off[k] = P->dev.ctrl_tiles_off[k];
+    g.lst[k] = P->dev.ctrl_tiles[k];
+    g.nM[k] = P->nM[k];
+    g.tiles[k] = P->tiles[k];
+    g.Lc[k] = P->Lc[k];
+  }
+  g.local_grad = local_grad;
+  g.grad = grad;
+  const int64_t n_ctrl = (int64_t)P->nM[0] * P->nM[1] * P->nM[2];
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)n_ctrl), dim3(256), 0, (hipStream_t)stream, g);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
+igamt_status launch_sum(const double *x, int64_t n, double *out, void *stream) {
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, x, n, out);
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
 static int64_t grad_ws_layout(const igamt_plan *P, igamt_precision prec, int64_t off[6]) {
   const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
   const int64_t eb = prec == IGAMT_F64 ? 8 : 4;
@@ -439,22 +462,7 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   }
   IGAMT_LAUNCH_CHECK();
   // (4) reductions
-  GradReduceArgs g;
-  for (int k = 0; k < 3; ++k) {
-    g.off[k] = P->dev.ctrl_tiles_off[k];
-    g.lst[k] = P->dev.ctrl_tiles[k];
-    g.nM[k] = P->nM[k];
-    g.tiles[k] = P->tiles[k];
-    g.Lc[k] = P->Lc[k];
-  }
-  g.local_grad = lg;
-  g.grad = d_grad;
-  const int64_t nm = 3LL * P->nM[0] * P->nM[1] * P->nM[2];
-  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)(nm / 3)), dim3(256), 0, s, g);
-  IGAMT_LAUNCH_CHECK();
-  if (d_uKu) {
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, part, P->n_tiles, d_uKu);
-    IGAMT_LAUNCH_CHECK();
-  }
+  if ((st = launch_grad_reduce(P, lg, d_grad, stream))) return st;
+  if (d_uKu && (st = launch_sum(part, P->n_tiles, d_uKu, stream))) return st;
   return IGAMT_OK;
 }

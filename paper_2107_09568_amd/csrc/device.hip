@@ -86,7 +86,7 @@ void free_device(igamt_plan *P) {
   void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
                   d.table_h_scale, d.point_data, d.mirror_perm, d.pair_desc,
-                  d.batch_points, d.load_table, d.apply_rec};
+                  d.batch_points, d.load_table, d.apply_rec, d.volume_data};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 3; ++k) {
@@ -99,6 +99,7 @@ void free_device(igamt_plan *P) {
   d = DevicePtrs();
   P->batch_points_cap = 0;
   P->load_table_ready = false;
+  P->volume_ready = false;
 }
 
 igamt_status upload_tile_ctrl(igamt_plan *P) {
@@ -352,6 +353,7 @@ extern "C" igamt_status igamt_set_tile_ctrl_device(igamt_plan *P, const double *
   IGAMT_LAUNCH_CHECK();
   P->tables_ready = false;
   P->load_table_ready = false;
+  P->volume_ready = false;
   return IGAMT_OK;
 }
 

@@ -84,6 +84,7 @@ struct DevicePtrs {
   int32_t *apply_rec = nullptr;      // [n_pairs] A | B << 16
   int32_t *apply_perm = nullptr;     // per chunk: slots sorted by destination row (16 bits each)
   int32_t *apply_seg = nullptr;      // per chunk: row | segment end << 16
+  double *volume_data = nullptr;     // volume table t^h [npi], folded table t_pi [npi], sample weights [n_fit^3]
 };
 
 }  // namespace igamt
@@ -128,6 +129,7 @@ struct igamt_plan {
   bool tables_ready = false;
   int64_t batch_points_cap = 0;       // doubles allocated in dev.batch_points
   bool load_table_ready = false;
+  bool volume_ready = false;
   igamt::DevicePtrs dev;
 };
 
@@ -162,6 +164,11 @@ igamt_status launch_scatter(igamt_plan *plan, igamt_precision prec, const void *
 // written as out[t][row][ab] for row < rows; FP64 or FP32 operands (contract.hip)
 igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *B, void *out, int64_t rows,
                                int64_t rows_pad, int64_t kdim, int64_t n_tiles, int64_t n_groups, void *stream);
+// fixed-order reductions of the shape gradients (adjoint.hip): per-tile local gradients
+// [n_tiles][Lc2][Lc1][Lc0][3] summed per macro control point into grad [n_macro_ctrl][3]; and a
+// one-workgroup sum of x [n] into out[0]
+igamt_status launch_grad_reduce(igamt_plan *plan, const double *local_grad, double *grad, void *stream);
+igamt_status launch_sum(const double *x, int64_t n, double *out, void *stream);
 // rows of the transposed table (table columns padded to a multiple of the contraction's row block)
 inline int64_t transposed_rows(const igamt_plan *P) { return (P->Kp + 127) / 128 * 128; }
 }  // namespace igamt

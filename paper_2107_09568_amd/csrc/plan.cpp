@@ -495,6 +495,7 @@ extern "C" igamt_status igamt_set_tile_ctrl(igamt_plan *P, const double *ctrl) {
   P->ctrlT = c;
   P->tables_ready = false;
   P->load_table_ready = false;
+  P->volume_ready = false;
   if (P->dev.ready) return upload_tile_ctrl(P);
   return IGAMT_OK;
 }
