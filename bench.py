@@ -275,6 +275,23 @@ def bench_volume(torch, plan, steps, warmup):
             "volume_and_gradient_ms": float(np.median(st[:, 1])), "n_macro_ctrl": int(g.shape[0])}
 
 
+def bench_eproj(torch, plan, w):
+    """Sampled projection error (5^3 samples per tile) at degrees 2 and 4 on the assembly workload,
+    and the adaptive degree for tolerance 1e-3 (a host loop over the same kernel)."""
+    import time
+    out = {"workload": "assembly workload, 5^3 uniform samples per tile"}
+    for q in (2, 4):
+        plan.eproj(w.E, w.nu, q)
+        t0 = time.perf_counter()
+        e = plan.eproj(w.E, w.nu, q)
+        out[f"q{q}"] = {"E_proj": e, "ms": (time.perf_counter() - t0) * 1e3}
+    t0 = time.perf_counter()
+    q, e = plan.select_q(w.E, w.nu, 1e-3)
+    out["select_q_tol_1e-3"] = {"q": q, "E_proj": e, "ms": (time.perf_counter() - t0) * 1e3}
+    plan.check()
+    return out
+
+
 def bench_adjoint(torch, W, P, steps):
     """Shape gradient of u^T K u on the differentiation workload (16^3 uniform boxes, cubic macro net)."""
     w = W.make("cfg4")
@@ -501,6 +518,8 @@ def main():
     out["solve"] = bench_solve(torch, W, P, plan, w)
     log("bench: volume")
     out["volume"] = bench_volume(torch, plan, args.steps, args.warmup)
+    log("bench: projection error")
+    out["eproj"] = bench_eproj(torch, plan, w)
     if not args.no_extras:
         log("bench: shape gradient")
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)

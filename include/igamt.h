@@ -382,6 +382,25 @@ igamt_status igamt_volume_workspace_bytes(const igamt_plan *plan, int64_t *bytes
 igamt_status igamt_volume(igamt_plan *plan, double *d_tile_volumes, double *d_volume, double *d_grad,
                           void *d_workspace, void *stream);
 
+/* --- projection error and adaptive degree (Section 3.2.2 after eq. (48);
+ *     Section 3.3.1, eq. (59), (65)) --------------------------------------------
+ * igamt_eproj: E_proj(q) = max over tiles and samples of |A - Pi_q A|_F / |A|_F
+ *   (eq. (59)), A the macro field of eq. (37) for (E, nu), Pi_q its projection
+ *   onto the degree-q Bernstein space fitted on q + 1 Gauss-Legendre nodes per
+ *   direction, whatever the plan's own q; samples: the uniform grid
+ *   k / (n_sample - 1), k = 0 .. n_sample - 1, per direction of every tile's
+ *   box (2 <= n_sample <= 8; 0 <= q <= 6).  *e_proj on the host (the call
+ *   synchronises the stream); d_tile_e double [n_tiles] receives the per-tile
+ *   maxima if not NULL.  det J_M <= 0 raises the degeneracy flag.
+ * igamt_select_q: eq. (65), the first q from the macro degree to q_max with
+ *   E_proj(q) <= tol; *q_out = that q and *e_out its error, or *q_out = -1 and
+ *   *e_out = E_proj(q_max) when none meets tol.  A plan for the chosen degree
+ *   is then made with igamt_plan_create.                                       */
+igamt_status igamt_eproj(igamt_plan *plan, double E, double nu, int32_t q, int32_t n_sample, double *d_tile_e,
+                         double *e_proj, void *stream);
+igamt_status igamt_select_q(igamt_plan *plan, double E, double nu, double tol, int32_t q_max, int32_t n_sample,
+                            int32_t *q_out, double *e_out, void *stream);
+
 /* --- batches of designs ----------------------------------------------------
  * The same table steps for n_design designs of one tile family at once (same
  * knots, degree and pair set as the plan's reference tile, different control

@@ -412,6 +412,25 @@ class Plan:
                                  _stream()))
         return v, tv, g
 
+    # ---- projection error and adaptive degree (eq. (59), (65)) -----------------------------
+    def eproj(self, E, nu, q=None, n_sample=5, per_tile=False):
+        """E_proj (eq. (59)) at degree q (default the plan's); with per_tile, also the per-tile maxima."""
+        torch = _torch()
+        q = self.q if q is None else int(q)
+        te = torch.empty(self.n_tiles, dtype=torch.float64, device="cuda") if per_tile else None
+        e = C.c_double()
+        check(lib().igamt_eproj(self._h, float(E), float(nu), q, int(n_sample), _ptr(te) if per_tile else None,
+                                C.byref(e), _stream()))
+        return (e.value, te) if per_tile else e.value
+
+    def select_q(self, E, nu, tol=1e-3, q_max=6, n_sample=5):
+        """Eq. (65): (q, E_proj(q)) for the first q from the macro degree with E_proj <= tol, or
+        (None, E_proj(q_max))."""
+        q, e = C.c_int32(), C.c_double()
+        check(lib().igamt_select_q(self._h, float(E), float(nu), float(tol), int(q_max), int(n_sample),
+                                   C.byref(q), C.byref(e), _stream()))
+        return (None if q.value < 0 else q.value), e.value
+
     # ---- batches of designs of the plan's tile family -------------------------------------
     def _batch_ctrl(self, ctrls):
         torch = _torch()

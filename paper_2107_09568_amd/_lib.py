@@ -80,6 +80,8 @@ SIGNATURES = {
     "igamt_volume_table_get": (status, [vp, vp, vp, vp]),
     "igamt_volume_workspace_bytes": (status, [vp, P_i64]),
     "igamt_volume": (status, [vp, vp, vp, vp, vp, vp]),
+    "igamt_eproj": (status, [vp, f64, f64, i32, i32, vp, C.POINTER(f64), vp]),
+    "igamt_select_q": (status, [vp, f64, f64, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
     "igamt_pcg": (status, [vp, i32, vp, vp, vp, vp, f64, i32, vp, vp, C.POINTER(i32), C.POINTER(f64)]),
     "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),

@@ -86,7 +86,7 @@ void free_device(igamt_plan *P) {
   void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
                   d.table_h_scale, d.point_data, d.mirror_perm, d.pair_desc,
-                  d.batch_points, d.load_table, d.apply_rec, d.volume_data};
+                  d.batch_points, d.load_table, d.apply_rec, d.volume_data, d.eproj_buf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 3; ++k) {

@@ -1,0 +1,268 @@
+// Sampled projection error of the macro field and the adaptive projection degree
+// (Section 3.2.2 after eq. (48); Section 3.3.1, eq. (59), (65)).
+//
+// E_proj(q) = max over tiles t and samples xi of |A(xi) - Pi_q A(xi)|_F / |A(xi)|_F, with A the
+// macro field of eq. (37) (Cartesian form, as the fit) and Pi_q A its projection onto the degree-q
+// Bernstein space from q + 1 Gauss-Legendre nodes per direction (the fit of eq. (42) at degree q).
+// The samples are a uniform tensor grid with both ends, x_k = k / (n_s - 1), in box coordinates.
+// Per tile one 256-thread workgroup: F = J^-1 and D = det J at the fit nodes and the samples (LDS);
+// for each (i, j) block of A, the nine components' coefficients, then their values at the samples;
+// per sample the squared Frobenius error and norm accumulate over the blocks.  The maxima are
+// order-free, so the result is deterministic.  Eq. (65): the first q from the macro degree up
+// whose E_proj meets the tolerance (a host loop over this kernel).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_common.h"
+
+namespace igamt {
+
+constexpr int kMaxSample = 8;   // samples per direction
+
+struct EprojArgs {
+  const double *knots[3];
+  int nM[3];
+  const double *ctrl;
+  const double *box_a[3];
+  const double *box_h[3];
+  int tiles[3];
+  const double *fx;       // [nf] fit nodes
+  const double *fP;       // [q1][nf] 1-D projection operator
+  const double *sx;       // [n_s] sample coordinates
+  int q, nf, n_s;
+  double lam, mu;
+  double *tile_e;         // [n_tiles]
+  int32_t *flag;
+};
+
+__device__ inline double field_component(const double *FD, int i, int j, int aa, int bb, double lam, double mu) {
+  const double *Fi = FD + 3 * i, *Fj = FD + 3 * j;
+  const double fij = Fi[0] * Fj[0] + Fi[1] * Fj[1] + Fi[2] * Fj[2];
+  return FD[9] * (lam * Fi[aa] * Fj[bb] + (aa == bb ? mu * fij : 0.0) + mu * Fi[bb] * Fj[aa]);
+}
+
+template <int PM>
+__device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const double (&hx)[3], const double (&x)[3],
+                                double *FD, int64_t t) {
+  const double xh[3] = {ax[0] + hx[0] * x[0], ax[1] + hx[1] * x[1], ax[2] + hx[2] * x[2]};
+  double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+  int span[3];
+  spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int n = 0; n < 3; ++n) J[c][n] *= hx[n];
+  double F[3][3];
+  const double D = inv3(J, F);
+  if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag, (int32_t)t);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) FD[3 * r + c] = F[r][c];
+  FD[9] = D;
+}
+
+template <int PM>
+__global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, nf = a.nf, ns1 = a.n_s, q1 = a.q + 1;
+  const int nfit = nf * nf * nf, nsmp = ns1 * ns1 * ns1, npi = q1 * q1 * q1;
+  double *FDf = smem;                 // [nfit][10]
+  double *FDs = FDf + nfit * 10;      // [nsmp][10]
+  double *cf = FDs + nsmp * 10;       // [9][npi]
+  double *err2 = cf + 9 * npi;        // [nsmp]
+  double *nrm2 = err2 + nsmp;         // [nsmp]
+  __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
+  __shared__ double Bs[kMaxSample][kMaxQ + 1];
+  __shared__ double red[256];
+  const int64_t t = blockIdx.x;
+  const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
+                     (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
+  const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
+  const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
+  for (int e = tid; e < q1 * nf; e += 256) Pm[e] = a.fP[e];
+  for (int e = tid; e < ns1; e += 256) {
+    double B[kMaxQ + 1];
+    bernstein(a.q, a.sx[e], B);
+    for (int c = 0; c < q1; ++c) Bs[e][c] = B[c];
+  }
+  for (int s = tid; s < nfit; s += 256) {
+    const double x[3] = {a.fx[s % nf], a.fx[(s / nf) % nf], a.fx[s / (nf * nf)]};
+    point_FD<PM>(a, ax, hx, x, FDf + s * 10, t);
+  }
+  for (int k = tid; k < nsmp; k += 256) {
+    const double x[3] = {a.sx[k % ns1], a.sx[(k / ns1) % ns1], a.sx[k / (ns1 * ns1)]};
+    point_FD<PM>(a, ax, hx, x, FDs + k * 10, t);
+    err2[k] = 0.0;
+    nrm2[k] = 0.0;
+  }
+  __syncthreads();
+  for (int ij = 0; ij < 9; ++ij) {
+    const int i = ij / 3, j = ij % 3;
+    for (int e = tid; e < 9 * npi; e += 256) {
+      const int ab = e / npi, C = e % npi;
+      const int c0 = C % q1, c1 = (C / q1) % q1, c2 = C / (q1 * q1);
+      double s = 0.0;
+      for (int sp = 0; sp < nfit; ++sp) {
+        const int s0 = sp % nf, s1 = (sp / nf) % nf, s2 = sp / (nf * nf);
+        s += Pm[c0 * nf + s0] * Pm[c1 * nf + s1] * Pm[c2 * nf + s2] *
+             field_component(FDf + sp * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
+      }
+      cf[e] = s;
+    }
+    __syncthreads();
+    for (int k = tid; k < nsmp; k += 256) {
+      const int k0 = k % ns1, k1 = (k / ns1) % ns1, k2 = k / (ns1 * ns1);
+      double e2 = 0.0, n2 = 0.0;
+      for (int ab = 0; ab < 9; ++ab) {
+        const double ex = field_component(FDs + k * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
+        double pr = 0.0;
+        for (int C = 0; C < npi; ++C)
+          pr += cf[ab * npi + C] * Bs[k0][C % q1] * Bs[k1][(C / q1) % q1] * Bs[k2][C / (q1 * q1)];
+        e2 += (ex - pr) * (ex - pr);
+        n2 += ex * ex;
+      }
+      err2[k] += e2;
+      nrm2[k] += n2;
+    }
+    __syncthreads();
+  }
+  double m = 0.0;
+  for (int k = tid; k < nsmp; k += 256) m = fmax(m, sqrt(err2[k] / nrm2[k]));
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) a.tile_e[t] = red[0];
+}
+
+__global__ __launch_bounds__(256) void max_kernel(const double *x, int64_t n, double *out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, x[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// scratch layout (doubles): [0, n_tiles) per-tile errors; then fit nodes [kMaxFit], operator
+// [(kMaxQ+1) kMaxFit], samples [kMaxSample], result [1]
+static int64_t eproj_buf_doubles(const igamt_plan *P) {
+  return P->n_tiles + kMaxFit + (kMaxQ + 1) * kMaxFit + kMaxSample + 1;
+}
+
+static igamt_status eproj_run(igamt_plan *P, double E, double nu, int q, int n_s, double *d_tile_e, double *e_out,
+                              hipStream_t s) {
+  if (!P->dev.eproj_buf) IGAMT_HIP(hipMalloc((void **)&P->dev.eproj_buf, eproj_buf_doubles(P) * sizeof(double)));
+  double *buf = P->dev.eproj_buf;
+  double *d_fx = buf + P->n_tiles, *d_fP = d_fx + kMaxFit, *d_sx = d_fP + (kMaxQ + 1) * kMaxFit,
+         *d_res = d_sx + kMaxSample;
+  const int nf = q + 1;
+  std::vector<double> fx, fw, fP, sx(n_s);
+  gauss_legendre01(nf, fx, fw);
+  if (!projection_1d(q, fx, fw, fP)) { set_error("singular projection matrix"); return IGAMT_EINVAL; }
+  for (int k = 0; k < n_s; ++k) sx[k] = (double)k / (n_s - 1);
+  IGAMT_HIP(hipMemcpyAsync(d_fx, fx.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+  IGAMT_HIP(hipMemcpyAsync(d_fP, fP.data(), fP.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  IGAMT_HIP(hipMemcpyAsync(d_sx, sx.data(), n_s * sizeof(double), hipMemcpyHostToDevice, s));
+  EprojArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.knots[k] = P->dev.macro_knots[k];
+    a.nM[k] = P->nM[k];
+    a.box_a[k] = P->dev.box_a[k];
+    a.box_h[k] = P->dev.box_h[k];
+    a.tiles[k] = P->tiles[k];
+  }
+  a.ctrl = P->dev.macro_ctrl;
+  a.fx = d_fx;
+  a.fP = d_fP;
+  a.sx = d_sx;
+  a.q = q;
+  a.nf = nf;
+  a.n_s = n_s;
+  a.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  a.mu = E / (2.0 * (1.0 + nu));
+  a.tile_e = d_tile_e ? d_tile_e : buf;
+  a.flag = P->dev.flag;
+  const int q1 = q + 1, nfit = nf * nf * nf, nsmp = n_s * n_s * n_s, npi = q1 * q1 * q1;
+  const size_t shm = (size_t)(10 * nfit + 10 * nsmp + 9 * npi + 2 * nsmp) * sizeof(double);
+  const dim3 grid((unsigned)P->n_tiles), block(256);
+  switch (P->pM[0]) {
+#define EP_CASE(p)                                                                                        \
+  case p:                                                                                                 \
+    if (shm > 65536)                                                                                      \
+      IGAMT_HIP(hipFuncSetAttribute((const void *)eproj_kernel<p>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                    (int)shm));                                                           \
+    hipLaunchKernelGGL(eproj_kernel<p>, grid, block, shm, s, a);                                          \
+    break;
+    EP_CASE(1)
+    EP_CASE(2)
+    EP_CASE(3)
+    EP_CASE(4)
+    EP_CASE(5)
+    EP_CASE(6)
+#undef EP_CASE
+    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+  }
+  IGAMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, a.tile_e, P->n_tiles, d_res);
+  IGAMT_LAUNCH_CHECK();
+  IGAMT_HIP(hipMemcpyAsync(e_out, d_res, sizeof(double), hipMemcpyDeviceToHost, s));
+  IGAMT_HIP(hipStreamSynchronize(s));   // the host vectors above and *e_out are used until here
+  return IGAMT_OK;
+}
+
+static igamt_status eproj_checks(igamt_plan *P, double E, double nu, int n_s) {
+  if (!(E > 0.0) || !std::isfinite(E) || !(nu > -1.0 && nu < 0.5)) {
+    set_error("E must be positive and -1 < nu < 0.5");
+    return IGAMT_EINVAL;
+  }
+  if (n_s < 2 || n_s > kMaxSample) { set_error("samples per direction must be in [2, 8]"); return IGAMT_EINVAL; }
+  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
+    set_error("macro maps with different degrees per direction are not supported");
+    return IGAMT_EUNSUPPORTED;
+  }
+  return ensure_device(P);
+}
+
+}  // namespace igamt
+
+using namespace igamt;
+
+extern "C" igamt_status igamt_eproj(igamt_plan *P, double E, double nu, int32_t q, int32_t n_sample,
+                                    double *d_tile_e, double *e_proj, void *stream) {
+  if (!P || !e_proj) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (q < 0 || q > kMaxQ) { set_error("projection degree must be in [0, 6]"); return IGAMT_EINVAL; }
+  igamt_status st = eproj_checks(P, E, nu, n_sample);
+  if (st) return st;
+  return eproj_run(P, E, nu, q, n_sample, d_tile_e, e_proj, (hipStream_t)stream);
+}
+
+extern "C" igamt_status igamt_select_q(igamt_plan *P, double E, double nu, double tol, int32_t q_max,
+                                       int32_t n_sample, int32_t *q_out, double *e_out, void *stream) {
+  if (!P || !q_out || !e_out) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (!(tol >= 0.0) || !std::isfinite(tol)) { set_error("tolerance must be finite and non-negative"); return IGAMT_EINVAL; }
+  igamt_status st = eproj_checks(P, E, nu, n_sample);
+  if (st) return st;
+  const int q0 = P->pM[0];
+  if (q_max < q0 || q_max > kMaxQ) { set_error("q_max must be in [macro degree, 6]"); return IGAMT_EINVAL; }
+  double e = 0.0;
+  for (int q = q0; q <= q_max; ++q) {
+    if ((st = eproj_run(P, E, nu, q, n_sample, nullptr, &e, (hipStream_t)stream))) return st;
+    if (e <= tol) {
+      *q_out = q;
+      *e_out = e;
+      return IGAMT_OK;
+    }
+  }
+  *q_out = -1;
+  *e_out = e;
+  return IGAMT_OK;
+}

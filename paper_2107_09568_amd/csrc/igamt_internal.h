@@ -84,6 +84,7 @@ struct DevicePtrs {
   int32_t *apply_rec = nullptr;      // [n_pairs] A | B << 16
   int32_t *apply_perm = nullptr;     // per chunk: slots sorted by destination row (16 bits each)
   int32_t *apply_seg = nullptr;      // per chunk: row | segment end << 16
+  double *eproj_buf = nullptr;       // projection-error scratch: per-tile errors, nodes, operator, result
   double *volume_data = nullptr;     // volume table t^h [npi], folded table t_pi [npi], sample weights [n_fit^3]
 };
 
@@ -136,6 +137,9 @@ struct igamt_plan {
 namespace igamt {
 // host helpers (plan.cpp)
 void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w);
+// 1-D projection operator P ((q+1) x n, row-major) onto the degree-q Bernstein basis by the
+// weighted discrete L2 fit at the points x with weights w (eq. (23)-(24)); false if singular
+bool projection_1d(int q, const std::vector<double> &x, const std::vector<double> &w, std::vector<double> &P);
 int find_span_host(const std::vector<double> &U, int n, int p, double x);
 // device helpers (device.hip)
 igamt_status ensure_device(igamt_plan *plan);

@@ -74,8 +74,7 @@ static double binom(int n, int k) {
 }
 
 // Solve (V^T W V) P = V^T W for the 1-D projection operator P ((q+1) x n).
-static bool projection_1d(int q, const std::vector<double> &x, const std::vector<double> &w,
-                          std::vector<double> &P) {
+bool projection_1d(int q, const std::vector<double> &x, const std::vector<double> &w, std::vector<double> &P) {
   const int m = q + 1, n = (int)x.size();
   std::vector<double> V(n * m);
   for (int s = 0; s < n; ++s)
