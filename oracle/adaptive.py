@@ -33,7 +33,7 @@ def tile_field_at(w, t: int, x1: np.ndarray) -> np.ndarray:
     a = [boxes[0][0][tx], boxes[1][0][ty], boxes[2][0][tz]]
     h = [boxes[0][1][tx], boxes[1][1][ty], boxes[2][1][tz]]
     _, J = eval_volume_grid(w.macro.degree, w.macro.knots, w.macro.ctrl,
-                            a[0] + h[0] * x1, a[1] + h[1] * x1, a[2] + h[2] * x1)
+                            a[0] + h[0] * x1, a[1] + h[1] * x1, a[2] + h[2] * x1, weights=w.macro.weights)
     J = J.reshape(-1, 3, 3) * np.array(h)[None, None, :]
     return macro_field(J, lam, mu).reshape(len(J), 81)
 

@@ -64,7 +64,9 @@ def tile_box(w, t):
 
 
 def grad_uKu(w, table, pairs, u, tiles=None):
-    """d(u^T K^pi u)/d m, shape like w.macro.ctrl (n_z, n_y, n_x, 3)."""
+    """d(u^T K^pi u)/d m, shape like w.macro.ctrl (n_z, n_y, n_x, 3) (B-spline maps)."""
+    if getattr(w.macro, "weights", None) is not None:
+        raise ValueError("the control-point derivative here is for B-spline macro maps")
     lam, mu = lame(w.E, w.nu)
     P = projection_operator(w.q, w.n_fit)
     x, _ = gauss01(w.n_fit)

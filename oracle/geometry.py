@@ -16,37 +16,64 @@ import numpy as np
 from .basis import bspline_basis, n_basis, nonempty_spans
 
 
-def eval_volume_grid(degree, knots, ctrl, xs, ys, zs):
+def _rational(X, J, W, dW):
+    """Quotient rule for a NURBS map from the homogeneous sums A = sum w N P (X, J here) and
+    W = sum w N: M = A / W, dM/dx_k = (dA/dx_k - M dW/dx_k) / W."""
+    M = X / W[..., None]
+    Jr = (J - M[..., :, None] * dW[..., None, :]) / W[..., None, None]
+    return M, Jr
+
+
+def eval_volume_grid(degree, knots, ctrl, xs, ys, zs, weights=None):
     """Map value X and Jacobian J on the tensor grid xs x ys x zs (each 1-D).
 
-    ctrl has shape (n_z, n_y, n_x, 3).  Returns X with shape (len(zs), len(ys), len(xs), 3)
+    ctrl has shape (n_z, n_y, n_x, 3); weights (n_z, n_y, n_x) makes the map a NURBS
+    (R_i = w_i N_i / sum_j w_j N_j).  Returns X with shape (len(zs), len(ys), len(xs), 3)
     and J with shape (len(zs), len(ys), len(xs), 3, 3), J[..., c, k] = d X_c / d x_k.
     """
     Bx, dBx = bspline_basis(knots[0], degree[0], xs, deriv=True)
     By, dBy = bspline_basis(knots[1], degree[1], ys, deriv=True)
     Bz, dBz = bspline_basis(knots[2], degree[2], zs, deriv=True)
     c = np.asarray(ctrl, dtype=np.float64)
+    if weights is not None:
+        wt = np.asarray(weights, dtype=np.float64)
+        c = c * wt[..., None]
     X = np.einsum("zk,yj,xi,kjic->zyxc", Bz, By, Bx, c, optimize=True)
     J = np.empty(X.shape + (3,))
     J[..., 0] = np.einsum("zk,yj,xi,kjic->zyxc", Bz, By, dBx, c, optimize=True)
     J[..., 1] = np.einsum("zk,yj,xi,kjic->zyxc", Bz, dBy, Bx, c, optimize=True)
     J[..., 2] = np.einsum("zk,yj,xi,kjic->zyxc", dBz, By, Bx, c, optimize=True)
-    return X, J
+    if weights is None:
+        return X, J
+    W = np.einsum("zk,yj,xi,kji->zyx", Bz, By, Bx, wt, optimize=True)
+    dW = np.stack([np.einsum("zk,yj,xi,kji->zyx", Bz, By, dBx, wt, optimize=True),
+                   np.einsum("zk,yj,xi,kji->zyx", Bz, dBy, Bx, wt, optimize=True),
+                   np.einsum("zk,yj,xi,kji->zyx", dBz, By, Bx, wt, optimize=True)], axis=-1)
+    return _rational(X, J, W, dW)
 
 
-def eval_volume_points(degree, knots, ctrl, pts):
-    """Map value and Jacobian at scattered points pts (P, 3)."""
+def eval_volume_points(degree, knots, ctrl, pts, weights=None):
+    """Map value and Jacobian at scattered points pts (P, 3) (weights as in eval_volume_grid)."""
     pts = np.asarray(pts, dtype=np.float64)
     Bx, dBx = bspline_basis(knots[0], degree[0], pts[:, 0], deriv=True)
     By, dBy = bspline_basis(knots[1], degree[1], pts[:, 1], deriv=True)
     Bz, dBz = bspline_basis(knots[2], degree[2], pts[:, 2], deriv=True)
     c = np.asarray(ctrl, dtype=np.float64)
+    if weights is not None:
+        wt = np.asarray(weights, dtype=np.float64)
+        c = c * wt[..., None]
     X = np.einsum("pk,pj,pi,kjic->pc", Bz, By, Bx, c, optimize=True)
     J = np.empty(X.shape + (3,))
     J[..., 0] = np.einsum("pk,pj,pi,kjic->pc", Bz, By, dBx, c, optimize=True)
     J[..., 1] = np.einsum("pk,pj,pi,kjic->pc", Bz, dBy, Bx, c, optimize=True)
     J[..., 2] = np.einsum("pk,pj,pi,kjic->pc", dBz, By, Bx, c, optimize=True)
-    return X, J
+    if weights is None:
+        return X, J
+    W = np.einsum("pk,pj,pi,kji->p", Bz, By, Bx, wt, optimize=True)
+    dW = np.stack([np.einsum("pk,pj,pi,kji->p", Bz, By, dBx, wt, optimize=True),
+                   np.einsum("pk,pj,pi,kji->p", Bz, dBy, Bx, wt, optimize=True),
+                   np.einsum("pk,pj,pi,kji->p", dBz, By, Bx, wt, optimize=True)], axis=-1)
+    return _rational(X, J, W, dW)
 
 
 def tile_boxes_1d(knots, n_tiles: int, box_mode: int):
@@ -124,6 +151,6 @@ def composed_control_points(w) -> np.ndarray:
         tx, ty, tz = tile_index(w, t)
         a = np.array([boxes[0][0][tx], boxes[1][0][ty], boxes[2][0][tz]])
         h = np.array([boxes[0][1][tx], boxes[1][1][ty], boxes[2][1][tz]])
-        X, _ = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * tc)
+        X, _ = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * tc, w.macro.weights)
         out[tile_global_indices(w, t)] = X
     return out

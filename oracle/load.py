@@ -144,7 +144,7 @@ def load_coefficients(w, t: int, body, traction, P=None, P2=None) -> np.ndarray:
     # body: samples at the tensor GL nodes (x fastest), |det J_M^(t)|
     x, _ = gauss01(nf)
     _, J = eval_volume_grid(w.macro.degree, w.macro.knots, w.macro.ctrl, a[0] + h[0] * x, a[1] + h[1] * x,
-                            a[2] + h[2] * x)
+                            a[2] + h[2] * x, weights=w.macro.weights)
     det = np.abs(np.linalg.det(J.reshape(-1, 3, 3) * h[None, None, :]))
     out[0] = (P @ (det[:, None] * body[None, :])).T
     # tractions on the touched macro faces
@@ -155,7 +155,7 @@ def load_coefficients(w, t: int, body, traction, P=None, P2=None) -> np.ndarray:
         pts[:, d] = side
         pts[:, u] = PU.ravel()
         pts[:, v] = PV.ravel()
-        _, Jp = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * pts)
+        _, Jp = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * pts, weights=w.macro.weights)
         Jp = Jp * h[None, None, :]
         area = np.linalg.norm(np.cross(Jp[:, :, u], Jp[:, :, v]), axis=1)
         cf = P2 @ (area[:, None] * traction[f][None, :])              # (q1^2, 3), index c_u + q1 c_v
@@ -205,7 +205,7 @@ def standard_load(w, body, traction, n_g: int = None) -> np.ndarray:
         for e, box in micro_elements(tile):
             act = np.array(active_functions(tile, e))
             R, _, X, JT, wts = element_points(tile, box, n_g)
-            _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X)
+            _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X, weights=w.macro.weights)
             J = (JM * h[None, None, :]) @ JT
             det = np.abs(np.linalg.det(J))
             ft[act] += np.einsum("g,gA->A", wts * det, R[:, act])[:, None] * body[None, :]
@@ -233,7 +233,7 @@ def standard_load(w, body, traction, n_g: int = None) -> np.ndarray:
                     ctrl = tile.ctrl.reshape(-1, 3)
                     X = R @ ctrl
                     JT = np.einsum("gAk,Ac->gck", dR, ctrl)
-                    _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X)
+                    _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X, weights=w.macro.weights)
                     J = (JM * h[None, None, :]) @ JT
                     area = np.linalg.norm(np.cross(J[:, :, u], J[:, :, v]), axis=1)
                     wt = np.einsum("v,u->vu", (hv - lv) * wg, (hu - lu) * wg).ravel()

@@ -54,7 +54,7 @@ def tile_macro_jacobians(w, t: int):
     a = [boxes[0][0][tx], boxes[1][0][ty], boxes[2][0][tz]]
     h = [boxes[0][1][tx], boxes[1][1][ty], boxes[2][1][tz]]
     _, J = eval_volume_grid(w.macro.degree, w.macro.knots, w.macro.ctrl,
-                            a[0] + h[0] * x, a[1] + h[1] * x, a[2] + h[2] * x)
+                            a[0] + h[0] * x, a[1] + h[1] * x, a[2] + h[2] * x, weights=w.macro.weights)
     J = J.reshape(-1, 3, 3) * np.array(h)[None, None, :]
     return J
 

@@ -52,7 +52,7 @@ def tile_matrix_standard(w, t: int, n_g: int = None) -> np.ndarray:
     for e, box in micro_elements(w.tile):
         act = np.array(active_functions(w.tile, e))
         R, dR, X, JT, wts = element_points(w.tile, box, n_g)
-        _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X)
+        _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X, weights=w.macro.weights)
         JM = JM * h[None, None, :]
         J = JM @ JT
         det = np.linalg.det(J)

@@ -82,7 +82,7 @@ def volume_standard(w, n_g: int = None) -> float:
         h = np.array([boxes[0][1][tx], boxes[1][1][ty], boxes[2][1][tz]])
         for _, box in micro_elements(w.tile):
             _, _, X, JT, wts = element_points(w.tile, box, n_g)
-            _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X)
+            _, JM = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * X, weights=w.macro.weights)
             v += float(np.sum(wts * np.abs(np.linalg.det(JT)) * np.abs(np.linalg.det(JM * h[None, None, :]))))
     return v
 
@@ -93,7 +93,9 @@ def adjoint_field(q: int, t_pi: np.ndarray, pts: np.ndarray) -> np.ndarray:
 
 
 def volume_grad(w, t_pi: np.ndarray) -> np.ndarray:
-    """dV/dm (eq. (66)), shape (n_z, n_y, n_x, 3) like the macro control points."""
+    """dV/dm (eq. (66)), shape (n_z, n_y, n_x, 3) like the macro control points (B-spline maps)."""
+    if w.macro.weights is not None:
+        raise ValueError("the control-point derivative here is for B-spline macro maps")
     nz, ny, nx = w.macro.ctrl.shape[:3]
     grad = np.zeros((nz, ny, nx, 3))
     xg, _ = gauss01(w.n_fit)

@@ -25,7 +25,7 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "Spline3D", "Workload", "open_knots", "greville", "make", "CONFIGS",
+    "Spline3D", "Workload", "open_knots", "greville", "make", "CONFIGS", "nurbs_quarter_torus",
     "tile_family", "family_params", "random_displacement",
 ]
 
@@ -36,10 +36,12 @@ class Spline3D:
 
     degree[k], knots[k] (clamped, non-decreasing, on [0, 1]) for k = x, y, z and
     ctrl of shape (n_z, n_y, n_x, 3): control point (i, j, k) is ctrl[k, j, i].
+    weights: None for a B-spline, else positive NURBS weights of shape (n_z, n_y, n_x).
     """
     degree: Tuple[int, int, int]
     knots: Tuple[np.ndarray, np.ndarray, np.ndarray]
     ctrl: np.ndarray
+    weights: Optional[np.ndarray] = None
 
     @property
     def n_ctrl(self) -> Tuple[int, int, int]:
@@ -147,6 +149,37 @@ def _torus_sector(u, v, w):
     return rho * np.cos(phi), rho * np.sin(phi), 0.25 * (2.0 * w - 1.0)
 
 
+def nurbs_quarter_torus(R: float = 2.0, r1: float = 0.5, r2: float = 1.0) -> Spline3D:
+    """A quarter of a thick-walled torus tube, exact as a degree-2 NURBS with one element per
+    direction: x = tube angle theta in [0, pi/2] (a rational quarter circle), y = radius rho in
+    [r1, r2] (linear, written at degree 2), z = revolution angle phi in [0, pi/2] (a rational
+    quarter circle).  The point is (d cos phi, d sin phi, rho sin theta), d = R + rho cos theta.
+    Its volume is (pi/2) (R (r2^2 - r1^2) pi/4 + (r2^3 - r1^3) / 3)."""
+    s = np.sqrt(0.5)
+    arc = [(1.0, 0.0), (1.0, 1.0), (0.0, 1.0)]       # quarter-circle control points on the unit circle
+    warc = [1.0, s, 1.0]
+    rho = [r1, 0.5 * (r1 + r2), r2]
+    ctrl = np.zeros((3, 3, 3, 3))
+    wts = np.zeros((3, 3, 3))
+    for k in range(3):                                  # phi
+        for j in range(3):                              # rho
+            for i in range(3):                          # theta
+                d = R + rho[j] * arc[i][0]
+                z = rho[j] * arc[i][1]
+                ctrl[k, j, i] = (d * arc[k][0], d * arc[k][1], z)
+                wts[k, j, i] = warc[i] * warc[k]
+    knots = tuple(np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0]) for _ in range(3))
+    return Spline3D((2, 2, 2), knots, ctrl, wts)
+
+
+def _nurbs_torus(seed: int, n_boxes: int = 4) -> Workload:
+    rng = np.random.default_rng(seed)
+    macro = nurbs_quarter_torus()
+    tile = identity_spline((2, 2, 2), (3, 3, 3))
+    _pull_interior(tile, rng, 0.2)
+    return Workload("nurbs_torus", macro, tile, (n_boxes, n_boxes, n_boxes), 1, 2, 3, 3, seed=seed)
+
+
 def family_params(seed: int, count: int) -> np.ndarray:
     """Design parameters (pinch, a_x, a_y, a_z) ~ U(0, 0.3)^4 for the parameterised tile family."""
     rng = np.random.default_rng(seed)
@@ -226,9 +259,11 @@ CONFIGS = {
 
 def make(name: str, **kw) -> Workload:
     """Build a named workload.  Keyword arguments shrink the large ones for CPU-side tests:
-    cfg3(n_el=...), cfg4(n_boxes=...), cfg5(n_el=...)."""
-    seeds = {"cfg1": 1001, "cfg2": 1002, "cfg3": 1003, "cfg4": 1004, "cfg5": 1005}
-    fn = {"cfg1": _cfg1, "cfg2": _cfg2, "cfg3": _cfg3, "cfg4": _cfg4, "cfg5": _cfg5}[name]
+    cfg3(n_el=...), cfg4(n_boxes=...), cfg5(n_el=...); nurbs_torus(n_boxes=...) is the exact NURBS
+    quarter torus under uniform boxes."""
+    seeds = {"cfg1": 1001, "cfg2": 1002, "cfg3": 1003, "cfg4": 1004, "cfg5": 1005, "nurbs_torus": 1006}
+    fn = {"cfg1": _cfg1, "cfg2": _cfg2, "cfg3": _cfg3, "cfg4": _cfg4, "cfg5": _cfg5,
+          "nurbs_torus": _nurbs_torus}[name]
     return fn(seeds[name], **kw)
 
 
