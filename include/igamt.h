@@ -48,15 +48,21 @@ typedef enum { IGAMT_F64 = 0, IGAMT_F32 = 1, IGAMT_BF16X3 = 2, IGAMT_F16X3 = 3 }
 
 typedef struct igamt_plan igamt_plan;
 
-/* Trivariate B-spline (eq. (2)-(4)).  host memory.
+/* Trivariate B-spline or NURBS (eq. (1)-(4)).  host memory.
  * knots[k]: n_ctrl[k] + degree[k] + 1 values, clamped (first and last
  * degree+1 values equal), non-decreasing, spanning [0, 1].
- * ctrl: [n_ctrl[2]][n_ctrl[1]][n_ctrl[0]][3], x fastest.                     */
+ * ctrl: [n_ctrl[2]][n_ctrl[1]][n_ctrl[0]][3], x fastest.
+ * weights: NULL for a B-spline; else [n_ctrl[2]][n_ctrl[1]][n_ctrl[0]]
+ *   positive NURBS weights (rational basis w_i N_i / sum_j w_j N_j).  Accepted
+ *   for the macro map (fit, load vector, volume, projection error; the shape
+ *   gradients return IGAMT_EUNSUPPORTED); the tile must be a B-spline
+ *   (IGAMT_EUNSUPPORTED).                                                     */
 typedef struct {
   int32_t degree[3];
   int32_t n_ctrl[3];
   const double *knots[3];
   const double *ctrl;
+  const double *weights;
 } igamt_spline3d;
 
 /* Tile grid and method parameters.

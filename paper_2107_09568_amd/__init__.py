@@ -41,11 +41,16 @@ def _prec(p):
     return PRECISIONS[p] if isinstance(p, str) else int(p)
 
 
-def _spline(degree, knots, ctrl, keep):
+def _spline(degree, knots, ctrl, keep, weights=None):
     s = _lib.Spline3D()
     ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
     ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
     keep.extend([ctrl] + ks)
+    if weights is not None:
+        weights = np.ascontiguousarray(weights, dtype=np.float64)
+        assert weights.shape == ctrl.shape[:3], "one weight per control point"
+        keep.append(weights)
+        s.weights = weights.ctypes.data_as(_lib.P_f64)
     for d in range(3):
         s.degree[d] = int(degree[d])
         s.knots[d] = ks[d].ctypes.data_as(_lib.P_f64)
@@ -62,8 +67,8 @@ class Plan:
 
     def __init__(self, macro, tile, tiles, box_mode=0, q=2, n_fit=None, n_gauss=3):
         keep = []
-        m = _spline(macro.degree, macro.knots, macro.ctrl, keep)
-        t = _spline(tile.degree, tile.knots, tile.ctrl, keep)
+        m = _spline(macro.degree, macro.knots, macro.ctrl, keep, getattr(macro, "weights", None))
+        t = _spline(tile.degree, tile.knots, tile.ctrl, keep, getattr(tile, "weights", None))
         d = _lib.PlanDesc()
         for k in range(3):
             d.tiles[k] = int(tiles[k])

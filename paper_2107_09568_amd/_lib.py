@@ -19,7 +19,7 @@ P_f64 = C.POINTER(C.c_double)
 
 
 class Spline3D(C.Structure):
-    _fields_ = [("degree", i32 * 3), ("n_ctrl", i32 * 3), ("knots", P_f64 * 3), ("ctrl", P_f64)]
+    _fields_ = [("degree", i32 * 3), ("n_ctrl", i32 * 3), ("knots", P_f64 * 3), ("ctrl", P_f64), ("weights", P_f64)]
 
 
 class PlanDesc(C.Structure):

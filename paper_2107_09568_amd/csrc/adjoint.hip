@@ -69,6 +69,7 @@ struct FitAdjArgs {
   const double *knots[3];
   int nM[3];
   const double *ctrl;
+  const double *wts;      // NURBS weights of the macro map, or null (B-spline)
   const double *box_a[3];
   const double *box_h[3];
   const int32_t *ctrl_lo[3];
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PM + 1], dN[3][PM + 1];
     int span[3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -377,6 +378,10 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
+  if (!P->wM.empty()) {
+    set_error("the shape gradient is for B-spline macro maps (NURBS weights given)");
+    return IGAMT_EUNSUPPORTED;
+  }
   if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
     set_error("macro maps with different degrees per direction are not supported");
     return IGAMT_EUNSUPPORTED;
@@ -427,6 +432,7 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
     f.Lc[k] = P->Lc[k];
   }
   f.ctrl = P->dev.macro_ctrl;
+  f.wts = P->dev.macro_w;
   f.n_tiles = P->n_tiles;
   f.fx = P->dev.fit_x;
   f.fP = P->dev.fit_P;

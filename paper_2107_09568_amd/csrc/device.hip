@@ -47,6 +47,7 @@ igamt_status ensure_device(igamt_plan *P) {
     UP(d.ctrl_tiles[k], P->ctrl_tiles[k]);
   }
   UP(d.macro_ctrl, P->ctrlM);
+  if (!P->wM.empty()) UP(d.macro_w, P->wM);
   UP(d.tile_ctrl, P->ctrlT);
   UP(d.tile_grev, P->grevT);
   UP(d.fit_x, P->fit_x);
@@ -83,7 +84,7 @@ void free_device(igamt_plan *P) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(d.device);
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {d.macro_ctrl, d.fit_x, d.fit_P, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
+  void *ptrs[] = {d.macro_ctrl, d.macro_w, d.fit_x, d.fit_P, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
                   d.table_h_scale, d.point_data, d.mirror_perm, d.pair_desc,
                   d.batch_points, d.load_table, d.apply_rec, d.volume_data, d.eproj_buf};

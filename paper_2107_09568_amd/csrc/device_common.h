@@ -169,18 +169,20 @@ __device__ inline double f16_scale_for(double bound) {
   return ldexp(1.0, 14 - e);  // bound * scale < 2^14
 }
 
-// Jacobian of the trivariate B-spline map with control points ctrl
-// ([n2][n1][n0][3], x fastest) at parameter x (degree P in every direction);
-// also returns the span and the 1-D basis values/derivatives used.
+// Jacobian of the trivariate spline map with control points ctrl ([n2][n1][n0][3], x fastest) at
+// parameter x (degree P in every direction); also returns the span and the 1-D basis values and
+// derivatives used.  w: NULL for a B-spline map, else the NURBS weights ([n2][n1][n0]); the map is
+// then A / W with A = sum w_i N_i P_i, W = sum w_i N_i, and dM/dx_k = (dA/dx_k - M dW/dx_k) / W.
 template <int P>
 __device__ inline void spline_jacobian(const double *const *knots, const int *n, const double *__restrict__ ctrl,
-                                       const double (&x)[3], double (&J)[3][3], int (&span)[3],
-                                       double (&N)[3][P + 1], double (&dN)[3][P + 1]) {
+                                       const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
+                                       int (&span)[3], double (&N)[3][P + 1], double (&dN)[3][P + 1]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     span[k] = find_span(knots[k], n[k], P, x[k]);
     bspline_ders<P>(knots[k], span[k], x[k], N[k], dN[k]);
   }
+  double A[3] = {0.0, 0.0, 0.0}, W = 0.0, dW[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) J[c][0] = J[c][1] = J[c][2] = 0.0;
   for (int rz = 0; rz <= P; ++rz) {
@@ -193,15 +195,32 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
 #pragma unroll
       for (int rx = 0; rx <= P; ++rx) {
         const int ix = span[0] - P + rx;
-        const double *c = ctrl + 3 * (ix + (int64_t)n[0] * (iy + (int64_t)n[1] * iz));
-        const double g0 = dN[0][rx] * wyz, g1 = N[0][rx] * dy, g2 = N[0][rx] * dz;
+        const int64_t id = ix + (int64_t)n[0] * (iy + (int64_t)n[1] * iz);
+        const double *c = ctrl + 3 * id;
+        const double wi = w ? w[id] : 1.0;
+        const double v = N[0][rx] * wyz * wi;
+        const double g0 = dN[0][rx] * wyz * wi, g1 = N[0][rx] * dy * wi, g2 = N[0][rx] * dz * wi;
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
+          A[cc] += c[cc] * v;
           J[cc][0] += c[cc] * g0;
           J[cc][1] += c[cc] * g1;
           J[cc][2] += c[cc] * g2;
         }
+        W += v;
+        dW[0] += g0;
+        dW[1] += g1;
+        dW[2] += g2;
       }
+    }
+  }
+  if (w) {
+    const double r = 1.0 / W;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const double M = A[cc] * r;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) J[cc][k] = (J[cc][k] - M * dW[k]) * r;
     }
   }
 }

@@ -24,6 +24,7 @@ struct EprojArgs {
   const double *knots[3];
   int nM[3];
   const double *ctrl;
+  const double *wts;      // NURBS weights of the macro map, or null (B-spline)
   const double *box_a[3];
   const double *box_h[3];
   int tiles[3];
@@ -48,7 +49,7 @@ __device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const
   const double xh[3] = {ax[0] + hx[0] * x[0], ax[1] + hx[1] * x[1], ax[2] + hx[2] * x[2]};
   double J[3][3], N[3][PM + 1], dN[3][PM + 1];
   int span[3];
-  spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+  spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -181,6 +182,7 @@ static igamt_status eproj_run(igamt_plan *P, double E, double nu, int q, int n_s
     a.tiles[k] = P->tiles[k];
   }
   a.ctrl = P->dev.macro_ctrl;
+  a.wts = P->dev.macro_w;
   a.fx = d_fx;
   a.fP = d_fP;
   a.sx = d_sx;

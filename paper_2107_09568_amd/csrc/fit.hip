@@ -17,6 +17,7 @@ struct FitArgs {
   const double *knots[3];
   int nM[3];
   const double *ctrl;
+  const double *wts;      // NURBS weights of the macro map, or null (B-spline)
   const double *box_a[3];
   const double *box_h[3];
   int tiles[3];
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
     int span[3];
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -210,6 +211,7 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
     a.tiles[k] = P->tiles[k];
   }
   a.ctrl = P->dev.macro_ctrl;
+  a.wts = P->dev.macro_w;
   a.n_tiles = P->n_tiles;
   a.fx = P->dev.fit_x;
   a.fP = P->dev.fit_P;

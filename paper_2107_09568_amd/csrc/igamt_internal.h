@@ -48,6 +48,7 @@ struct DevicePtrs {
   int device = -1;
   double *macro_knots[3] = {nullptr, nullptr, nullptr};
   double *macro_ctrl = nullptr;
+  double *macro_w = nullptr;         // NURBS weights of the macro map (null: B-spline)
   double *box_a[3] = {nullptr, nullptr, nullptr};
   double *box_h[3] = {nullptr, nullptr, nullptr};
   double *fit_x = nullptr;           // [n_fit] Gauss nodes on [0,1]
@@ -95,6 +96,7 @@ struct igamt_plan {
   int pM[3], nM[3];
   std::vector<double> kM[3];
   std::vector<double> ctrlM;
+  std::vector<double> wM;             // NURBS weights [nz][ny][nx] (empty: B-spline)
   // reference tile
   int pT[3], nT[3];
   std::vector<double> kT[3];

@@ -113,6 +113,7 @@ struct LoadFitArgs {
   const double *knots[3];
   int nM[3];
   const double *ctrl;
+  const double *wts;      // NURBS weights of the macro map, or null (B-spline)
   const double *box_a[3];
   const double *box_h[3];
   int tiles[3];
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PM + 1], dN[3][PM + 1];
     int span[3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
         xh[v] = ax[v] + hx[v] * a.fx[sv];
         double J[3][3], N[3][PM + 1], dN[3][PM + 1];
         int span[3];
-        spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+        spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
         const double gu[3] = {J[0][u] * hx[u], J[1][u] * hx[u], J[2][u] * hx[u]};
         const double gv[3] = {J[0][v] * hx[v], J[1][v] * hx[v], J[2][v] * hx[v]};
         const double n0 = gu[1] * gv[2] - gu[2] * gv[1], n1 = gu[2] * gv[0] - gu[0] * gv[2],
@@ -267,6 +268,7 @@ static igamt_status load_fit_launch(igamt_plan *P, const double *body, const dou
   for (int f = 0; f < 6; ++f)
     for (int k = 0; k < 3; ++k) a.traction[f][k] = traction[3 * f + k];
   a.ctrl = P->dev.macro_ctrl;
+  a.wts = P->dev.macro_w;
   a.n_tiles = P->n_tiles;
   a.fx = P->dev.fit_x;
   a.fP = P->dev.fit_P;

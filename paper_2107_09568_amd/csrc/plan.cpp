@@ -171,6 +171,16 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
   if (st) return st;
   st = check_spline(tile, "tile", P->pT, P->nT, P->kT, P->ctrlT);
   if (st) return st;
+  P->wM.clear();
+  if (macro->weights) {   // NURBS macro map: positive, finite weights
+    P->wM.assign(macro->weights, macro->weights + P->ctrlM.size() / 3);
+    for (double v : P->wM)
+      if (!(v > 0.0) || !std::isfinite(v)) { set_error("macro: NURBS weights must be positive and finite"); return IGAMT_EINVAL; }
+  }
+  if (tile->weights) {
+    set_error("NURBS reference tiles are not supported (the tile is a B-spline)");
+    return IGAMT_EUNSUPPORTED;
+  }
   if (!desc) { set_error("NULL descriptor"); return IGAMT_EINVAL; }
   // tile knots: no repeated interior knots; elements per direction
   for (int d = 0; d < 3; ++d) {

@@ -71,6 +71,7 @@ struct VolumeTileArgs {
   const double *knots[3];
   int nM[3];
   const double *ctrl;
+  const double *wts;      // NURBS weights of the macro map, or null (B-spline)
   const double *box_a[3];
   const double *box_h[3];
   const int32_t *ctrl_lo[3];
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PM + 1], dN[3][PM + 1];
     int span[3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, xh, J, span, N, dN);
+    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -270,6 +271,10 @@ extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, doub
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->volume_ready) { set_error("volume table not built"); return IGAMT_ESTATE; }
+  if (d_grad && !P->wM.empty()) {
+    set_error("the volume gradient is for B-spline macro maps (NURBS weights given)");
+    return IGAMT_EUNSUPPORTED;
+  }
   if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
     set_error("macro maps with different degrees per direction are not supported");
     return IGAMT_EUNSUPPORTED;
@@ -289,6 +294,7 @@ extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, doub
     a.Lc[k] = P->Lc[k];
   }
   a.ctrl = P->dev.macro_ctrl;
+  a.wts = P->dev.macro_w;
   a.fx = P->dev.fit_x;
   a.g = P->dev.volume_data + 2 * P->npi;
   a.nf = P->n_fit;

@@ -180,6 +180,18 @@ def test_plan_limits(P):
     assert e.value.code == -6
     ok = W.identity_spline((2, 2, 2), (14, 2, 2))         # 16: the largest supported
     P.Plan(w.macro, ok, w.tiles, 0, 2, 3, 3).close()
+    # NURBS: positive weights on the macro map only
+    import dataclasses
+    torus = W.nurbs_quarter_torus()
+    P.Plan(torus, w.tile, (2, 2, 2), 1, 2, 3, 3).close()
+    bad = dataclasses.replace(torus, weights=-torus.weights)
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(bad, w.tile, (2, 2, 2), 1, 2, 3, 3)
+    assert e.value.code == -1
+    rational_tile = dataclasses.replace(w.tile, weights=np.ones(w.tile.ctrl.shape[:3]))
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, rational_tile, w.tiles, 0, 2, 3, 3)
+    assert e.value.code == -6
     # a tile whose displacements do not fit the matrix-free product's LDS (1024 control points)
     from paper_2107_09568_amd import _lib
     wide = P.Plan(w.macro, W.identity_spline((2, 2, 2), (14, 14, 2)), w.tiles, 0, 2, 3, 3)
