@@ -292,6 +292,28 @@ def bench_eproj(torch, plan, w):
     return out
 
 
+def bench_nurbs(torch, W, P, steps, warmup):
+    """The FP64 assembly step on the exact NURBS quarter torus under 32^3 uniform boxes (same tile
+    count, pair count and table as the assembly workload; the fit evaluates the rational map)."""
+    w = W.make("nurbs_torus", n_boxes=32)
+    plan = P.Plan.from_workload(w)
+    plan.tables_build()
+    cb, bb = plan.workspace_bytes("f64")
+    ws = plan._empty_bytes(cb + bb)
+    vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    fit = lambda: plan.fit(w.E, w.nu, "f64", out=ws)
+    step = lambda: plan.assemble(w.E, w.nu, "f64", values=vals, workspace=ws)
+    for _ in range(warmup):
+        step()
+    st = _timed(torch, steps, [fit, step])
+    plan.check()
+    out = {"workload": "NURBS quarter torus, 32^3 uniform boxes, q=2", "n_tiles": plan.n_tiles,
+           "fit_ms": float(np.median(st[:, 0])), "step_ms": float(np.median(st[:, 1]))}
+    del ws, vals, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_adjoint(torch, W, P, steps):
     """Shape gradient of u^T K u on the differentiation workload (16^3 uniform boxes, cubic macro net)."""
     w = W.make("cfg4")
@@ -520,6 +542,9 @@ def main():
     out["volume"] = bench_volume(torch, plan, args.steps, args.warmup)
     log("bench: projection error")
     out["eproj"] = bench_eproj(torch, plan, w)
+    if not args.no_extras:
+        log("bench: NURBS macro map")
+        out["nurbs"] = bench_nurbs(torch, W, P, args.steps, args.warmup)
     if not args.no_extras:
         log("bench: shape gradient")
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)

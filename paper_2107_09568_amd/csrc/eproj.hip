@@ -104,11 +104,16 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
     for (int e = tid; e < 9 * npi; e += 256) {
       const int ab = e / npi, C = e % npi;
       const int c0 = C % q1, c1 = (C / q1) % q1, c2 = C / (q1 * q1);
+      const int aa = ab / 3, bb = ab % 3;
       double s = 0.0;
-      for (int sp = 0; sp < nfit; ++sp) {
-        const int s0 = sp % nf, s1 = (sp / nf) % nf, s2 = sp / (nf * nf);
-        s += Pm[c0 * nf + s0] * Pm[c1 * nf + s1] * Pm[c2 * nf + s2] *
-             field_component(FDf + sp * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
+      int sp = 0;
+      for (int s2 = 0; s2 < nf; ++s2) {
+        const double p2 = Pm[c2 * nf + s2];
+        for (int s1 = 0; s1 < nf; ++s1) {
+          const double p12 = p2 * Pm[c1 * nf + s1];
+          for (int s0 = 0; s0 < nf; ++s0, ++sp)
+            s += p12 * Pm[c0 * nf + s0] * field_component(FDf + sp * 10, i, j, aa, bb, a.lam, a.mu);
+        }
       }
       cf[e] = s;
     }
@@ -118,9 +123,16 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
       double e2 = 0.0, n2 = 0.0;
       for (int ab = 0; ab < 9; ++ab) {
         const double ex = field_component(FDs + k * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
+        const double *c = cf + ab * npi;
         double pr = 0.0;
-        for (int C = 0; C < npi; ++C)
-          pr += cf[ab * npi + C] * Bs[k0][C % q1] * Bs[k1][(C / q1) % q1] * Bs[k2][C / (q1 * q1)];
+        int C = 0;
+        for (int c2 = 0; c2 < q1; ++c2) {
+          const double b2 = Bs[k2][c2];
+          for (int c1 = 0; c1 < q1; ++c1) {
+            const double b12 = b2 * Bs[k1][c1];
+            for (int c0 = 0; c0 < q1; ++c0, ++C) pr += c[C] * b12 * Bs[k0][c0];
+          }
+        }
         e2 += (ex - pr) * (ex - pr);
         n2 += ex * ex;
       }
