@@ -17,7 +17,7 @@ import numpy as np
 
 from .geometry import eval_volume_grid, tile_boxes, tile_index
 from .macro_field import lame, macro_field
-from .projection import bernstein3, tile_coefficients
+from .projection import bernstein3, degrees, tile_coefficients
 
 
 def sample_grid(n_s: int) -> np.ndarray:
@@ -50,10 +50,11 @@ def tile_eproj(w, t: int, n_s: int) -> float:
     return float(np.max(np.linalg.norm(A - PA, axis=1) / np.linalg.norm(A, axis=1)))
 
 
-def eproj(w, q: int = None, n_s: int = 5) -> float:
-    """E_proj (eq. (59)) at projection degree q (default w.q), fit on q + 1 points per direction."""
+def eproj(w, q=None, n_s: int = 5) -> float:
+    """E_proj (eq. (59)) at projection degree q (default w.q; an int or a triple), fit on
+    max_k q_k + 1 points per direction (a least-squares fit in the directions of lower degree)."""
     if q is not None:
-        w = dataclasses.replace(w, q=q, n_fit=q + 1)
+        w = dataclasses.replace(w, q=q, n_fit=max(degrees(q)) + 1)
     return max(tile_eproj(w, t, n_s) for t in range(w.n_tiles))
 
 
@@ -67,3 +68,26 @@ def select_q(w, tol: float, q_max: int = 6, n_s: int = 5):
         if e <= tol:
             return q, e
     return None, e
+
+
+def select_q_aniso(w, tol: float, q_max: int = 6, n_s: int = 5):
+    """The anisotropic reading of eq. (65) (the paper's twisted square, degrees (3, 3, 4)): start
+    from the macro map's degrees per direction; while E_proj > tol, raise by one the direction
+    whose raise gives the lowest E_proj (ties: the lowest direction index), up to q_max each.
+    Returns (degrees, E_proj) or (None, E_proj of the last degrees tried)."""
+    q = list(w.macro.degree)
+    e = eproj(w, tuple(q), n_s)
+    while e > tol:
+        best = None
+        for k in range(3):
+            if q[k] >= q_max:
+                continue
+            trial = list(q)
+            trial[k] += 1
+            et = eproj(w, tuple(trial), n_s)
+            if best is None or et < best[0]:
+                best = (et, trial)
+        if best is None:
+            return None, e
+        e, q = best
+    return tuple(q), e

@@ -21,11 +21,25 @@ from .geometry import eval_volume_grid, tile_boxes, tile_index
 from .macro_field import lame, macro_field
 
 
-def bernstein3(q: int, pts: np.ndarray) -> np.ndarray:
-    """N_C at points pts (P, 3); column C = c1 + (q+1)(c2 + (q+1) c3)."""
-    B1 = bernstein(q, pts[:, 0])
-    B2 = bernstein(q, pts[:, 1])
-    B3 = bernstein(q, pts[:, 2])
+def degrees(q):
+    """Projection degrees per direction: an int q is (q, q, q); a triple is anisotropic (the
+    paper's (3, 3, 4) for the twisted square)."""
+    if np.ndim(q) == 0:
+        return (int(q),) * 3
+    return tuple(int(v) for v in q)
+
+
+def n_pi(q) -> int:
+    """Dimension of the projection space, prod_k (q_k + 1) (eq. (21))."""
+    return int(np.prod([d + 1 for d in degrees(q)]))
+
+
+def bernstein3(q, pts: np.ndarray) -> np.ndarray:
+    """N_C at points pts (P, 3); column C = c1 + (q1+1)(c2 + (q2+1) c3), degrees q per direction."""
+    qx, qy, qz = degrees(q)
+    B1 = bernstein(qx, pts[:, 0])
+    B2 = bernstein(qy, pts[:, 1])
+    B3 = bernstein(qz, pts[:, 2])
     return np.einsum("pk,pj,pi->pkji", B3, B2, B1).reshape(len(pts), -1)
 
 
@@ -38,7 +52,7 @@ def fit_points(n_fit: int):
     return pts, (WX * WY * WZ).ravel()
 
 
-def projection_operator(q: int, n_fit: int) -> np.ndarray:
+def projection_operator(q, n_fit: int) -> np.ndarray:
     """Matrix P (n_pi x n_fit^3) with d = P f(samples): P = M_pi^-1 N^T W (eq. (23)-(24))."""
     pts, wts = fit_points(n_fit)
     N = bernstein3(q, pts)                    # (S, n_pi)

@@ -16,7 +16,7 @@ import itertools
 import numpy as np
 
 from .basis import bspline_basis, gauss01, nonempty_spans, support_elements
-from .projection import bernstein3
+from .projection import bernstein3, n_pi
 
 
 def micro_elements(tile):
@@ -78,14 +78,14 @@ def element_points(tile, box, n_g):
     return R, dR, X, J, w
 
 
-def stiffness_table(tile, q: int, n_g: int, pairs=None) -> np.ndarray:
-    """mat[K] of eq. (57): shape (n_nz, 9 (q+1)^3), rows ordered as ``pairs``."""
+def stiffness_table(tile, q, n_g: int, pairs=None) -> np.ndarray:
+    """mat[K] of eq. (57): shape (n_nz, 9 n_pi), rows ordered as ``pairs``; q an int or a triple."""
     if pairs is None:
         pairs = pair_set(tile)
     nT = int(np.prod(tile.n_ctrl))
     pidx = -np.ones((nT, nT), dtype=np.int64)
     pidx[pairs[:, 0], pairs[:, 1]] = np.arange(len(pairs))
-    npi = (q + 1) ** 3
+    npi = n_pi(q)
     table = np.zeros((len(pairs), 9 * npi))
     for e, box in micro_elements(tile):
         act = np.array(active_functions(tile, e))

@@ -1,0 +1,79 @@
+"""Pins for anisotropic projection degrees (q_x, q_y, q_z) (Section 3.3.4, the twisted square's
+(3, 3, 4); eq. (21), (23)-(24), (57), (59), (65)) in the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adaptive, assembly, projection, standard, tables
+
+
+def test_isotropic_triple_is_the_scalar_degree():
+    rng = np.random.default_rng(2)
+    pts = rng.random((20, 3))
+    np.testing.assert_array_equal(projection.bernstein3((2, 2, 2), pts), projection.bernstein3(2, pts))
+    assert projection.n_pi((1, 2, 3)) == 24
+    tile = W.make("cfg1").tile
+    pairs = tables.pair_set(tile)
+    np.testing.assert_array_equal(tables.stiffness_table(tile, (1, 1, 1), 3, pairs),
+                                  tables.stiffness_table(tile, 1, 3, pairs))
+
+
+def test_projection_reproduces_per_direction_degrees():
+    """The tensor L2 projection with degrees (q_x, q_y, q_z) reproduces x^a y^b z^c exactly when
+    a <= q_x, b <= q_y, c <= q_z, and not when one exponent exceeds its degree."""
+    q = (1, 3, 2)
+    P = projection.projection_operator(q, 4)
+    pts, _ = projection.fit_points(4)
+    rng = np.random.default_rng(5)
+    chk = rng.random((30, 3))
+    Bc = projection.bernstein3(q, chk)
+    for (a, b, c), ok in [((1, 3, 2), True), ((0, 2, 1), True), ((2, 0, 0), False), ((0, 0, 3), False)]:
+        f = pts[:, 0] ** a * pts[:, 1] ** b * pts[:, 2] ** c
+        g = Bc @ (P @ f)
+        exact = chk[:, 0] ** a * chk[:, 1] ** b * chk[:, 2] ** c
+        err = np.abs(g - exact).max()
+        assert (err < 1e-13) == ok, ((a, b, c), err)
+
+
+def test_degree_elevation_across_anisotropic_tables():
+    """For a field g in Q_(1,2,1), the anisotropic table times g's (1,2,1) coefficients equals the
+    isotropic q = 2 table times g's q = 2 coefficients: both sum the same integrals of g, which
+    checks the per-direction Bernstein indexing of the table."""
+    tile = W.make("cfg1").tile
+    pairs = tables.pair_set(tile)
+    Ta = tables.stiffness_table(tile, (1, 2, 1), 3, pairs)
+    Ti = tables.stiffness_table(tile, 2, 3, pairs)
+    pts, _ = projection.fit_points(3)
+    g = 1.0 + 0.3 * pts[:, 0] - 0.7 * pts[:, 1] ** 2 * pts[:, 2] + 0.2 * pts[:, 0] * pts[:, 1] * pts[:, 2]
+    da = projection.projection_operator((1, 2, 1), 3) @ g
+    di = projection.projection_operator(2, 3) @ g
+    for ij in range(9):
+        ya = Ta[:, ij::9] @ da
+        yi = Ti[:, ij::9] @ di
+        assert np.abs(ya - yi).max() <= 1e-13 * np.abs(yi).max()
+
+
+def test_affine_map_exact_with_anisotropic_degrees():
+    A = np.array([[1.3, 0.2, -0.1], [0.1, 0.8, 0.15], [-0.05, 0.1, 1.1]])
+    macro = W.affine_macro((2, 2, 2), (2, 2, 2), A, np.array([0.5, -1.0, 2.0]))
+    w = W.Workload("affine", macro, W.make("cfg1").tile, (2, 2, 2), 0, (0, 1, 2), 3, 3)
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    blocks = assembly.tile_blocks(T, projection.all_coefficients(w))
+    for t in (0, 5):
+        ref = standard.tile_block_standard(w, t, pairs)
+        assert np.linalg.norm(blocks[t] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_twisted_square_selects_an_anisotropic_degree():
+    """The twist varies along the axis only: raising the section degrees leaves E_proj unchanged,
+    raising the axial degree lowers it; the anisotropic selection stops at (2, 2, 3) for 1e-3 with
+    36 Bernstein functions where the isotropic rule needs q = 3 (64)."""
+    w = W.make("twisted_square")
+    e222 = adaptive.eproj(w, (2, 2, 2))
+    assert adaptive.eproj(w, (3, 3, 2)) == pytest.approx(e222, rel=0.05)
+    assert adaptive.eproj(w, (2, 2, 3)) < 0.2 * e222
+    q, e = adaptive.select_q_aniso(w, 1e-3)
+    assert q == (2, 2, 3) and e <= 1e-3
+    qi, _ = adaptive.select_q(w, 1e-3)
+    assert qi == 3 and projection.n_pi(q) < projection.n_pi(qi)

@@ -172,6 +172,21 @@ def nurbs_quarter_torus(R: float = 2.0, r1: float = 0.5, r2: float = 1.0) -> Spl
     return Spline3D((2, 2, 2), knots, ctrl, wts)
 
 
+def _twist(u, v, w):
+    # a square section 1 x 1 twisted by a quarter turn along a length-3 axis
+    a = 0.5 * np.pi * w
+    x, y = u - 0.5, v - 0.5
+    return x * np.cos(a) - y * np.sin(a), x * np.sin(a) + y * np.cos(a), 3.0 * w
+
+
+def _twisted_square(seed: int, n_el: int = 2) -> Workload:
+    rng = np.random.default_rng(seed)
+    macro = _mapped_spline((2, 2, 2), (1, 1, 3), _twist)
+    tile = identity_spline((2, 2, 2), (2, 2, 2))
+    _pull_interior(tile, rng, 0.2)
+    return Workload("twisted_square", macro, tile, (1, 1, 3), 0, 2, 3, 3, seed=seed)
+
+
 def _nurbs_torus(seed: int, n_boxes: int = 4) -> Workload:
     rng = np.random.default_rng(seed)
     macro = nurbs_quarter_torus()
@@ -260,10 +275,12 @@ CONFIGS = {
 def make(name: str, **kw) -> Workload:
     """Build a named workload.  Keyword arguments shrink the large ones for CPU-side tests:
     cfg3(n_el=...), cfg4(n_boxes=...), cfg5(n_el=...); nurbs_torus(n_boxes=...) is the exact NURBS
-    quarter torus under uniform boxes."""
-    seeds = {"cfg1": 1001, "cfg2": 1002, "cfg3": 1003, "cfg4": 1004, "cfg5": 1005, "nurbs_torus": 1006}
+    quarter torus under uniform boxes; twisted_square is a square section twisted along its axis
+    (a macro field far smoother across the section than along the axis)."""
+    seeds = {"cfg1": 1001, "cfg2": 1002, "cfg3": 1003, "cfg4": 1004, "cfg5": 1005, "nurbs_torus": 1006,
+             "twisted_square": 1007}
     fn = {"cfg1": _cfg1, "cfg2": _cfg2, "cfg3": _cfg3, "cfg4": _cfg4, "cfg5": _cfg5,
-          "nurbs_torus": _nurbs_torus}[name]
+          "nurbs_torus": _nurbs_torus, "twisted_square": _twisted_square}[name]
     return fn(seeds[name], **kw)
 
 
