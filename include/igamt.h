@@ -75,13 +75,23 @@ typedef struct {
  *             >= q + 1 (q + 1 = interpolation at the Gauss nodes, which equals
  *             the discrete L2 projection of eq. (23)-(24) with that rule).
  * n_gauss   : Gauss-Legendre points per direction per micro element for the
- *             lookup table (eq. (52)), 1..8.                                  */
+ *             lookup table (eq. (52)), 1..8.
+ * anisotropic, q_dir[3]: with anisotropic != 0, the projection degrees per
+ *             direction (Section 3.3.4), each 0..6 (q is then ignored);
+ *             n_pi = prod_k (q_k + 1) and n_fit >= max_k q_k + 1 (a
+ *             least-squares fit in the directions of lower degree).  With
+ *             anisotropic = 0, q in every direction and q_dir is not read.  Plans whose degrees differ per direction run the
+ *             stiffness path (tables, fit, contraction, scatter, products,
+ *             solve); the load vector, volume and shape gradients return
+ *             IGAMT_EUNSUPPORTED for them.                                   */
 typedef struct {
   int32_t tiles[3];
   int32_t box_mode;
   int32_t q;
   int32_t n_fit;
   int32_t n_gauss;
+  int32_t anisotropic;
+  int32_t q_dir[3];
 } igamt_plan_desc;
 
 /* Sizes derived from a plan. */
@@ -406,6 +416,16 @@ igamt_status igamt_eproj(igamt_plan *plan, double E, double nu, int32_t q, int32
                          double *e_proj, void *stream);
 igamt_status igamt_select_q(igamt_plan *plan, double E, double nu, double tol, int32_t q_max, int32_t n_sample,
                             int32_t *q_out, double *e_out, void *stream);
+/* Anisotropic forms (Section 3.3.4).  igamt_eproj_aniso: as igamt_eproj with
+ * degrees q[3] per direction (host array), fitted on max_k q_k + 1 nodes per
+ * direction.  igamt_select_q_aniso: from the macro degrees per direction, while
+ * E_proj > tol raise by one the direction (below q_max) whose raise gives the
+ * lowest E_proj (ties: the lowest direction); q_out[3] the degrees found (all
+ * -1 when every direction reached q_max first) and *e_out their E_proj.      */
+igamt_status igamt_eproj_aniso(igamt_plan *plan, double E, double nu, const int32_t *q, int32_t n_sample,
+                               double *d_tile_e, double *e_proj, void *stream);
+igamt_status igamt_select_q_aniso(igamt_plan *plan, double E, double nu, double tol, int32_t q_max,
+                                  int32_t n_sample, int32_t *q_out, double *e_out, void *stream);
 
 /* --- batches of designs ----------------------------------------------------
  * The same table steps for n_design designs of one tile family at once (same

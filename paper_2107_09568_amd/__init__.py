@@ -73,8 +73,12 @@ class Plan:
         for k in range(3):
             d.tiles[k] = int(tiles[k])
         d.box_mode = int(box_mode)
-        d.q = int(q)
-        d.n_fit = int(q + 1 if n_fit is None else n_fit)
+        qd = (int(q),) * 3 if np.ndim(q) == 0 else tuple(int(v) for v in q)
+        d.q = max(qd)
+        d.anisotropic = int(np.ndim(q) != 0)
+        for k in range(3):
+            d.q_dir[k] = qd[k]
+        d.n_fit = int(max(qd) + 1 if n_fit is None else n_fit)
         d.n_gauss = int(n_gauss)
         h = C.c_void_p()
         check(lib().igamt_plan_create(C.byref(m), C.byref(t), C.byref(d), C.byref(h)))
@@ -86,7 +90,8 @@ class Plan:
         s = _lib.Sizes()
         check(lib().igamt_plan_sizes(h, C.byref(s)))
         self.sizes = {f: getattr(s, f) for f, _ in _lib.Sizes._fields_}
-        self.q = int(q)
+        self.q_dir = qd                     # projection degrees per direction
+        self.q = max(qd)
 
     @classmethod
     def from_workload(cls, w):
@@ -419,13 +424,15 @@ class Plan:
 
     # ---- projection error and adaptive degree (eq. (59), (65)) -----------------------------
     def eproj(self, E, nu, q=None, n_sample=5, per_tile=False):
-        """E_proj (eq. (59)) at degree q (default the plan's); with per_tile, also the per-tile maxima."""
+        """E_proj (eq. (59)) at degree q (an int or a triple; default the plan's); with per_tile, also
+        the per-tile maxima."""
         torch = _torch()
-        q = self.q if q is None else int(q)
+        q = self.q_dir if q is None else q
+        qd = np.ascontiguousarray(((int(q),) * 3 if np.ndim(q) == 0 else tuple(q)), dtype=np.int32)
         te = torch.empty(self.n_tiles, dtype=torch.float64, device="cuda") if per_tile else None
         e = C.c_double()
-        check(lib().igamt_eproj(self._h, float(E), float(nu), q, int(n_sample), _ptr(te) if per_tile else None,
-                                C.byref(e), _stream()))
+        check(lib().igamt_eproj_aniso(self._h, float(E), float(nu), qd.ctypes.data_as(C.c_void_p), int(n_sample),
+                                      _ptr(te) if per_tile else None, C.byref(e), _stream()))
         return (e.value, te) if per_tile else e.value
 
     def select_q(self, E, nu, tol=1e-3, q_max=6, n_sample=5):
@@ -435,6 +442,15 @@ class Plan:
         check(lib().igamt_select_q(self._h, float(E), float(nu), float(tol), int(q_max), int(n_sample),
                                    C.byref(q), C.byref(e), _stream()))
         return (None if q.value < 0 else q.value), e.value
+
+    def select_q_aniso(self, E, nu, tol=1e-3, q_max=6, n_sample=5):
+        """Anisotropic degrees (q_x, q_y, q_z) by the per-direction raise rule, with their E_proj, or
+        (None, E_proj) when every direction reached q_max."""
+        q = np.zeros(3, dtype=np.int32)
+        e = C.c_double()
+        check(lib().igamt_select_q_aniso(self._h, float(E), float(nu), float(tol), int(q_max), int(n_sample),
+                                         q.ctypes.data_as(C.c_void_p), C.byref(e), _stream()))
+        return (None if q[0] < 0 else tuple(int(v) for v in q)), e.value
 
     # ---- batches of designs of the plan's tile family -------------------------------------
     def _batch_ctrl(self, ctrls):

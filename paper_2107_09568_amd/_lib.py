@@ -23,7 +23,8 @@ class Spline3D(C.Structure):
 
 
 class PlanDesc(C.Structure):
-    _fields_ = [("tiles", i32 * 3), ("box_mode", i32), ("q", i32), ("n_fit", i32), ("n_gauss", i32)]
+    _fields_ = [("tiles", i32 * 3), ("box_mode", i32), ("q", i32), ("n_fit", i32), ("n_gauss", i32),
+                ("anisotropic", i32), ("q_dir", i32 * 3)]
 
 
 class Sizes(C.Structure):
@@ -82,6 +83,8 @@ SIGNATURES = {
     "igamt_volume": (status, [vp, vp, vp, vp, vp, vp]),
     "igamt_eproj": (status, [vp, f64, f64, i32, i32, vp, C.POINTER(f64), vp]),
     "igamt_select_q": (status, [vp, f64, f64, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
+    "igamt_eproj_aniso": (status, [vp, f64, f64, vp, i32, vp, C.POINTER(f64), vp]),
+    "igamt_select_q_aniso": (status, [vp, f64, f64, f64, i32, i32, vp, C.POINTER(f64), vp]),
     "igamt_pcg": (status, [vp, i32, vp, vp, vp, vp, f64, i32, vp, vp, C.POINTER(i32), C.POINTER(f64)]),
     "igamt_tables_build_batch": (status, [vp, vp, i32, vp, vp, vp]),
     "igamt_tables_build_rows_batch": (status, [vp, vp, i32, vp, i32, vp, vp]),

@@ -378,6 +378,7 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
+  if (P->aniso) { set_error("the shape gradient uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   if (!P->wM.empty()) {
     set_error("the shape gradient is for B-spline macro maps (NURBS weights given)");
     return IGAMT_EUNSUPPORTED;

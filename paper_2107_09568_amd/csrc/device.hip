@@ -52,6 +52,7 @@ igamt_status ensure_device(igamt_plan *P) {
   UP(d.tile_grev, P->grevT);
   UP(d.fit_x, P->fit_x);
   UP(d.fit_P, P->fit_P);
+  UP(d.fit_P3, P->fit_P3);
   UP(d.gauss_x, P->gauss_x);
   UP(d.gauss_w, P->gauss_w);
   UP(d.pairs, P->pairs);
@@ -84,7 +85,7 @@ void free_device(igamt_plan *P) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(d.device);
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {d.macro_ctrl, d.macro_w, d.fit_x, d.fit_P, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
+  void *ptrs[] = {d.macro_ctrl, d.macro_w, d.fit_x, d.fit_P, d.fit_P3, d.tile_ctrl, d.tile_grev, d.gauss_x, d.gauss_w, d.pairs, d.pair_lut,
                   d.flag, d.table, d.table_t, d.table_f32, d.table_t_f32, d.table_bf, d.table_h,
                   d.table_h_scale, d.point_data, d.mirror_perm, d.pair_desc,
                   d.batch_points, d.load_table, d.apply_rec, d.volume_data, d.eproj_buf};

@@ -29,9 +29,9 @@ struct EprojArgs {
   const double *box_h[3];
   int tiles[3];
   const double *fx;       // [nf] fit nodes
-  const double *fP;       // [q1][nf] 1-D projection operator
+  const double *fP;       // per-direction 1-D projection operators [q1[0]][nf], [q1[1]][nf], [q1[2]][nf]
   const double *sx;       // [n_s] sample coordinates
-  int q, nf, n_s;
+  int q1[3], nf, n_s;
   double lam, mu;
   double *tile_e;         // [n_tiles]
   int32_t *flag;
@@ -67,26 +67,28 @@ __device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const
 template <int PM>
 __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
   extern __shared__ double smem[];
-  const int tid = threadIdx.x, nf = a.nf, ns1 = a.n_s, q1 = a.q + 1;
-  const int nfit = nf * nf * nf, nsmp = ns1 * ns1 * ns1, npi = q1 * q1 * q1;
+  const int tid = threadIdx.x, nf = a.nf, ns1 = a.n_s, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
+  const int nfit = nf * nf * nf, nsmp = ns1 * ns1 * ns1, npi = q1x * q1y * q1z;
   double *FDf = smem;                 // [nfit][10]
   double *FDs = FDf + nfit * 10;      // [nsmp][10]
   double *cf = FDs + nsmp * 10;       // [9][npi]
   double *err2 = cf + 9 * npi;        // [nsmp]
   double *nrm2 = err2 + nsmp;         // [nsmp]
-  __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
-  __shared__ double Bs[kMaxSample][kMaxQ + 1];
+  __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
+  __shared__ double Bs[3][kMaxSample][kMaxQ + 1];
   __shared__ double red[256];
   const int64_t t = blockIdx.x;
   const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
                      (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
   const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
   const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
-  for (int e = tid; e < q1 * nf; e += 256) Pm[e] = a.fP[e];
-  for (int e = tid; e < ns1; e += 256) {
+  for (int k = 0, off = 0; k < 3; off += a.q1[k] * nf, ++k)
+    for (int e = tid; e < a.q1[k] * nf; e += 256) Pm[k][e] = a.fP[off + e];
+  for (int e = tid; e < 3 * ns1; e += 256) {
+    const int k = e / ns1, m = e % ns1;
     double B[kMaxQ + 1];
-    bernstein(a.q, a.sx[e], B);
-    for (int c = 0; c < q1; ++c) Bs[e][c] = B[c];
+    bernstein(a.q1[k] - 1, a.sx[m], B);
+    for (int c = 0; c < a.q1[k]; ++c) Bs[k][m][c] = B[c];
   }
   for (int s = tid; s < nfit; s += 256) {
     const double x[3] = {a.fx[s % nf], a.fx[(s / nf) % nf], a.fx[s / (nf * nf)]};
@@ -103,16 +105,16 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
     const int i = ij / 3, j = ij % 3;
     for (int e = tid; e < 9 * npi; e += 256) {
       const int ab = e / npi, C = e % npi;
-      const int c0 = C % q1, c1 = (C / q1) % q1, c2 = C / (q1 * q1);
+      const int c0 = C % q1x, c1 = (C / q1x) % q1y, c2 = C / (q1x * q1y);
       const int aa = ab / 3, bb = ab % 3;
       double s = 0.0;
       int sp = 0;
       for (int s2 = 0; s2 < nf; ++s2) {
-        const double p2 = Pm[c2 * nf + s2];
+        const double p2 = Pm[2][c2 * nf + s2];
         for (int s1 = 0; s1 < nf; ++s1) {
-          const double p12 = p2 * Pm[c1 * nf + s1];
+          const double p12 = p2 * Pm[1][c1 * nf + s1];
           for (int s0 = 0; s0 < nf; ++s0, ++sp)
-            s += p12 * Pm[c0 * nf + s0] * field_component(FDf + sp * 10, i, j, aa, bb, a.lam, a.mu);
+            s += p12 * Pm[0][c0 * nf + s0] * field_component(FDf + sp * 10, i, j, aa, bb, a.lam, a.mu);
         }
       }
       cf[e] = s;
@@ -126,11 +128,11 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
         const double *c = cf + ab * npi;
         double pr = 0.0;
         int C = 0;
-        for (int c2 = 0; c2 < q1; ++c2) {
-          const double b2 = Bs[k2][c2];
-          for (int c1 = 0; c1 < q1; ++c1) {
-            const double b12 = b2 * Bs[k1][c1];
-            for (int c0 = 0; c0 < q1; ++c0, ++C) pr += c[C] * b12 * Bs[k0][c0];
+        for (int c2 = 0; c2 < q1z; ++c2) {
+          const double b2 = Bs[2][k2][c2];
+          for (int c1 = 0; c1 < q1y; ++c1) {
+            const double b12 = b2 * Bs[1][k1][c1];
+            for (int c0 = 0; c0 < q1x; ++c0, ++C) pr += c[C] * b12 * Bs[0][k0][c0];
           }
         }
         e2 += (ex - pr) * (ex - pr);
@@ -165,22 +167,27 @@ __global__ __launch_bounds__(256) void max_kernel(const double *x, int64_t n, do
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// scratch layout (doubles): [0, n_tiles) per-tile errors; then fit nodes [kMaxFit], operator
-// [(kMaxQ+1) kMaxFit], samples [kMaxSample], result [1]
+// scratch layout (doubles): [0, n_tiles) per-tile errors; then fit nodes [kMaxFit], operators
+// [3 (kMaxQ+1) kMaxFit], samples [kMaxSample], result [1]
 static int64_t eproj_buf_doubles(const igamt_plan *P) {
-  return P->n_tiles + kMaxFit + (kMaxQ + 1) * kMaxFit + kMaxSample + 1;
+  return P->n_tiles + kMaxFit + 3 * (kMaxQ + 1) * kMaxFit + kMaxSample + 1;
 }
 
-static igamt_status eproj_run(igamt_plan *P, double E, double nu, int q, int n_s, double *d_tile_e, double *e_out,
-                              hipStream_t s) {
+// E_proj for degrees q[3], fitted on max_k q_k + 1 Gauss-Legendre nodes per direction
+static igamt_status eproj_run(igamt_plan *P, double E, double nu, const int (&q)[3], int n_s, double *d_tile_e,
+                              double *e_out, hipStream_t s) {
   if (!P->dev.eproj_buf) IGAMT_HIP(hipMalloc((void **)&P->dev.eproj_buf, eproj_buf_doubles(P) * sizeof(double)));
   double *buf = P->dev.eproj_buf;
-  double *d_fx = buf + P->n_tiles, *d_fP = d_fx + kMaxFit, *d_sx = d_fP + (kMaxQ + 1) * kMaxFit,
+  double *d_fx = buf + P->n_tiles, *d_fP = d_fx + kMaxFit, *d_sx = d_fP + 3 * (kMaxQ + 1) * kMaxFit,
          *d_res = d_sx + kMaxSample;
-  const int nf = q + 1;
+  const int nf = std::max(q[0], std::max(q[1], q[2])) + 1;
   std::vector<double> fx, fw, fP, sx(n_s);
   gauss_legendre01(nf, fx, fw);
-  if (!projection_1d(q, fx, fw, fP)) { set_error("singular projection matrix"); return IGAMT_EINVAL; }
+  for (int k = 0; k < 3; ++k) {
+    std::vector<double> Pk;
+    if (!projection_1d(q[k], fx, fw, Pk)) { set_error("singular projection matrix"); return IGAMT_EINVAL; }
+    fP.insert(fP.end(), Pk.begin(), Pk.end());
+  }
   for (int k = 0; k < n_s; ++k) sx[k] = (double)k / (n_s - 1);
   IGAMT_HIP(hipMemcpyAsync(d_fx, fx.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
   IGAMT_HIP(hipMemcpyAsync(d_fP, fP.data(), fP.size() * sizeof(double), hipMemcpyHostToDevice, s));
@@ -198,14 +205,14 @@ static igamt_status eproj_run(igamt_plan *P, double E, double nu, int q, int n_s
   a.fx = d_fx;
   a.fP = d_fP;
   a.sx = d_sx;
-  a.q = q;
+  for (int k = 0; k < 3; ++k) a.q1[k] = q[k] + 1;
   a.nf = nf;
   a.n_s = n_s;
   a.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   a.mu = E / (2.0 * (1.0 + nu));
   a.tile_e = d_tile_e ? d_tile_e : buf;
   a.flag = P->dev.flag;
-  const int q1 = q + 1, nfit = nf * nf * nf, nsmp = n_s * n_s * n_s, npi = q1 * q1 * q1;
+  const int nfit = nf * nf * nf, nsmp = n_s * n_s * n_s, npi = (q[0] + 1) * (q[1] + 1) * (q[2] + 1);
   const size_t shm = (size_t)(10 * nfit + 10 * nsmp + 9 * npi + 2 * nsmp) * sizeof(double);
   const dim3 grid((unsigned)P->n_tiles), block(256);
   switch (P->pM[0]) {
@@ -252,11 +259,19 @@ using namespace igamt;
 
 extern "C" igamt_status igamt_eproj(igamt_plan *P, double E, double nu, int32_t q, int32_t n_sample,
                                     double *d_tile_e, double *e_proj, void *stream) {
-  if (!P || !e_proj) { set_error("NULL argument"); return IGAMT_EINVAL; }
-  if (q < 0 || q > kMaxQ) { set_error("projection degree must be in [0, 6]"); return IGAMT_EINVAL; }
+  const int32_t qd[3] = {q, q, q};
+  return igamt_eproj_aniso(P, E, nu, qd, n_sample, d_tile_e, e_proj, stream);
+}
+
+extern "C" igamt_status igamt_eproj_aniso(igamt_plan *P, double E, double nu, const int32_t *q, int32_t n_sample,
+                                          double *d_tile_e, double *e_proj, void *stream) {
+  if (!P || !e_proj || !q) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  for (int k = 0; k < 3; ++k)
+    if (q[k] < 0 || q[k] > kMaxQ) { set_error("projection degrees must be in [0, 6]"); return IGAMT_EINVAL; }
   igamt_status st = eproj_checks(P, E, nu, n_sample);
   if (st) return st;
-  return eproj_run(P, E, nu, q, n_sample, d_tile_e, e_proj, (hipStream_t)stream);
+  const int qd[3] = {q[0], q[1], q[2]};
+  return eproj_run(P, E, nu, qd, n_sample, d_tile_e, e_proj, (hipStream_t)stream);
 }
 
 extern "C" igamt_status igamt_select_q(igamt_plan *P, double E, double nu, double tol, int32_t q_max,
@@ -269,7 +284,8 @@ extern "C" igamt_status igamt_select_q(igamt_plan *P, double E, double nu, doubl
   if (q_max < q0 || q_max > kMaxQ) { set_error("q_max must be in [macro degree, 6]"); return IGAMT_EINVAL; }
   double e = 0.0;
   for (int q = q0; q <= q_max; ++q) {
-    if ((st = eproj_run(P, E, nu, q, n_sample, nullptr, &e, (hipStream_t)stream))) return st;
+    const int qd[3] = {q, q, q};
+    if ((st = eproj_run(P, E, nu, qd, n_sample, nullptr, &e, (hipStream_t)stream))) return st;
     if (e <= tol) {
       *q_out = q;
       *e_out = e;
@@ -277,6 +293,44 @@ extern "C" igamt_status igamt_select_q(igamt_plan *P, double E, double nu, doubl
     }
   }
   *q_out = -1;
+  *e_out = e;
+  return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_select_q_aniso(igamt_plan *P, double E, double nu, double tol, int32_t q_max,
+                                             int32_t n_sample, int32_t *q_out, double *e_out, void *stream) {
+  if (!P || !q_out || !e_out) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (!(tol >= 0.0) || !std::isfinite(tol)) { set_error("tolerance must be finite and non-negative"); return IGAMT_EINVAL; }
+  igamt_status st = eproj_checks(P, E, nu, n_sample);
+  if (st) return st;
+  if (q_max < P->pM[0] || q_max > kMaxQ) { set_error("q_max must be in [macro degree, 6]"); return IGAMT_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  int q[3] = {P->pM[0], P->pM[1], P->pM[2]};
+  double e = 0.0;
+  if ((st = eproj_run(P, E, nu, q, n_sample, nullptr, &e, s))) return st;
+  while (e > tol) {   // raise the direction whose raise lowers E_proj most (ties: lowest index)
+    int best = -1;
+    double be = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      if (q[k] >= q_max) continue;
+      int trial[3] = {q[0], q[1], q[2]};
+      ++trial[k];
+      double et = 0.0;
+      if ((st = eproj_run(P, E, nu, trial, n_sample, nullptr, &et, s))) return st;
+      if (best < 0 || et < be) {
+        best = k;
+        be = et;
+      }
+    }
+    if (best < 0) {
+      for (int k = 0; k < 3; ++k) q_out[k] = -1;
+      *e_out = e;
+      return IGAMT_OK;
+    }
+    ++q[best];
+    e = be;
+  }
+  for (int k = 0; k < 3; ++k) q_out[k] = q[k];
   *e_out = e;
   return IGAMT_OK;
 }

@@ -23,8 +23,8 @@ struct FitArgs {
   int tiles[3];
   int64_t n_tiles;
   const double *fx;
-  const double *fP;
-  int q, nf, Kp, prec;
+  const double *fP3;    // per-direction 1-D operators [(q1[0]) nf][(q1[1]) nf][(q1[2]) nf]
+  int q1[3], nf, Kp, prec;
   double lam, mu;
   void *out;
   int64_t plane;        // n_tiles_pad * 9 * Kp elements per stored plane
@@ -54,13 +54,13 @@ __device__ inline void store_coef(const FitArgs &a, int64_t idx, double v, doubl
 template <int PM>
 __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   extern __shared__ double smem[];
-  const int nf = a.nf, q1 = a.q + 1;
+  const int nf = a.nf, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
   const int ns = nf * nf * nf;
-  const int npi = q1 * q1 * q1;
+  const int npi = q1x * q1y * q1z;
   double *FD = smem;              // [ns][10]
   double *buf0 = FD + ns * 10;    // [ns][9]
   double *buf1 = buf0 + ns * 9;   // [ns][9]
-  __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
+  __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
   __shared__ double colmax[64][9];
   __shared__ double scale[9];
   const int tid = threadIdx.x;
@@ -73,7 +73,9 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
       ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = 1.0f;
     return;
   }
-  for (int e = tid; e < q1 * nf; e += 64) Pm[e] = a.fP[e];
+  for (int e = tid; e < q1x * nf; e += 64) Pm[0][e] = a.fP3[e];
+  for (int e = tid; e < q1y * nf; e += 64) Pm[1][e] = a.fP3[q1x * nf + e];
+  for (int e = tid; e < q1z * nf; e += 64) Pm[2][e] = a.fP3[(q1x + q1y) * nf + e];
   const int tx = (int)(t % a.tiles[0]);
   const int ty = (int)((t / a.tiles[0]) % a.tiles[1]);
   const int tz = (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]));
@@ -123,13 +125,17 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   if (a.prec == IGAMT_F16X3 && tid < 9) {
     double m = 0.0;
     for (int r = 0; r < 64; ++r) m = fmax(m, colmax[r][tid]);
-    double L = 0.0;  // max row sum of |P1|: |coef| <= L^3 max|A|
-    for (int c = 0; c < q1; ++c) {
-      double rs = 0.0;
-      for (int s = 0; s < nf; ++s) rs += fabs(Pm[c * nf + s]);
-      L = fmax(L, rs);
+    double L3 = 1.0;  // product of the max row sums of |P_k|: |coef| <= L_x L_y L_z max|A|
+    for (int k = 0; k < 3; ++k) {
+      double L = 0.0;
+      for (int c = 0; c < a.q1[k]; ++c) {
+        double rs = 0.0;
+        for (int s = 0; s < nf; ++s) rs += fabs(Pm[k][c * nf + s]);
+        L = fmax(L, rs);
+      }
+      L3 *= L;
     }
-    scale[tid] = f16_scale_for(m * L * L * L);
+    scale[tid] = f16_scale_for(m * L3);
     ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = (float)(1.0 / scale[tid]);
   }
   __syncthreads();
@@ -146,27 +152,27 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
     }
     __syncthreads();
     // x direction: buf1[(s3, s2, c1)][ab]
-    for (int e = tid; e < q1 * nf * nf * 9; e += 64) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1, s23 = r / q1;
+    for (int e = tid; e < q1x * nf * nf * 9; e += 64) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1x, s23 = r / q1x;
       double v = 0.0;
-      for (int s1 = 0; s1 < nf; ++s1) v += Pm[c1 * nf + s1] * buf0[(s23 * nf + s1) * 9 + ab];
+      for (int s1 = 0; s1 < nf; ++s1) v += Pm[0][c1 * nf + s1] * buf0[(s23 * nf + s1) * 9 + ab];
       buf1[e] = v;
     }
     __syncthreads();
     // y direction: buf0[(s3, c2, c1)][ab]
-    for (int e = tid; e < q1 * q1 * nf * 9; e += 64) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1, c2 = (r / q1) % q1, s3 = r / (q1 * q1);
+    for (int e = tid; e < q1x * q1y * nf * 9; e += 64) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1x, c2 = (r / q1x) % q1y, s3 = r / (q1x * q1y);
       double v = 0.0;
-      for (int s2 = 0; s2 < nf; ++s2) v += Pm[c2 * nf + s2] * buf1[(((s3 * nf + s2) * q1) + c1) * 9 + ab];
+      for (int s2 = 0; s2 < nf; ++s2) v += Pm[1][c2 * nf + s2] * buf1[(((s3 * nf + s2) * q1x) + c1) * 9 + ab];
       buf0[e] = v;
     }
     __syncthreads();
-    // z direction and store: C = c1 + q1 (c2 + q1 c3)
+    // z direction and store: C = c1 + q1x (c2 + q1y c3)
     for (int e = tid; e < npi * 9; e += 64) {
       const int C = e % npi, ab = e / npi;
-      const int c1 = C % q1, c2 = (C / q1) % q1, c3 = C / (q1 * q1);
+      const int c1 = C % q1x, c2 = (C / q1x) % q1y, c3 = C / (q1x * q1y);
       double v = 0.0;
-      for (int s3 = 0; s3 < nf; ++s3) v += Pm[c3 * nf + s3] * buf0[(((s3 * q1 + c2) * q1) + c1) * 9 + ab];
+      for (int s3 = 0; s3 < nf; ++s3) v += Pm[2][c3 * nf + s3] * buf0[(((s3 * q1y + c2) * q1x) + c1) * 9 + ab];
       store_coef<double>(a, tbase + (int64_t)ab * a.Kp + 9 * C + ij, v, a.prec == IGAMT_F16X3 ? scale[ab] : 1.0);
     }
     __syncthreads();
@@ -214,8 +220,8 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.wts = P->dev.macro_w;
   a.n_tiles = P->n_tiles;
   a.fx = P->dev.fit_x;
-  a.fP = P->dev.fit_P;
-  a.q = P->q;
+  a.fP3 = P->dev.fit_P3;
+  for (int k = 0; k < 3; ++k) a.q1[k] = P->qd[k] + 1;
   a.nf = P->n_fit;
   a.Kp = P->Kp;
   a.prec = prec;

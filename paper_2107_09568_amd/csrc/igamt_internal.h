@@ -53,6 +53,7 @@ struct DevicePtrs {
   double *box_h[3] = {nullptr, nullptr, nullptr};
   double *fit_x = nullptr;           // [n_fit] Gauss nodes on [0,1]
   double *fit_P = nullptr;           // [(q+1) * n_fit] 1-D projection matrix
+  double *fit_P3 = nullptr;          // the three per-direction operators, concatenated
   double *tile_knots[3] = {nullptr, nullptr, nullptr};
   double *tile_ctrl = nullptr;
   double *tile_grev = nullptr;       // [n_x + n_y + n_z] Greville abscissae of the tile knots
@@ -105,6 +106,8 @@ struct igamt_plan {
   int eT[3];                          // micro elements per direction
   // descriptor
   int tiles[3], box_mode, q, n_fit, n_gauss;
+  int qd[3];                          // projection degree per direction (all q unless anisotropic)
+  bool aniso = false;                 // degrees differ per direction
   // derived sizes
   int64_t n_tiles, n_tiles_pad, n_groups;
   int npi, K, Kp;
@@ -123,6 +126,7 @@ struct igamt_plan {
   int64_t n_global, nnz;
   // 1-D fit operator
   std::vector<double> fit_x, fit_w, fit_P;
+  std::vector<double> fit_P3;         // per-direction operators, [(qd[0]+1) nf][(qd[1]+1) nf][(qd[2]+1) nf]
   std::vector<double> gauss_x, gauss_w;
   // macro control points touched by each tile (for the fit adjoint)
   int Lc[3];                          // local control points per direction (max over tiles)

@@ -305,6 +305,7 @@ static bool finite_loads(const double *body, const double *traction) {
 
 extern "C" igamt_status igamt_load_table_build(igamt_plan *P, void *stream) {
   if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (P->aniso) { set_error("the load vector uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (P->pT[0] != P->pT[1] || P->pT[0] != P->pT[2]) {
@@ -362,6 +363,7 @@ extern "C" igamt_status igamt_load_fit(igamt_plan *P, const double *body, const 
                                        void *stream) {
   if (!P || !body || !traction || !d_coef) { set_error("NULL argument"); return IGAMT_EINVAL; }
   if (!finite_loads(body, traction)) { set_error("non-finite body force or traction"); return IGAMT_EINVAL; }
+  if (P->aniso) { set_error("the load vector uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   igamt_status st = ensure_device(P);
   if (st) return st;
   return load_fit_launch(P, body, traction, d_coef, (hipStream_t)stream);

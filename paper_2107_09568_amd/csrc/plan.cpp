@@ -221,8 +221,15 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
   P->q = desc->q;
   P->n_fit = desc->n_fit;
   P->n_gauss = desc->n_gauss;
-  if (P->q < 0 || P->q > kMaxQ) { set_error("q must be in 0..6"); return IGAMT_EUNSUPPORTED; }
-  if (P->n_fit < P->q + 1 || P->n_fit > kMaxFit) { set_error("n_fit must be in q+1..8"); return IGAMT_EINVAL; }
+  int qmax = 0;
+  for (int k = 0; k < 3; ++k) {
+    P->qd[k] = desc->anisotropic ? desc->q_dir[k] : desc->q;
+    if (P->qd[k] < 0 || P->qd[k] > kMaxQ) { set_error("projection degrees must be in 0..6"); return IGAMT_EUNSUPPORTED; }
+    qmax = std::max(qmax, P->qd[k]);
+  }
+  P->aniso = P->qd[0] != P->qd[1] || P->qd[1] != P->qd[2];
+  P->q = P->aniso ? qmax : P->qd[0];   // the isotropic degree (largest one when anisotropic)
+  if (P->n_fit < qmax + 1 || P->n_fit > kMaxFit) { set_error("n_fit must be in max(q)+1..8"); return IGAMT_EINVAL; }
   if (P->n_gauss < 1 || P->n_gauss > kMaxGauss) { set_error("n_gauss must be in 1..8"); return IGAMT_EINVAL; }
   if (P->box_mode != 0 && P->box_mode != 1) { set_error("box_mode must be 0 or 1"); return IGAMT_EINVAL; }
   // tile boxes
@@ -248,7 +255,7 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
   P->n_tiles = (int64_t)P->tiles[0] * P->tiles[1] * P->tiles[2];
   P->n_tiles_pad = (P->n_tiles + kTileGroup - 1) / kTileGroup * kTileGroup;
   P->n_groups = P->n_tiles_pad / kTileGroup;
-  P->npi = (P->q + 1) * (P->q + 1) * (P->q + 1);
+  P->npi = (P->qd[0] + 1) * (P->qd[1] + 1) * (P->qd[2] + 1);
   P->K = 9 * P->npi;
   P->Kp = (P->K + kColPad - 1) / kColPad * kColPad;
   P->nTt = (int64_t)P->nT[0] * P->nT[1] * P->nT[2];
@@ -373,6 +380,12 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
   gauss_legendre01(P->n_fit, P->fit_x, P->fit_w);
   gauss_legendre01(P->n_gauss, P->gauss_x, P->gauss_w);
   if (!projection_1d(P->q, P->fit_x, P->fit_w, P->fit_P)) { set_error("singular projection matrix"); return IGAMT_EINVAL; }
+  P->fit_P3.clear();
+  for (int k = 0; k < 3; ++k) {
+    std::vector<double> Pk;
+    if (!projection_1d(P->qd[k], P->fit_x, P->fit_w, Pk)) { set_error("singular projection matrix"); return IGAMT_EINVAL; }
+    P->fit_P3.insert(P->fit_P3.end(), Pk.begin(), Pk.end());
+  }
   // macro control points touched by each tile's samples, and the reverse map
   for (int d = 0; d < 3; ++d) {
     const int p = P->pM[d], n = P->nM[d], T = P->tiles[d];

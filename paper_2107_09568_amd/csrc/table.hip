@@ -19,7 +19,7 @@ struct TableArgs {
   int nT[3], eT[3];
   const double *ctrl;
   const double *gx, *gw;
-  int ng, q, npi;
+  int ng, qd[3], npi;    // projection degree per direction, n_pi = prod (qd + 1)
   int64_t stride;        // doubles per point record
   double *pts;
   int32_t *flag;
@@ -78,9 +78,9 @@ __global__ __launch_bounds__(64) void table_points_kernel(TableArgs a) {
   out[0] = w * D;
   double B[3][kMaxQ + 1];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) bernstein(a.q, X[k], B[k]);
-  const int q1 = a.q + 1;
-  for (int C = 0; C < a.npi; ++C) out[1 + C] = B[0][C % q1] * B[1][(C / q1) % q1] * B[2][C / (q1 * q1)];
+  for (int k = 0; k < 3; ++k) bernstein(a.qd[k], X[k], B[k]);
+  const int q1x = a.qd[0] + 1, q1y = a.qd[1] + 1;
+  for (int C = 0; C < a.npi; ++C) out[1 + C] = B[0][C % q1x] * B[1][(C / q1x) % q1y] * B[2][C / (q1x * q1y)];
   double *gout = out + 1 + a.npi;
   int la = 0;
   for (int rz = 0; rz <= PT; ++rz)
@@ -196,7 +196,7 @@ static igamt_status run_points(igamt_plan *P, hipStream_t s, int64_t &stride, co
   a.gx = P->dev.gauss_x;
   a.gw = P->dev.gauss_w;
   a.ng = P->n_gauss;
-  a.q = P->q;
+  for (int k = 0; k < 3; ++k) a.qd[k] = P->qd[k];
   a.npi = P->npi;
   a.stride = stride;
   a.pts = P->dev.point_data;
@@ -343,7 +343,7 @@ static igamt_status run_points_batch(igamt_plan *P, hipStream_t s, const double 
   a.gx = P->dev.gauss_x;
   a.gw = P->dev.gauss_w;
   a.ng = P->n_gauss;
-  a.q = P->q;
+  for (int k = 0; k < 3; ++k) a.qd[k] = P->qd[k];
   a.npi = P->npi;
   a.stride = stride;
   a.pts = P->dev.batch_points;

@@ -221,6 +221,7 @@ using namespace igamt;
 
 extern "C" igamt_status igamt_volume_table_build(igamt_plan *P, void *stream) {
   if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (P->aniso) { set_error("the volume uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   igamt_status st = ensure_device(P);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;

@@ -180,6 +180,16 @@ def test_plan_limits(P):
     assert e.value.code == -6
     ok = W.identity_spline((2, 2, 2), (14, 2, 2))         # 16: the largest supported
     P.Plan(w.macro, ok, w.tiles, 0, 2, 3, 3).close()
+    # anisotropic degrees: 0..6 per direction, n_fit at least the largest degree + 1
+    pa = P.Plan(w.macro, w.tile, w.tiles, 0, (1, 2, 3), 4, 3)
+    assert pa.n_cols == 9 * 2 * 3 * 4 and pa.q_dir == (1, 2, 3)
+    pa.close()
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, w.tile, w.tiles, 0, (1, 2, 7), 8, 3)
+    assert e.value.code == -6
+    with pytest.raises(P.IgamtError) as e:
+        P.Plan(w.macro, w.tile, w.tiles, 0, (1, 2, 3), 3, 3)
+    assert e.value.code == -1
     # NURBS: positive weights on the macro map only
     import dataclasses
     torus = W.nurbs_quarter_torus()
