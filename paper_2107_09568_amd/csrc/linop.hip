@@ -34,6 +34,7 @@ constexpr int kApplyChunk = 256;        // block records per chunk (one per thre
 constexpr int kApplyThreads = 256;
 constexpr int kApplyLdsMax = 64 * 1024;
 static_assert(kApplyChunk == kApplyThreads && kApplyChunk % 64 == 0, "one record per thread, whole waves");
+static_assert(kApplyChunk * 9 == 2 * (4 * kApplyThreads + 128), "16-byte units of a chunk: 4.5 per thread");
 
 // Dynamic LDS of the tile product kernel for block element type of `eb` bytes.
 inline int64_t apply_lds_bytes(int64_t nTt, int eb) {
@@ -55,7 +56,12 @@ struct ApplyArgs {
   int GX, GY;
 };
 
-template <typename BT>
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// V16: FP64 blocks moved in 16-byte units (4.5 per thread and chunk: four, then a fifth on the
+// first 128 threads, clamped on the others so that every thread issues the same loads); needs a
+// 16-byte aligned tile base, i.e. an even pair count.  Otherwise one element per load.
+template <typename BT, bool V16>
 __global__ __launch_bounds__(kApplyThreads) void tile_apply_kernel(ApplyArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   BT *kb = (BT *)lds_raw;                                                    // [kApplyChunk][9]
@@ -75,6 +81,7 @@ __global__ __launch_bounds__(kApplyThreads) void tile_apply_kernel(ApplyArgs a) 
   // so every set always issues the same loads); their data is never used.
   struct Pref {
     BT r[9];
+    dbl2 v[5];
     int32_t rec, perm, seg0, seg1;
   };
   auto load = [&](Pref &f, int c) {
@@ -86,8 +93,16 @@ __global__ __launch_bounds__(kApplyThreads) void tile_apply_kernel(ApplyArgs a) 
     f.perm = a.perm[(int64_t)cc * kApplyChunk + tid];
     f.seg0 = a.seg[(int64_t)cc * 2 * kApplyChunk + tid];
     f.seg1 = a.seg[(int64_t)cc * 2 * kApplyChunk + kApplyThreads + tid];
+    if constexpr (V16) {
+      const dbl2 *src2 = (const dbl2 *)src;
+      const int64_t nu = n / 2;   // n is even: an even number of records per chunk
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f.r[i] = src[min(tid + (int64_t)i * kApplyThreads, n - 1)];
+      for (int i = 0; i < 4; ++i) f.v[i] = src2[min(tid + (int64_t)i * kApplyThreads, nu - 1)];
+      f.v[4] = src2[min((int64_t)4 * kApplyThreads + (tid & 127), nu - 1)];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f.r[i] = src[min(tid + (int64_t)i * kApplyThreads, n - 1)];
+    }
   };
   Pref f0, f1;
   load(f0, 0);
@@ -103,8 +118,15 @@ __global__ __launch_bounds__(kApplyThreads) void tile_apply_kernel(ApplyArgs a) 
   // one chunk from set f, then the load of chunk c + 2 into f
   auto step = [&](Pref &f, int c) {
     const int64_t c0 = (int64_t)c * kApplyChunk;
+    if constexpr (V16) {
+      dbl2 *kb2 = (dbl2 *)kb;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) kb[tid + i * kApplyThreads] = f.r[i];
+      for (int i = 0; i < 4; ++i) kb2[tid + i * kApplyThreads] = f.v[i];
+      if (tid < 128) kb2[4 * kApplyThreads + tid] = f.v[4];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) kb[tid + i * kApplyThreads] = f.r[i];
+    }
     ((int32_t *)perm)[tid] = f.perm;
     segs[tid] = f.seg0;
     segs[kApplyThreads + tid] = f.seg1;
@@ -313,9 +335,12 @@ static igamt_status launch_tile_apply(igamt_plan *P, igamt_precision prec, const
   a.GY = P->dir[1].NG;
   const dim3 grid((unsigned)(t1 - t0)), block(kApplyThreads);
   if (prec == IGAMT_F64)
-    hipLaunchKernelGGL(tile_apply_kernel<double>, grid, block, (size_t)apply_lds_bytes(P->nTt, 8), s, a);
+    if (P->n_pairs % 2 == 0 && (uintptr_t)blocks % 16 == 0)
+      hipLaunchKernelGGL((tile_apply_kernel<double, true>), grid, block, (size_t)apply_lds_bytes(P->nTt, 8), s, a);
+    else
+      hipLaunchKernelGGL((tile_apply_kernel<double, false>), grid, block, (size_t)apply_lds_bytes(P->nTt, 8), s, a);
   else
-    hipLaunchKernelGGL(tile_apply_kernel<float>, grid, block, (size_t)apply_lds_bytes(P->nTt, 4), s, a);
+    hipLaunchKernelGGL((tile_apply_kernel<float, false>), grid, block, (size_t)apply_lds_bytes(P->nTt, 4), s, a);
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
