@@ -19,27 +19,27 @@ import numpy as np
 
 from .basis import bspline_basis, gauss01
 from .geometry import tile_boxes, tile_index
-from .projection import bernstein3, fit_points, projection_operator, tile_macro_jacobians
+from .projection import bernstein3, degrees, fit_points, n_pi, projection_operator, tile_macro_jacobians
 from .tables import element_points, micro_elements
 
 
-def volume_table(tile, q: int, n_g: int) -> np.ndarray:
-    """t^h (eq. (18)), shape (n_pi,)."""
-    t = np.zeros((q + 1) ** 3)
+def volume_table(tile, q, n_g: int) -> np.ndarray:
+    """t^h (eq. (18)), shape (n_pi,); q an int or a degree triple."""
+    t = np.zeros(n_pi(q))
     for _, box in micro_elements(tile):
         _, _, X, JT, wts = element_points(tile, box, n_g)
         t += (wts * np.abs(np.linalg.det(JT))) @ bernstein3(q, X)
     return t
 
 
-def mass_matrix(q: int) -> np.ndarray:
-    """M_pi (eq. (24)): int N_k N_l over [0,1]^3 by a Gauss rule exact for degree 2q."""
-    pts, wts = fit_points(q + 1)
+def mass_matrix(q) -> np.ndarray:
+    """M_pi (eq. (24)): int N_k N_l over [0,1]^3 by a Gauss rule exact for degree 2 max q."""
+    pts, wts = fit_points(max(degrees(q)) + 1)
     N = bernstein3(q, pts)
     return N.T @ (wts[:, None] * N)
 
 
-def folded_table(q: int, t_h: np.ndarray) -> np.ndarray:
+def folded_table(q, t_h: np.ndarray) -> np.ndarray:
     """t_pi = M_pi^-1 t^h (eq. (26))."""
     return np.linalg.solve(mass_matrix(q), t_h)
 
@@ -87,7 +87,7 @@ def volume_standard(w, n_g: int = None) -> float:
     return v
 
 
-def adjoint_field(q: int, t_pi: np.ndarray, pts: np.ndarray) -> np.ndarray:
+def adjoint_field(q, t_pi: np.ndarray, pts: np.ndarray) -> np.ndarray:
     """v(xi) = sum_C N_C(xi) t_pi[C] (eq. (67)) at points pts (P, 3)."""
     return bernstein3(q, pts) @ t_pi
 

@@ -65,6 +65,34 @@ def test_affine_map_exact_with_anisotropic_degrees():
         assert np.linalg.norm(blocks[t] - ref) <= 1e-13 * np.linalg.norm(ref)
 
 
+def test_anisotropic_volume_and_gradient():
+    """Volume with degrees (1, 2, 3): the mass matrix is the Kronecker product of the 1-D ones of
+    each degree; affine maps give |det A|; the gradient matches central differences."""
+    from math import comb
+    from oracle import volume
+    def m1(q):
+        return np.array([[comb(q, a) * comb(q, b) / ((2 * q + 1) * comb(2 * q, a + b)) for b in range(q + 1)]
+                         for a in range(q + 1)])
+    np.testing.assert_allclose(volume.mass_matrix((1, 2, 3)), np.kron(np.kron(m1(3), m1(2)), m1(1)), rtol=1e-13)
+    A = np.array([[1.3, 0.2, -0.1], [0.1, 0.8, 0.15], [-0.05, 0.1, 1.1]])
+    wa = W.Workload("affine", W.affine_macro((2, 2, 2), (2, 2, 2), A, np.zeros(3)), W.make("cfg1").tile,
+                    (2, 2, 2), 0, (1, 2, 3), 4, 3)
+    assert volume.volume(wa, volume.volume_table(wa.tile, wa.q, 8)) == pytest.approx(abs(np.linalg.det(A)), rel=1e-12)
+    import dataclasses
+    w = dataclasses.replace(W.make("cfg1"), q=(1, 2, 3), n_fit=4)
+    t_h = volume.volume_table(w.tile, w.q, w.n_gauss)
+    g = volume.volume_grad(w, volume.folded_table(w.q, t_h))
+    eps = 1e-6
+    for (k, j, i, c) in [(1, 1, 1, 0), (2, 0, 3, 2)]:
+        vals = []
+        for sgn in (1, -1):
+            ctrl = w.macro.ctrl.copy()
+            ctrl[k, j, i, c] += sgn * eps
+            ws = dataclasses.replace(w, macro=dataclasses.replace(w.macro, ctrl=ctrl))
+            vals.append(volume.volume(ws, t_h))
+        assert g[k, j, i, c] == pytest.approx((vals[0] - vals[1]) / (2 * eps), rel=1e-6, abs=1e-9)
+
+
 def test_twisted_square_selects_an_anisotropic_degree():
     """The twist varies along the axis only: raising the section degrees leaves E_proj unchanged,
     raising the axial degree lowers it; the anisotropic selection stops at (2, 2, 3) for 1e-3 with
