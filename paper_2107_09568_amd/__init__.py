@@ -298,7 +298,7 @@ class Plan:
 
     def load_table_get(self):
         torch = _torch()
-        out = torch.empty((self.n_tile_ctrl, (self.q + 1) ** 3, 7), dtype=torch.float64, device="cuda")
+        out = torch.empty((self.n_tile_ctrl, self.n_cols // 9, 7), dtype=torch.float64, device="cuda")
         check(lib().igamt_load_table_get(self._h, _ptr(out), _stream()))
         return out
 
@@ -312,7 +312,7 @@ class Plan:
         torch = _torch()
         b, t = self._loads(body, traction)
         if out is None:
-            out = torch.empty((self.n_tiles, 7, 3, (self.q + 1) ** 3), dtype=torch.float64, device="cuda")
+            out = torch.empty((self.n_tiles, 7, 3, self.n_cols // 9), dtype=torch.float64, device="cuda")
         check(lib().igamt_load_fit(self._h, b.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
                                    _ptr(out), _stream()))
         return out
@@ -400,7 +400,7 @@ class Plan:
     def volume_table_get(self):
         """(t^h, t_pi) as float64 [n_pi] device tensors."""
         torch = _torch()
-        n = (self.q + 1) ** 3
+        n = self.n_cols // 9
         t = torch.empty(n, dtype=torch.float64, device="cuda")
         tp = torch.empty(n, dtype=torch.float64, device="cuda")
         check(lib().igamt_volume_table_get(self._h, _ptr(t), _ptr(tp), _stream()))

@@ -36,23 +36,24 @@ __global__ __launch_bounds__(64) void volume_table_kernel(const double *__restri
 }
 
 struct VolumeFoldArgs {
-  double minv[(kMaxQ + 1) * (kMaxQ + 1)];   // inverse 1-D Bernstein mass matrix
-  const double *fP;                          // [q1][nf] 1-D projection operator
-  int q, nf;
-  double *data;                              // t^h [npi] in; t_pi [npi], g [nf^3] out
+  double minv[3][(kMaxQ + 1) * (kMaxQ + 1)];   // inverse 1-D Bernstein mass matrix per direction
+  const double *fP3;                            // per-direction 1-D projection operators [q1[k]][nf]
+  int q1[3], nf;
+  double *data;                                 // t^h [npi] in; t_pi [npi], g [nf^3] out
 };
 
-// t_pi = (Minv x Minv x Minv) t^h and g = (P x P x P)^T t^h
+// t_pi = (Minv_x x Minv_y x Minv_z) t^h and g = (P_x x P_y x P_z)^T t^h
 __global__ __launch_bounds__(256) void volume_fold_kernel(VolumeFoldArgs a) {
-  const int q1 = a.q + 1, npi = q1 * q1 * q1, nf = a.nf, ns = nf * nf * nf;
+  const int qx = a.q1[0], qy = a.q1[1], qz = a.q1[2], npi = qx * qy * qz, nf = a.nf, ns = nf * nf * nf;
   const double *th = a.data;
   double *tpi = a.data + npi, *g = a.data + 2 * npi;
+  const double *Px = a.fP3, *Py = Px + qx * nf, *Pz = Py + qy * nf;
   for (int C = threadIdx.x; C < npi; C += 256) {
-    const int c[3] = {C % q1, (C / q1) % q1, C / (q1 * q1)};
+    const int c[3] = {C % qx, (C / qx) % qy, C / (qx * qy)};
     double s = 0.0;
     for (int D = 0; D < npi; ++D) {
-      const int d[3] = {D % q1, (D / q1) % q1, D / (q1 * q1)};
-      s += a.minv[c[0] * q1 + d[0]] * a.minv[c[1] * q1 + d[1]] * a.minv[c[2] * q1 + d[2]] * th[D];
+      const int d[3] = {D % qx, (D / qx) % qy, D / (qx * qy)};
+      s += a.minv[0][c[0] * qx + d[0]] * a.minv[1][c[1] * qy + d[1]] * a.minv[2][c[2] * qz + d[2]] * th[D];
     }
     tpi[C] = s;
   }
@@ -60,8 +61,8 @@ __global__ __launch_bounds__(256) void volume_fold_kernel(VolumeFoldArgs a) {
     const int si[3] = {S % nf, (S / nf) % nf, S / (nf * nf)};
     double s = 0.0;
     for (int C = 0; C < npi; ++C) {
-      const int c[3] = {C % q1, (C / q1) % q1, C / (q1 * q1)};
-      s += a.fP[c[0] * nf + si[0]] * a.fP[c[1] * nf + si[1]] * a.fP[c[2] * nf + si[2]] * th[C];
+      const int c[3] = {C % qx, (C / qx) % qy, C / (qx * qy)};
+      s += Px[c[0] * nf + si[0]] * Py[c[1] * nf + si[1]] * Pz[c[2] * nf + si[2]] * th[C];
     }
     g[S] = s;
   }
@@ -221,7 +222,6 @@ using namespace igamt;
 
 extern "C" igamt_status igamt_volume_table_build(igamt_plan *P, void *stream) {
   if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
-  if (P->aniso) { set_error("the volume uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   igamt_status st = ensure_device(P);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -234,9 +234,11 @@ extern "C" igamt_status igamt_volume_table_build(igamt_plan *P, void *stream) {
                      stride, n_rec, P->npi, P->dev.volume_data);
   IGAMT_LAUNCH_CHECK();
   VolumeFoldArgs f;
-  if (!bernstein_mass_inverse(P->q, f.minv)) { set_error("singular Bernstein mass matrix"); return IGAMT_EINVAL; }
-  f.fP = P->dev.fit_P;
-  f.q = P->q;
+  for (int k = 0; k < 3; ++k) {
+    if (!bernstein_mass_inverse(P->qd[k], f.minv[k])) { set_error("singular Bernstein mass matrix"); return IGAMT_EINVAL; }
+    f.q1[k] = P->qd[k] + 1;
+  }
+  f.fP3 = P->dev.fit_P3;
   f.nf = P->n_fit;
   f.data = P->dev.volume_data;
   hipLaunchKernelGGL(volume_fold_kernel, dim3(1), dim3(256), 0, s, f);

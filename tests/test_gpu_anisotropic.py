@@ -92,9 +92,28 @@ def test_isotropic_only_entry_points_refuse(env):
     w = _aniso((1, 2, 2))
     plan = P.Plan.from_workload(w)
     plan.tables_build()
-    for call in (plan.load_table_build, plan.volume_table_build,
+    for call in (plan.load_table_build,
                  lambda: plan.load_fit(np.zeros(3)),
                  lambda: plan.uKu_grad(w.E, w.nu, torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda"))):
         with pytest.raises(P.IgamtError) as e:
             call()
         assert e.value.code == -6
+
+
+def test_anisotropic_volume_vs_oracle(env):
+    torch, P = env
+    from oracle import volume
+    w = _aniso((1, 2, 3))
+    plan = P.Plan.from_workload(w)
+    plan.volume_table_build()
+    t, tp = plan.volume_table_get()
+    assert t.numel() == projection.n_pi(w.q)
+    ref_th = volume.volume_table(w.tile, w.q, w.n_gauss)
+    ref_tpi = volume.folded_table(w.q, ref_th)
+    assert np.abs(t.cpu().numpy() - ref_th).max() <= 1e-13 * np.abs(ref_th).max()
+    assert np.abs(tp.cpu().numpy() - ref_tpi).max() <= 1e-11 * np.abs(ref_tpi).max()
+    v, tv, g = plan.volume(grad=True)
+    ref_tv = volume.tile_volumes(w, ref_th)
+    assert np.abs(tv.cpu().numpy() - ref_tv).max() <= 1e-13 * np.abs(ref_tv).max()
+    ref_g = volume.volume_grad(w, ref_tpi).reshape(-1, 3)
+    assert np.abs(g.cpu().numpy() - ref_g).max() <= 1e-11 * np.abs(ref_g).max()
