@@ -27,7 +27,7 @@ import numpy as np
 from .basis import bernstein, bspline_basis, gauss01
 from .geometry import (eval_volume_grid, eval_volume_points, n_global_dofs, tile_boxes, tile_global_indices,
                        tile_index)
-from .projection import bernstein3, fit_points, projection_operator
+from .projection import bernstein3, degrees, fit_points, n_pi, projection_operator
 from .tables import active_functions, element_points, micro_elements
 
 N_FACES = 6
@@ -40,33 +40,35 @@ def face_axes(f: int):
     return d, side, u, v
 
 
-def face_index_set(q: int, f: int) -> np.ndarray:
-    """I_f: the Bernstein indices C = c1 + (q+1)(c2 + (q+1) c3) that do not vanish on face f."""
+def face_index_set(q, f: int) -> np.ndarray:
+    """I_f: the Bernstein indices C = c1 + (q1+1)(c2 + (q2+1) c3) that do not vanish on face f
+    (q an int or a degree triple)."""
     d, side, _, _ = face_axes(f)
-    q1 = q + 1
+    qd = degrees(q)
     out = []
-    for C in range(q1 ** 3):
-        c = (C % q1, (C // q1) % q1, C // (q1 * q1))
-        if c[d] == (q if side else 0):
+    for C in range(n_pi(q)):
+        c = (C % (qd[0] + 1), (C // (qd[0] + 1)) % (qd[1] + 1), C // ((qd[0] + 1) * (qd[1] + 1)))
+        if c[d] == (qd[d] if side else 0):
             out.append(C)
     return np.array(out, dtype=np.int64)
 
 
-def face_projection_operator(q: int, n_fit: int) -> np.ndarray:
-    """2-D version of eq. (23)-(24) on [0,1]^2: P2 (q1^2 x n_fit^2), index c_u + q1 c_v, point s_u + n_fit s_v."""
+def face_projection_operator(q, n_fit: int) -> np.ndarray:
+    """2-D version of eq. (23)-(24) on [0,1]^2 with degrees q = (q_u, q_v) (or one int):
+    P2 ((q_u+1)(q_v+1) x n_fit^2), index c_u + (q_u+1) c_v, point s_u + n_fit s_v."""
+    qu, qv = (int(q), int(q)) if np.ndim(q) == 0 else (int(q[0]), int(q[1]))
     x, wx = gauss01(n_fit)
-    B = bernstein(q, x)                                   # (n_fit, q1)
-    N = np.einsum("vj,ui->vuji", B, B).reshape(n_fit * n_fit, -1)   # [(s_v, s_u), (c_v, c_u)]
+    Bu, Bv = bernstein(qu, x), bernstein(qv, x)            # (n_fit, q+1)
+    N = np.einsum("vj,ui->vuji", Bv, Bu).reshape(n_fit * n_fit, -1)   # [(s_v, s_u), (c_v, c_u)]
     W = np.einsum("v,u->vu", wx, wx).reshape(-1)
     M = N.T @ (W[:, None] * N)
     return np.linalg.solve(M, N.T * W[None, :])
 
 
-def load_table(tile, q: int, n_g: int) -> np.ndarray:
+def load_table(tile, q, n_g: int) -> np.ndarray:
     """F of eq. (54)-(55): shape (n_T, n_pi, 7), slot 0 the volume, 1 + f the faces."""
     nT = int(np.prod(tile.n_ctrl))
-    q1 = q + 1
-    npi = q1 ** 3
+    npi = n_pi(q)
     F = np.zeros((nT, npi, 1 + N_FACES))
     # volume: micro elements and their Gauss points
     for e, box in micro_elements(tile):
@@ -135,10 +137,9 @@ def load_coefficients(w, t: int, body, traction, P=None, P2=None) -> np.ndarray:
     body = np.asarray(body, dtype=np.float64)
     traction = np.asarray(traction, dtype=np.float64).reshape(N_FACES, 3)
     q, nf = w.q, w.n_fit
-    q1 = q + 1
-    npi = q1 ** 3
+    qd = degrees(q)
+    npi = n_pi(q)
     P = projection_operator(q, nf) if P is None else P
-    P2 = face_projection_operator(q, nf) if P2 is None else P2
     a, h, _ = _box(w, t)
     out = np.zeros((1 + N_FACES, 3, npi))
     # body: samples at the tensor GL nodes (x fastest), |det J_M^(t)|
@@ -158,14 +159,15 @@ def load_coefficients(w, t: int, body, traction, P=None, P2=None) -> np.ndarray:
         _, Jp = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * pts, weights=w.macro.weights)
         Jp = Jp * h[None, None, :]
         area = np.linalg.norm(np.cross(Jp[:, :, u], Jp[:, :, v]), axis=1)
-        cf = P2 @ (area[:, None] * traction[f][None, :])              # (q1^2, 3), index c_u + q1 c_v
-        for cv in range(q1):
-            for cu in range(q1):
+        P2f = P2 if (P2 is not None and qd[u] == qd[v]) else face_projection_operator((qd[u], qd[v]), nf)
+        cf = P2f @ (area[:, None] * traction[f][None, :])             # index c_u + (q_u+1) c_v
+        for cv in range(qd[v] + 1):
+            for cu in range(qd[u] + 1):
                 c = [0, 0, 0]
-                c[d] = q if side else 0
+                c[d] = qd[d] if side else 0
                 c[u], c[v] = cu, cv
-                C = c[0] + q1 * (c[1] + q1 * c[2])
-                out[1 + f, :, C] = cf[cu + q1 * cv]
+                C = c[0] + (qd[0] + 1) * (c[1] + (qd[1] + 1) * c[2])
+                out[1 + f, :, C] = cf[cu + (qd[u] + 1) * cv]
     return out
 
 
@@ -178,7 +180,7 @@ def assemble_load(w, table, body, traction) -> np.ndarray:
     """Global f^pi [3 N_G]: tile vectors summed over the tiles holding each point, in ascending tile order."""
     f = np.zeros(n_global_dofs(w))
     P = projection_operator(w.q, w.n_fit)
-    P2 = face_projection_operator(w.q, w.n_fit)
+    P2 = face_projection_operator(w.q, w.n_fit) if np.ndim(w.q) == 0 else None
     for t in range(w.n_tiles):
         ft = tile_load(table, load_coefficients(w, t, body, traction, P, P2))
         G = tile_global_indices(w, t)

@@ -105,3 +105,32 @@ def test_twisted_square_selects_an_anisotropic_degree():
     assert q == (2, 2, 3) and e <= 1e-3
     qi, _ = adaptive.select_q(w, 1e-3)
     assert qi == 3 and projection.n_pi(q) < projection.n_pi(qi)
+
+
+def test_anisotropic_load_table_and_affine_vector():
+    """Load table with degrees (1, 2, 3): sum_A F[A, C, 0] = int N_C = prod_k 1/(q_k+1) (identity
+    tile, exact rule); sum_A F[A, C, 1+f] = prod_{k != d} 1/(q_k+1) on I_f and 0 off it; an affine map
+    gives f^pi = f^bullet."""
+    from oracle import load
+    q = (1, 2, 3)
+    F = load.load_table(W.identity_spline((2, 2, 2), (2, 2, 2)), q, 4)
+    np.testing.assert_allclose(F[:, :, 0].sum(axis=0), 1.0 / (2 * 3 * 4), rtol=1e-13)
+    for f in range(6):
+        d = f // 2
+        I = load.face_index_set(q, f)
+        s = F[:, :, 1 + f].sum(axis=0)
+        expect = np.prod([1.0 / (q[k] + 1) for k in range(3) if k != d])
+        np.testing.assert_allclose(s[I], expect, rtol=1e-13)
+        mask = np.ones(len(s), bool)
+        mask[I] = False
+        assert np.abs(s[mask]).max() < 1e-15
+    A = np.array([[1.3, 0.2, -0.1], [0.1, 0.8, 0.15], [-0.05, 0.1, 1.1]])
+    macro = W.affine_macro((2, 2, 2), (2, 2, 2), A, np.array([0.5, -1.0, 2.0]))
+    w = W.Workload("affine", macro, W.make("cfg1").tile, (2, 3, 2), 1, (0, 1, 2), 3, 3)
+    body = np.array([0.3, -1.2, 0.7])
+    tr = np.zeros((6, 3))
+    tr[1] = [1.0, 0.0, 0.5]
+    tr[4] = [0.0, -2.0, 1.0]
+    fpi = load.assemble_load(w, load.load_table(w.tile, w.q, 3), body, tr)
+    fstd = load.standard_load(w, body, tr)
+    assert np.linalg.norm(fpi - fstd) <= 1e-13 * np.linalg.norm(fstd)
