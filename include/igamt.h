@@ -80,10 +80,9 @@ typedef struct {
  *             direction (Section 3.3.4), each 0..6 (q is then ignored);
  *             n_pi = prod_k (q_k + 1) and n_fit >= max_k q_k + 1 (a
  *             least-squares fit in the directions of lower degree).  With
- *             anisotropic = 0, q in every direction and q_dir is not read.  Plans whose degrees differ per direction run the
- *             stiffness path (tables, fit, contraction, scatter, products,
- *             solve); the load vector, volume and shape gradients return
- *             IGAMT_EUNSUPPORTED for them.                                   */
+ *             anisotropic = 0, q in every direction and q_dir is not read.
+ *             Plans whose degrees differ per direction run every entry point
+ *             except the shape gradient (igamt_uKu_grad: IGAMT_EUNSUPPORTED). */
 typedef struct {
   int32_t tiles[3];
   int32_t box_mode;

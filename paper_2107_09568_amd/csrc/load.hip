@@ -31,7 +31,7 @@ struct LoadTableArgs {
   const double *knots[3];
   int nT[3], eT[3];
   const double *gx, *gw;
-  int ng, q, npi;
+  int ng, qd[3], npi;        // projection degree per direction
   int64_t stride;            // doubles per point record
   const double *pts;         // point records of the table builder
   double *table;             // [nTt][npi][7]
@@ -45,8 +45,8 @@ __global__ __launch_bounds__(64) void load_table_kernel(LoadTableArgs a) {
   const int C = (int)(id % a.npi);
   const int64_t A = id / a.npi;
   const int ai[3] = {(int)(A % a.nT[0]), (int)((A / a.nT[0]) % a.nT[1]), (int)(A / ((int64_t)a.nT[0] * a.nT[1]))};
-  const int q1 = a.q + 1;
-  const int ci[3] = {C % q1, (C / q1) % q1, C / (q1 * q1)};
+  const int q1x = a.qd[0] + 1, q1y = a.qd[1] + 1;
+  const int ci[3] = {C % q1x, (C / q1x) % q1y, C / (q1x * q1y)};
   const int G = a.ng * a.ng * a.ng;
   double *out = a.table + id * kLoadSlots;
   // volume: the micro elements in the support of R_A, Gauss points in ascending order
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64) void load_table_kernel(LoadTableArgs a) {
     const int d = f >> 1, side = f & 1;
     const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
     double s = 0.0;
-    if (ai[d] == (side ? a.nT[d] - 1 : 0) && ci[d] == (side ? a.q : 0)) {
+    if (ai[d] == (side ? a.nT[d] - 1 : 0) && ci[d] == (side ? a.qd[d] : 0)) {
       for (int ev = max(ai[v] - PT, 0); ev <= min(ai[v], a.eT[v] - 1); ++ev)
         for (int eu = max(ai[u] - PT, 0); eu <= min(ai[u], a.eT[u] - 1); ++eu)
           for (int gv = 0; gv < a.ng; ++gv)
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(64) void load_table_kernel(LoadTableArgs a) {
                 double N[PT + 1], dN[PT + 1];
                 bspline_ders<PT>(a.knots[k], span, th, N, dN);
                 double B[kMaxQ + 1];
-                bernstein(a.q, th, B);
+                bernstein(a.qd[k], th, B);
                 val *= N[ai[k] - ee[m]] * B[ci[k]];
                 wt *= (h - l) * a.gw[gg[m]];
               }
@@ -119,8 +119,8 @@ struct LoadFitArgs {
   int tiles[3];
   int64_t n_tiles;
   const double *fx;
-  const double *fP;          // [q1][n_fit] 1-D projection operator
-  int q, nf, npi;
+  const double *fP3;         // per-direction 1-D projection operators [qd[k]+1][n_fit], concatenated
+  int qd[3], nf, npi;
   double body[3];
   double traction[6][3];
   double *coef;              // [n_tiles][7][3][npi]
@@ -132,7 +132,9 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
   __shared__ double vals[kMaxFit * kMaxFit * kMaxFit];   // |det J| at the body samples / face areas
   const int64_t t = blockIdx.x;
   const int tid = threadIdx.x;
-  const int nf = a.nf, q1 = a.q + 1, npi = a.npi;
+  const int nf = a.nf, npi = a.npi;
+  const int q1[3] = {a.qd[0] + 1, a.qd[1] + 1, a.qd[2] + 1};
+  const double *Pk[3] = {a.fP3, a.fP3 + q1[0] * nf, a.fP3 + (q1[0] + q1[1]) * nf};
   const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
                      (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
   const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
@@ -157,11 +159,11 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
   __syncthreads();
   for (int e = tid; e < 3 * npi; e += 64) {
     const int comp = e / npi, C = e - comp * npi;
-    const int c1 = C % q1, c2 = (C / q1) % q1, c3 = C / (q1 * q1);
+    const int c1 = C % q1[0], c2 = (C / q1[0]) % q1[1], c3 = C / (q1[0] * q1[1]);
     double v = 0.0;
     for (int s = 0; s < ns; ++s) {
       const int s1 = s % nf, s2 = (s / nf) % nf, s3 = s / (nf * nf);
-      v += a.fP[c1 * nf + s1] * a.fP[c2 * nf + s2] * a.fP[c3 * nf + s3] * vals[s];
+      v += Pk[0][c1 * nf + s1] * Pk[1][c2 * nf + s2] * Pk[2][c3 * nf + s3] * vals[s];
     }
     co[e] = a.body[comp] * v;
   }
@@ -192,12 +194,12 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
     __syncthreads();
     for (int e = tid; e < 3 * npi; e += 64) {
       const int comp = e / npi, C = e - comp * npi;
-      const int c[3] = {C % q1, (C / q1) % q1, C / (q1 * q1)};
+      const int c[3] = {C % q1[0], (C / q1[0]) % q1[1], C / (q1[0] * q1[1])};
       double r = 0.0;
-      if (touched && c[d] == (side ? a.q : 0)) {
+      if (touched && c[d] == (side ? a.qd[d] : 0)) {
         for (int s = 0; s < nf * nf; ++s) {
           const int su = s % nf, sv = s / nf;
-          r += a.fP[c[u] * nf + su] * a.fP[c[v] * nf + sv] * vals[s];
+          r += Pk[u][c[u] * nf + su] * Pk[v][c[v] * nf + sv] * vals[s];
         }
         r *= a.traction[f][comp];
       }
@@ -271,8 +273,8 @@ static igamt_status load_fit_launch(igamt_plan *P, const double *body, const dou
   a.wts = P->dev.macro_w;
   a.n_tiles = P->n_tiles;
   a.fx = P->dev.fit_x;
-  a.fP = P->dev.fit_P;
-  a.q = P->q;
+  a.fP3 = P->dev.fit_P3;
+  for (int k = 0; k < 3; ++k) a.qd[k] = P->qd[k];
   a.nf = P->n_fit;
   a.npi = P->npi;
   a.coef = d_coef;
@@ -305,7 +307,6 @@ static bool finite_loads(const double *body, const double *traction) {
 
 extern "C" igamt_status igamt_load_table_build(igamt_plan *P, void *stream) {
   if (!P) { set_error("NULL argument"); return IGAMT_EINVAL; }
-  if (P->aniso) { set_error("the load vector uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (P->pT[0] != P->pT[1] || P->pT[0] != P->pT[2]) {
@@ -325,7 +326,7 @@ extern "C" igamt_status igamt_load_table_build(igamt_plan *P, void *stream) {
   a.gx = P->dev.gauss_x;
   a.gw = P->dev.gauss_w;
   a.ng = P->n_gauss;
-  a.q = P->q;
+  for (int k = 0; k < 3; ++k) a.qd[k] = P->qd[k];
   a.npi = P->npi;
   a.stride = stride;
   a.pts = P->dev.point_data;
@@ -363,7 +364,6 @@ extern "C" igamt_status igamt_load_fit(igamt_plan *P, const double *body, const 
                                        void *stream) {
   if (!P || !body || !traction || !d_coef) { set_error("NULL argument"); return IGAMT_EINVAL; }
   if (!finite_loads(body, traction)) { set_error("non-finite body force or traction"); return IGAMT_EINVAL; }
-  if (P->aniso) { set_error("the load vector uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   igamt_status st = ensure_device(P);
   if (st) return st;
   return load_fit_launch(P, body, traction, d_coef, (hipStream_t)stream);

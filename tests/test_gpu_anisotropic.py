@@ -92,9 +92,7 @@ def test_isotropic_only_entry_points_refuse(env):
     w = _aniso((1, 2, 2))
     plan = P.Plan.from_workload(w)
     plan.tables_build()
-    for call in (plan.load_table_build,
-                 lambda: plan.load_fit(np.zeros(3)),
-                 lambda: plan.uKu_grad(w.E, w.nu, torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda"))):
+    for call in (lambda: plan.uKu_grad(w.E, w.nu, torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda")),):
         with pytest.raises(P.IgamtError) as e:
             call()
         assert e.value.code == -6
@@ -117,3 +115,26 @@ def test_anisotropic_volume_vs_oracle(env):
     assert np.abs(tv.cpu().numpy() - ref_tv).max() <= 1e-13 * np.abs(ref_tv).max()
     ref_g = volume.volume_grad(w, ref_tpi).reshape(-1, 3)
     assert np.abs(g.cpu().numpy() - ref_g).max() <= 1e-11 * np.abs(ref_g).max()
+
+
+def test_anisotropic_load_vector_vs_oracle(env):
+    torch, P = env
+    from oracle import load
+    for q, name, kw, tiles in [((1, 2, 3), "cfg1", {}, None), ((2, 0, 1), "cfg4", {"n_boxes": 4}, (3, 2, 5))]:
+        w = _aniso(q, name, **kw)
+        if tiles is not None:
+            w = dataclasses.replace(w, tiles=tiles)
+        plan = P.Plan.from_workload(w)
+        plan.load_table_build()
+        got_t = plan.load_table_get().cpu().numpy()
+        ref_t = load.load_table(w.tile, w.q, w.n_gauss)
+        assert np.abs(got_t - ref_t).max() <= 1e-13 * np.abs(ref_t).max()
+        body = np.array([0.3, -1.2, 0.7])
+        tr = np.zeros((6, 3))
+        tr[1] = [1.0, 0.0, 0.5]
+        tr[4] = [0.0, -2.0, 1.0]
+        f = plan.load_assemble(body, tr).cpu().numpy()
+        ref = load.assemble_load(w, ref_t, body, tr)
+        e = np.linalg.norm(f - ref) / np.linalg.norm(ref)
+        _say(f"q={q} {name} {w.tiles}: load vector rel err {e:.2e}")
+        assert e < 1e-13
