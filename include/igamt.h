@@ -81,8 +81,7 @@ typedef struct {
  *             n_pi = prod_k (q_k + 1) and n_fit >= max_k q_k + 1 (a
  *             least-squares fit in the directions of lower degree).  With
  *             anisotropic = 0, q in every direction and q_dir is not read.
- *             Plans whose degrees differ per direction run every entry point
- *             except the shape gradient (igamt_uKu_grad: IGAMT_EUNSUPPORTED). */
+ *             Every entry point takes plans whose degrees differ per direction. */
 typedef struct {
   int32_t tiles[3];
   int32_t box_mode;

@@ -76,8 +76,8 @@ struct FitAdjArgs {
   int tiles[3], Lc[3];
   int64_t n_tiles;
   const double *fx;
-  const double *fP;
-  int q, nf, Kp;
+  const double *fP3;      // per-direction 1-D projection operators [q1[k]][nf], concatenated
+  int q1[3], nf, Kp;
   bool w_f64;
   double lam, mu;
   const double *coef;   // [n_tiles_pad][9][Kp] FP64
@@ -92,20 +92,22 @@ constexpr int kFitAdjThreads = 256;   // threads per tile in the fit adjoint
 template <int PM>
 __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs a) {
   extern __shared__ double smem[];
-  const int nf = a.nf, q1 = a.q + 1;
-  const int ns = nf * nf * nf, npi = q1 * q1 * q1;
+  const int nf = a.nf, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
+  const int ns = nf * nf * nf, npi = q1x * q1y * q1z;
   double *FD = smem;                 // [ns][10]  F, D
   double *FB = FD + ns * 10;         // [ns][10]  Fbar (before the factor D), Dbar
   double *buf0 = FB + ns * 10;       // [max(ns, npi)][9]
   double *buf1 = buf0 + ns * 9;      // [ns][9]
-  __shared__ double Pm[(kMaxQ + 1) * kMaxFit];
+  __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
   __shared__ double NB[3][kMaxFit][kMaxDegree + 1], DB[3][kMaxFit][kMaxDegree + 1];
   __shared__ int SP[3][kMaxFit];
   __shared__ double red[kFitAdjThreads];
   const int tid = threadIdx.x;
   const int64_t t = blockIdx.x;
   const int64_t tbase = t * 9 * (int64_t)a.Kp;
-  for (int e = tid; e < q1 * nf; e += kFitAdjThreads) Pm[e] = a.fP[e];
+  for (int e = tid; e < q1x * nf; e += kFitAdjThreads) Pm[0][e] = a.fP3[e];
+  for (int e = tid; e < q1y * nf; e += kFitAdjThreads) Pm[1][e] = a.fP3[q1x * nf + e];
+  for (int e = tid; e < q1z * nf; e += kFitAdjThreads) Pm[2][e] = a.fP3[(q1x + q1y) * nf + e];
   const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
                      (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
   const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
@@ -167,18 +169,18 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
     }
     __syncthreads();
     // transpose of the z pass: buf1[(s3, c2, c1)][ab] = sum_c3 P[c3][s3] W[(c3, c2, c1)]
-    for (int e = tid; e < nf * q1 * q1 * 9; e += kFitAdjThreads) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1, c2 = (r / q1) % q1, s3 = r / (q1 * q1);
+    for (int e = tid; e < nf * q1y * q1x * 9; e += kFitAdjThreads) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1x, c2 = (r / q1x) % q1y, s3 = r / (q1x * q1y);
       double v = 0.0;
-      for (int c3 = 0; c3 < q1; ++c3) v += Pm[c3 * nf + s3] * buf0[((c3 * q1 + c2) * q1 + c1) * 9 + ab];
+      for (int c3 = 0; c3 < q1z; ++c3) v += Pm[2][c3 * nf + s3] * buf0[((c3 * q1y + c2) * q1x + c1) * 9 + ab];
       buf1[e] = v;
     }
     __syncthreads();
     // transpose of the y pass: buf0[(s3, s2, c1)][ab]
-    for (int e = tid; e < nf * nf * q1 * 9; e += kFitAdjThreads) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1, s2 = (r / q1) % nf, s3 = r / (q1 * nf);
+    for (int e = tid; e < nf * nf * q1x * 9; e += kFitAdjThreads) {
+      const int ab = e % 9, r = e / 9, c1 = r % q1x, s2 = (r / q1x) % nf, s3 = r / (q1x * nf);
       double v = 0.0;
-      for (int c2 = 0; c2 < q1; ++c2) v += Pm[c2 * nf + s2] * buf1[((s3 * q1 + c2) * q1 + c1) * 9 + ab];
+      for (int c2 = 0; c2 < q1y; ++c2) v += Pm[1][c2 * nf + s2] * buf1[((s3 * q1y + c2) * q1x + c1) * 9 + ab];
       buf0[e] = v;
     }
     __syncthreads();
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
     for (int e = tid; e < ns * 9; e += kFitAdjThreads) {
       const int ab = e % 9, s = e / 9, s1 = s % nf, s23 = s / nf;
       double v = 0.0;
-      for (int c1 = 0; c1 < q1; ++c1) v += Pm[c1 * nf + s1] * buf0[(s23 * q1 + c1) * 9 + ab];
+      for (int c1 = 0; c1 < q1x; ++c1) v += Pm[0][c1 * nf + s1] * buf0[(s23 * q1x + c1) * 9 + ab];
       buf1[e] = v;
     }
     __syncthreads();
@@ -378,7 +380,6 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
-  if (P->aniso) { set_error("the shape gradient uses one projection degree in every direction (anisotropic plan)"); return IGAMT_EUNSUPPORTED; }
   if (!P->wM.empty()) {
     set_error("the shape gradient is for B-spline macro maps (NURBS weights given)");
     return IGAMT_EUNSUPPORTED;
@@ -436,8 +437,8 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   f.wts = P->dev.macro_w;
   f.n_tiles = P->n_tiles;
   f.fx = P->dev.fit_x;
-  f.fP = P->dev.fit_P;
-  f.q = P->q;
+  f.fP3 = P->dev.fit_P3;
+  for (int k = 0; k < 3; ++k) f.q1[k] = P->qd[k] + 1;
   f.nf = P->n_fit;
   f.Kp = P->Kp;
   f.w_f64 = prec == IGAMT_F64;

@@ -87,15 +87,22 @@ def test_twisted_square_eproj_and_selection(env):
     assert q is None
 
 
-def test_isotropic_only_entry_points_refuse(env):
+def test_anisotropic_compliance_gradient_vs_oracle(env):
     torch, P = env
-    w = _aniso((1, 2, 2))
+    from oracle import adjoint
+    w = _aniso((1, 3, 2), "cfg4", n_boxes=3)
     plan = P.Plan.from_workload(w)
     plan.tables_build()
-    for call in (lambda: plan.uKu_grad(w.E, w.nu, torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda")),):
-        with pytest.raises(P.IgamtError) as e:
-            call()
-        assert e.value.code == -6
+    u = W.random_displacement(plan.n_dofs, 7)
+    val, grad = plan.uKu_grad(w.E, w.nu, torch.from_numpy(u).cuda(), "f64")
+    plan.check()
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    g_ref = adjoint.grad_uKu(w, T, pairs, u).reshape(-1, 3)
+    err = np.abs(grad.cpu().numpy().reshape(-1, 3) - g_ref).max() / np.abs(g_ref).max()
+    _say(f"anisotropic compliance gradient vs oracle: {err:.2e}")
+    assert err < 1e-10
+    assert val.item() == pytest.approx(adjoint.uKu(w, T, pairs, u), rel=1e-12)
 
 
 def test_anisotropic_volume_vs_oracle(env):

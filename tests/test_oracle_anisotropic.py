@@ -134,3 +134,22 @@ def test_anisotropic_load_table_and_affine_vector():
     fpi = load.assemble_load(w, load.load_table(w.tile, w.q, 3), body, tr)
     fstd = load.standard_load(w, body, tr)
     assert np.linalg.norm(fpi - fstd) <= 1e-13 * np.linalg.norm(fstd)
+
+
+def test_anisotropic_compliance_gradient_against_differences():
+    import dataclasses
+    from oracle import adjoint
+    w = dataclasses.replace(W.make("cfg4", n_boxes=2), q=(1, 3, 2), n_fit=4)
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    n = 3 * int(np.prod([w.tiles[k] * (w.tile.n_ctrl[k] - 1) + 1 for k in range(3)]))
+    u = W.random_displacement(n, 7)
+    g = adjoint.grad_uKu(w, T, pairs, u)
+    eps = 1e-6
+    for idx in [(1, 1, 1, 0), (2, 3, 1, 2)]:
+        vals = []
+        for sgn in (1, -1):
+            c = w.macro.ctrl.copy()
+            c[idx] += sgn * eps
+            vals.append(adjoint.uKu(dataclasses.replace(w, macro=dataclasses.replace(w.macro, ctrl=c)), T, pairs, u))
+        assert g[idx] == pytest.approx((vals[0] - vals[1]) / (2 * eps), rel=1e-6)
