@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 from .basis import bspline_basis, gauss01
-from .geometry import tile_boxes, tile_dofs, tile_index
+from .geometry import control_point_gradient, tile_boxes, tile_dofs, tile_index
 from .macro_field import lame, macro_field
 from .projection import projection_operator, tile_coefficients, tile_macro_jacobians
 
@@ -64,9 +64,7 @@ def tile_box(w, t):
 
 
 def grad_uKu(w, table, pairs, u, tiles=None):
-    """d(u^T K^pi u)/d m, shape like w.macro.ctrl (n_z, n_y, n_x, 3) (B-spline maps)."""
-    if getattr(w.macro, "weights", None) is not None:
-        raise ValueError("the control-point derivative here is for B-spline macro maps")
+    """d(u^T K^pi u)/d m, shape like w.macro.ctrl (n_z, n_y, n_x, 3) (NURBS: weights fixed)."""
     lam, mu = lame(w.E, w.nu)
     P = projection_operator(w.q, w.n_fit)
     x, _ = gauss01(w.n_fit)
@@ -82,14 +80,10 @@ def grad_uKu(w, table, pairs, u, tiles=None):
         Jbar = np.einsum("sc,smnc->smn", Abar, dA)     # dL/dJ at each sample
         a, h = tile_box(w, t)
         pts = [a[k] + h[k] * x for k in range(3)]
-        Bx, dBx = bspline_basis(w.macro.knots[0], w.macro.degree[0], pts[0], deriv=True)
-        By, dBy = bspline_basis(w.macro.knots[1], w.macro.degree[1], pts[1], deriv=True)
-        Bz, dBz = bspline_basis(w.macro.knots[2], w.macro.degree[2], pts[2], deriv=True)
-        # J[s, c, n] = h_n sum_k m_k,c dN_k/dx_n ;  samples s = (sz, sy, sx), x fastest
-        Jb = Jbar.reshape(len(x), len(x), len(x), 3, 3)
-        g += h[0] * np.einsum("zyxc,zk,yj,xi->kjic", Jb[..., 0], Bz, By, dBx)
-        g += h[1] * np.einsum("zyxc,zk,yj,xi->kjic", Jb[..., 1], Bz, dBy, Bx)
-        g += h[2] * np.einsum("zyxc,zk,yj,xi->kjic", Jb[..., 2], dBz, By, Bx)
+        # J[s, c, n] = h_n sum_k m_k,c dR_k/dx_n ;  samples s = (sz, sy, sx), x fastest
+        Jb = Jbar.reshape(len(x), len(x), len(x), 3, 3) * h[None, None, None, None, :]
+        g += control_point_gradient(w.macro.knots, w.macro.degree, getattr(w.macro, "weights", None),
+                                    pts[0], pts[1], pts[2], Jb)
     return g
 
 

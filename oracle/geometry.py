@@ -24,6 +24,44 @@ def _rational(X, J, W, dW):
     return M, Jr
 
 
+def rational_grid_terms(knots, degree, weights, xs, ys, zs):
+    """Basis tensors of a NURBS control-point derivative on the grid xs x ys x zs: the 1-D
+    B-spline values and derivatives per direction, and W = sum w N with its gradient
+    (shapes (len(zs), len(ys), len(xs)) and (..., 3)).  With R_i = w_i N_i / W,
+    d_n R_i = w_i (d_n N_i - N_i d_n W / W) / W."""
+    Bx, dBx = bspline_basis(knots[0], degree[0], xs, deriv=True)
+    By, dBy = bspline_basis(knots[1], degree[1], ys, deriv=True)
+    Bz, dBz = bspline_basis(knots[2], degree[2], zs, deriv=True)
+    wt = np.asarray(weights, dtype=np.float64)
+    W = np.einsum("zk,yj,xi,kji->zyx", Bz, By, Bx, wt, optimize=True)
+    dW = np.stack([np.einsum("zk,yj,xi,kji->zyx", Bz, By, dBx, wt, optimize=True),
+                   np.einsum("zk,yj,xi,kji->zyx", Bz, dBy, Bx, wt, optimize=True),
+                   np.einsum("zk,yj,xi,kji->zyx", dBz, By, Bx, wt, optimize=True)], axis=-1)
+    return (Bx, dBx), (By, dBy), (Bz, dBz), W, dW
+
+
+def control_point_gradient(knots, degree, weights, xs, ys, zs, G):
+    """g[k, j, i, c] = sum over the grid s of sum_n G[s, c, n] d_n R_(i,j,k)(s), G of shape
+    (len(zs), len(ys), len(xs), 3, 3) (n: the parameter direction); R the B-spline basis when
+    weights is None, else the NURBS basis."""
+    if weights is None:
+        Bx, dBx = bspline_basis(knots[0], degree[0], xs, deriv=True)
+        By, dBy = bspline_basis(knots[1], degree[1], ys, deriv=True)
+        Bz, dBz = bspline_basis(knots[2], degree[2], zs, deriv=True)
+        g = np.einsum("zyxc,zk,yj,xi->kjic", G[..., 0], Bz, By, dBx)
+        g += np.einsum("zyxc,zk,yj,xi->kjic", G[..., 1], Bz, dBy, Bx)
+        g += np.einsum("zyxc,zk,yj,xi->kjic", G[..., 2], dBz, By, Bx)
+        return g
+    (Bx, dBx), (By, dBy), (Bz, dBz), W, dW = rational_grid_terms(knots, degree, weights, xs, ys, zs)
+    Gw = G / W[..., None, None]
+    H = np.einsum("zyxcn,zyxn->zyxc", G, dW) / (W * W)[..., None]
+    g = np.einsum("zyxc,zk,yj,xi->kjic", Gw[..., 0], Bz, By, dBx)
+    g += np.einsum("zyxc,zk,yj,xi->kjic", Gw[..., 1], Bz, dBy, Bx)
+    g += np.einsum("zyxc,zk,yj,xi->kjic", Gw[..., 2], dBz, By, Bx)
+    g -= np.einsum("zyxc,zk,yj,xi->kjic", H, Bz, By, Bx)
+    return g * np.asarray(weights, dtype=np.float64)[..., None]
+
+
 def eval_volume_grid(degree, knots, ctrl, xs, ys, zs, weights=None):
     """Map value X and Jacobian J on the tensor grid xs x ys x zs (each 1-D).
 

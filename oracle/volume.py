@@ -18,7 +18,7 @@ from __future__ import annotations
 import numpy as np
 
 from .basis import bspline_basis, gauss01
-from .geometry import tile_boxes, tile_index
+from .geometry import control_point_gradient, tile_boxes, tile_index
 from .projection import bernstein3, degrees, fit_points, n_pi, projection_operator, tile_macro_jacobians
 from .tables import element_points, micro_elements
 
@@ -93,9 +93,8 @@ def adjoint_field(q, t_pi: np.ndarray, pts: np.ndarray) -> np.ndarray:
 
 
 def volume_grad(w, t_pi: np.ndarray) -> np.ndarray:
-    """dV/dm (eq. (66)), shape (n_z, n_y, n_x, 3) like the macro control points (B-spline maps)."""
-    if w.macro.weights is not None:
-        raise ValueError("the control-point derivative here is for B-spline macro maps")
+    """dV/dm (eq. (66)), shape (n_z, n_y, n_x, 3) like the macro control points; for a NURBS map
+    the derivative of J by a control point is the rational basis' gradient (weights fixed)."""
     nz, ny, nx = w.macro.ctrl.shape[:3]
     grad = np.zeros((nz, ny, nx, 3))
     xg, _ = gauss01(w.n_fit)
@@ -107,15 +106,12 @@ def volume_grad(w, t_pi: np.ndarray) -> np.ndarray:
         tx, ty, tz = tile_index(w, t)
         a = [boxes[0][0][tx], boxes[1][0][ty], boxes[2][0][tz]]
         h = [boxes[0][1][tx], boxes[1][1][ty], boxes[2][1][tz]]
-        B = [bspline_basis(w.macro.knots[k], w.macro.degree[k], a[k] + h[k] * xg, deriv=True) for k in range(3)]
         J = tile_macro_jacobians(w, t)                   # (S, 3, 3), includes diag(h)
         D = np.linalg.det(J)
         F = np.linalg.inv(J)
         # per sample s = sx + nf (sy + nf sz): G[s, c, n] = w_s v_s D_s F[n, c] h_n
         G = (wts * v * D)[:, None, None] * np.transpose(F, (0, 2, 1)) * np.array(h)[None, None, :]
         G = G.reshape(nf, nf, nf, 3, 3)                  # (sz, sy, sx, c, n)
-        (Nx, dNx), (Ny, dNy), (Nz, dNz) = B
-        grad += np.einsum("zyxc,zk,yj,xi->kjic", G[..., 0], Nz, Ny, dNx)
-        grad += np.einsum("zyxc,zk,yj,xi->kjic", G[..., 1], Nz, dNy, Nx)
-        grad += np.einsum("zyxc,zk,yj,xi->kjic", G[..., 2], dNz, Ny, Nx)
+        grad += control_point_gradient(w.macro.knots, w.macro.degree, w.macro.weights,
+                                       a[0] + h[0] * xg, a[1] + h[1] * xg, a[2] + h[2] * xg, G)
     return grad

@@ -58,3 +58,28 @@ def test_torus_volume_closed_form():
     # the projection error of the macro field of a rational map falls with q as well
     e = [adaptive.eproj(w, q) for q in (2, 3, 4)]
     assert e[0] > e[1] > e[2] > 0
+
+
+def test_nurbs_gradients_against_differences():
+    """Volume and compliance gradients of the rational torus map (weights fixed) against central
+    differences of the oracle's own V^pi and u^T K^pi u."""
+    from oracle import adjoint, tables
+    w = W.make("nurbs_torus", n_boxes=2)
+    t_h = volume.volume_table(w.tile, w.q, w.n_gauss)
+    gv = volume.volume_grad(w, volume.folded_table(w.q, t_h))
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    n = 3 * int(np.prod([w.tiles[k] * (w.tile.n_ctrl[k] - 1) + 1 for k in range(3)]))
+    u = W.random_displacement(n, 5) * 0.1
+    gc = adjoint.grad_uKu(w, T, pairs, u)
+    eps = 1e-6
+    for idx in [(1, 1, 1, 0), (0, 2, 1, 2), (2, 0, 2, 1)]:
+        vv, cc = [], []
+        for sgn in (1, -1):
+            c = w.macro.ctrl.copy()
+            c[idx] += sgn * eps
+            ws = dataclasses.replace(w, macro=dataclasses.replace(w.macro, ctrl=c))
+            vv.append(volume.volume(ws, t_h))
+            cc.append(adjoint.uKu(ws, T, pairs, u))
+        assert gv[idx] == pytest.approx((vv[0] - vv[1]) / (2 * eps), rel=1e-6, abs=1e-9)
+        assert gc[idx] == pytest.approx((cc[0] - cc[1]) / (2 * eps), rel=1e-6, abs=1e-9)
