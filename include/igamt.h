@@ -54,9 +54,9 @@ typedef struct igamt_plan igamt_plan;
  * ctrl: [n_ctrl[2]][n_ctrl[1]][n_ctrl[0]][3], x fastest.
  * weights: NULL for a B-spline; else [n_ctrl[2]][n_ctrl[1]][n_ctrl[0]]
  *   positive NURBS weights (rational basis w_i N_i / sum_j w_j N_j).  Accepted
- *   for the macro map (fit, load vector, volume, projection error; the shape
- *   gradients return IGAMT_EUNSUPPORTED); the tile must be a B-spline
- *   (IGAMT_EUNSUPPORTED).                                                     */
+ *   for the macro map by every entry point (the shape gradients differentiate
+ *   with respect to the control points, weights fixed); the tile must be a
+ *   B-spline (IGAMT_EUNSUPPORTED).                                            */
 typedef struct {
   int32_t degree[3];
   int32_t n_ctrl[3];

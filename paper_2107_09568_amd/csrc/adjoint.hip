@@ -246,7 +246,17 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
       for (int n = 0; n < 3; ++n) fb[3 * c + n] = Jb[c][n] * hx[n];
   }
   __syncthreads();
-  // local control-point gradients: mbar[i][c] = sum_s sum_n JbarH[s][c][n] d_n N_i(s)
+  // NURBS: 1 / W and sum_n JbarH[c][n] d_n W / W^2 per sample (buf0 is free here)
+  double *WQ = buf0;
+  if (a.wts) {
+    for (int s = tid; s < ns; s += kFitAdjThreads) {
+      const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
+      rational_terms<PM>(a.wts, a.nM, SP, NB, DB, si, FB + s * 10, WQ + s * 4);
+    }
+    __syncthreads();
+  }
+  // local control-point gradients: mbar[i][c] = sum_s sum_n JbarH[s][c][n] d_n R_i(s)
+  // (R_i = N_i for a B-spline map; w_i (d_n N_i - N_i d_n W / W) / W for a NURBS map)
   const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2];
   const int lo[3] = {a.ctrl_lo[0][tt[0]], a.ctrl_lo[1][tt[1]], a.ctrl_lo[2][tt[2]]};
   double *lg = a.local_grad + t * (int64_t)L0 * L1 * L2 * 3;
@@ -266,9 +276,11 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
       }
       if (!on) continue;
       const double *jb = FB + s * 10 + 3 * c;
-      g += jb[0] * d[0] * v[1] * v[2] + jb[1] * v[0] * d[1] * v[2] + jb[2] * v[0] * v[1] * d[2];
+      const double tb = jb[0] * d[0] * v[1] * v[2] + jb[1] * v[0] * d[1] * v[2] + jb[2] * v[0] * v[1] * d[2];
+      g += a.wts ? tb * WQ[s * 4] - v[0] * v[1] * v[2] * WQ[s * 4 + 1 + c] : tb;
     }
-    lg[e] = g;
+    lg[e] = a.wts ? g * a.wts[(lo[0] + l[0]) + (int64_t)a.nM[0] * ((lo[1] + l[1]) + (int64_t)a.nM[1] * (lo[2] + l[2]))]
+                  : g;
   }
 }
 
@@ -380,10 +392,6 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
-  if (!P->wM.empty()) {
-    set_error("the shape gradient is for B-spline macro maps (NURBS weights given)");
-    return IGAMT_EUNSUPPORTED;
-  }
   if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
     set_error("macro maps with different degrees per direction are not supported");
     return IGAMT_EUNSUPPORTED;

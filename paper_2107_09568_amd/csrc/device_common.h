@@ -225,6 +225,31 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
   }
 }
 
+// NURBS control-point derivatives at one sample of a tensor grid: from the 1-D B-spline values NB
+// and derivatives DB at the sample's abscissae si (spans SP), W = sum w N and d_n W; then with
+// G[c][n] the sample's weights of d_n R_i (R_i = w_i N_i / W, d_n R_i = w_i (d_n N_i - N_i d_n W / W) / W):
+// out[0] = 1 / W, out[1 + c] = sum_n G[c][n] d_n W / W^2.
+template <int PM, int MF, int MD>
+__device__ inline void rational_terms(const double *__restrict__ wts, const int *nM, const int (&SP)[3][MF],
+                                      const double (&NB)[3][MF][MD], const double (&DB)[3][MF][MD],
+                                      const int (&si)[3], const double *G, double *out) {
+  double W = 0.0, dW[3] = {0.0, 0.0, 0.0};
+  for (int rz = 0; rz <= PM; ++rz)
+    for (int ry = 0; ry <= PM; ++ry)
+      for (int rx = 0; rx <= PM; ++rx) {
+        const int ix = SP[0][si[0]] - PM + rx, iy = SP[1][si[1]] - PM + ry, iz = SP[2][si[2]] - PM + rz;
+        const double wi = wts[ix + (int64_t)nM[0] * (iy + (int64_t)nM[1] * iz)];
+        const double nx = NB[0][si[0]][rx], ny = NB[1][si[1]][ry], nz = NB[2][si[2]][rz];
+        W += wi * nx * ny * nz;
+        dW[0] += wi * DB[0][si[0]][rx] * ny * nz;
+        dW[1] += wi * nx * DB[1][si[1]][ry] * nz;
+        dW[2] += wi * nx * ny * DB[2][si[2]][rz];
+      }
+  const double r = 1.0 / W;
+  out[0] = r;
+  for (int c = 0; c < 3; ++c) out[1 + c] = (G[3 * c] * dW[0] + G[3 * c + 1] * dW[1] + G[3 * c + 2] * dW[2]) * r * r;
+}
+
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace igamt

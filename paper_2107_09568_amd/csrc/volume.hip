@@ -87,7 +87,7 @@ struct VolumeTileArgs {
 
 template <int PM>
 __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
-  extern __shared__ double GS[];    // [ns][9]: g_s D_s (J^-1)[n][c] h_n at [3 c + n]
+  extern __shared__ double GS[];    // [ns][9]: g_s D_s (J^-1)[n][c] h_n at [3 c + n]; NURBS: then WQ [ns][4]
   __shared__ double NB[3][kMaxFit][kMaxDegree + 1], DB[3][kMaxFit][kMaxDegree + 1];
   __shared__ int SP[3][kMaxFit];
   __shared__ double red[64];
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
   const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
   const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
   const bool grad = a.local_grad != nullptr;
+  double *WQ = GS + ns * 9;   // NURBS: 1 / W and sum_n GS[c][n] d_n W / W^2 per sample
   if (grad)
     for (int e = tid; e < 3 * nf; e += 64) {
       const int k = e / nf, s = e % nf;
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
       SP[k][s] = sp;
       for (int r = 0; r <= PM; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
     }
+  __syncthreads();   // the basis tables are read by the sample loop (NURBS) and the local gradients
   double vol = 0.0;
   for (int s = tid; s < ns; s += 64) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
@@ -140,6 +142,7 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int n = 0; n < 3; ++n) GS[s * 9 + 3 * c + n] = gs * cof[c][n] * hx[n];
+      if (a.wts) rational_terms<PM>(a.wts, a.nM, SP, NB, DB, si, GS + s * 9, WQ + s * 4);
     }
   }
   red[tid] = vol;
@@ -170,9 +173,11 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
       }
       if (!on) continue;
       const double *gc = GS + s * 9 + 3 * c;
-      gsum += gc[0] * d[0] * v[1] * v[2] + gc[1] * v[0] * d[1] * v[2] + gc[2] * v[0] * v[1] * d[2];
+      const double tb = gc[0] * d[0] * v[1] * v[2] + gc[1] * v[0] * d[1] * v[2] + gc[2] * v[0] * v[1] * d[2];
+      gsum += a.wts ? tb * WQ[s * 4] - v[0] * v[1] * v[2] * WQ[s * 4 + 1 + c] : tb;
     }
-    lg[e] = gsum;
+    lg[e] = a.wts ? gsum * a.wts[(lo[0] + l[0]) + (int64_t)a.nM[0] * ((lo[1] + l[1]) + (int64_t)a.nM[1] * (lo[2] + l[2]))]
+                  : gsum;
   }
 }
 
@@ -274,10 +279,6 @@ extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, doub
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->volume_ready) { set_error("volume table not built"); return IGAMT_ESTATE; }
-  if (d_grad && !P->wM.empty()) {
-    set_error("the volume gradient is for B-spline macro maps (NURBS weights given)");
-    return IGAMT_EUNSUPPORTED;
-  }
   if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
     set_error("macro maps with different degrees per direction are not supported");
     return IGAMT_EUNSUPPORTED;
@@ -305,7 +306,7 @@ extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, doub
   a.local_grad = d_grad ? lg : nullptr;
   a.flag = P->dev.flag;
   const int ns = P->n_fit * P->n_fit * P->n_fit;
-  const size_t shm = d_grad ? (size_t)ns * 9 * sizeof(double) : 0;
+  const size_t shm = d_grad ? (size_t)ns * (9 + 4) * sizeof(double) : 0;
   const dim3 grid((unsigned)P->n_tiles), block(64);
   switch (P->pM[0]) {
     case 1: hipLaunchKernelGGL(volume_tile_kernel<1>, grid, block, shm, s, a); break;

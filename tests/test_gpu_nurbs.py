@@ -1,6 +1,6 @@
 """GPU parity on the exact NURBS quarter torus (rational macro map) against the oracle: tile
-blocks, load vector, volume (and its closed form), projection error; the shape gradients refuse
-rational maps."""
+blocks, load vector, volume (and its closed form), projection error, and the volume and compliance
+gradients with respect to the control points (weights fixed)."""
 import numpy as np
 import pytest
 
@@ -66,9 +66,6 @@ def test_volume_vs_oracle_and_closed_form(case):
     _say(f"nurbs torus: V(q=2) {v.item():.12f}, V(q=5) {v5:.12f}, exact {exact:.12f}")
     assert abs(v5 - exact) < 1e-8 * exact
     assert abs(v5 - exact) < abs(v.item() - exact)
-    with pytest.raises(P.IgamtError) as e:
-        plan.volume(grad=True)
-    assert e.value.code == -6
 
 
 def test_eproj_vs_oracle(case):
@@ -80,9 +77,24 @@ def test_eproj_vs_oracle(case):
         assert abs(e - ref) <= 1e-9 * ref
 
 
-def test_shape_gradient_refuses_rational_maps(case):
+def test_nurbs_gradients_vs_oracle(case):
+    """Volume and compliance gradients of the rational map (weights fixed) against the oracle."""
     torch, P, w, plan = case
-    u = torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda")
-    with pytest.raises(P.IgamtError) as e:
-        plan.uKu_grad(w.E, w.nu, u)
-    assert e.value.code == -6
+    from oracle import adjoint
+    plan.volume_table_build()
+    _, _, g = plan.volume(grad=True)
+    plan.check()
+    t_h = volume.volume_table(w.tile, w.q, w.n_gauss)
+    ref = volume.volume_grad(w, volume.folded_table(w.q, t_h)).reshape(-1, 3)
+    e = np.abs(g.cpu().numpy() - ref).max() / np.abs(ref).max()
+    _say(f"nurbs torus: volume gradient rel err {e:.2e}")
+    assert e < 1e-12
+    u = W.random_displacement(plan.n_dofs, 5) * 0.1
+    val, grad = plan.uKu_grad(w.E, w.nu, torch.from_numpy(u).cuda(), "f64")
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    refc = adjoint.grad_uKu(w, T, pairs, u).reshape(-1, 3)
+    e = np.abs(grad.cpu().numpy().reshape(-1, 3) - refc).max() / np.abs(refc).max()
+    _say(f"nurbs torus: compliance gradient rel err {e:.2e}")
+    assert e < 1e-10
+    assert val.item() == pytest.approx(adjoint.uKu(w, T, pairs, u), rel=1e-12)
