@@ -213,6 +213,12 @@ def bench_linop(torch, W, P, plan, w, steps, warmup):
                            "effective_GBps": nb / (ms * 1e-3) / 1e9}
     ref = y.clone()
     out["rel_err_vs_csr"] = {k: ((v - ref).norm() / ref.norm()).item() for k, v in ys.items()}
+    # the product from stored FP64 blocks is bound by HBM: algorithmic bytes (blocks once, u once,
+    # tile products written and read by the gather, y written) per call against 8 TB/s
+    a = out["apply_blocks_f64"]
+    out["roofline_apply_blocks_f64"] = {"bound": "hbm", "achieved": a["effective_GBps"], "peak": 8000.0,
+                                        "unit": "GB/s", "frac": a["effective_GBps"] / 8000.0,
+                                        "bytes_per_call": a["bytes"]}
     out["onthefly_equals_stored_bitwise"] = all(torch.equal(ys["apply_blocks_f64"], ys[k])
                                                 for k in ys if k.startswith("linop_f64"))
     plan.check()
@@ -555,6 +561,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_tiles)
         log("bench: cpu baseline, one thread")
         out["cpu_baseline_1thread"] = cpu_baseline(w, max(256, args.cpu_tiles // 8), one_thread=True)
+        out["cpu_baseline"]["note"] = ("cores counts the BLAS threads the oracle's table contraction may use; the "
+                                       "one-thread run (cpu_baseline_1thread) reaches about the same rate, so most "
+                                       "of the oracle's time is single-threaded numpy")
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
