@@ -6,7 +6,8 @@
 // Bernstein space from q + 1 Gauss-Legendre nodes per direction (the fit of eq. (42) at degree q).
 // The samples are a uniform tensor grid with both ends, x_k = k / (n_s - 1), in box coordinates.
 // Per tile one 256-thread workgroup: F = J^-1 and D = det J at the fit nodes and the samples (LDS);
-// for each (i, j) block of A, the nine components' coefficients, then their values at the samples;
+// for each (i, j) block of A, the nine components at the fit nodes, their coefficients by three 1-D
+// passes (one operator per direction), their values at the samples by three 1-D Bernstein passes;
 // per sample the squared Frobenius error and norm accumulate over the blocks.  The maxima are
 // order-free, so the result is deterministic.  Eq. (65): the first q from the macro degree up
 // whose E_proj meets the tolerance (a host loop over this kernel).
@@ -69,11 +70,13 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x, nf = a.nf, ns1 = a.n_s, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
   const int nfit = nf * nf * nf, nsmp = ns1 * ns1 * ns1, npi = q1x * q1y * q1z;
+  const int nbuf = 9 * max(nfit, nsmp);
   double *FDf = smem;                 // [nfit][10]
   double *FDs = FDf + nfit * 10;      // [nsmp][10]
-  double *cf = FDs + nsmp * 10;       // [9][npi]
-  double *err2 = cf + 9 * npi;        // [nsmp]
+  double *err2 = FDs + nsmp * 10;     // [nsmp]
   double *nrm2 = err2 + nsmp;         // [nsmp]
+  double *b0 = nrm2 + nsmp;           // ping-pong buffers of the sum-factorised passes, [9][...]
+  double *b1 = b0 + nbuf;
   __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
   __shared__ double Bs[3][kMaxSample][kMaxQ + 1];
   __shared__ double red[256];
@@ -103,38 +106,62 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
   __syncthreads();
   for (int ij = 0; ij < 9; ++ij) {
     const int i = ij / 3, j = ij % 3;
-    for (int e = tid; e < 9 * npi; e += 256) {
-      const int ab = e / npi, C = e % npi;
-      const int c0 = C % q1x, c1 = (C / q1x) % q1y, c2 = C / (q1x * q1y);
-      const int aa = ab / 3, bb = ab % 3;
-      double s = 0.0;
-      int sp = 0;
-      for (int s2 = 0; s2 < nf; ++s2) {
-        const double p2 = Pm[2][c2 * nf + s2];
-        for (int s1 = 0; s1 < nf; ++s1) {
-          const double p12 = p2 * Pm[1][c1 * nf + s1];
-          for (int s0 = 0; s0 < nf; ++s0, ++sp)
-            s += p12 * Pm[0][c0 * nf + s0] * field_component(FDf + sp * 10, i, j, aa, bb, a.lam, a.mu);
-        }
-      }
-      cf[e] = s;
+    // the nine components A_ij,ab at the fit nodes: b0[ab][s], s = s1 + nf (s2 + nf s3)
+    for (int e = tid; e < 9 * nfit; e += 256) {
+      const int ab = e / nfit, sp = e % nfit;
+      b0[e] = field_component(FDf + sp * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
     }
     __syncthreads();
+    // projection, one direction at a time: x: b1[ab][(s3, s2), c1]
+    for (int e = tid; e < 9 * nf * nf * q1x; e += 256) {
+      const int c1 = e % q1x, r = e / q1x, s23 = r % (nf * nf), ab = r / (nf * nf);
+      const double *src = b0 + (int64_t)ab * nfit + s23 * nf;
+      double v = 0.0;
+      for (int s1 = 0; s1 < nf; ++s1) v += Pm[0][c1 * nf + s1] * src[s1];
+      b1[e] = v;
+    }
+    __syncthreads();
+    // y: b0[ab][s3, c2, c1]
+    for (int e = tid; e < 9 * nf * q1y * q1x; e += 256) {
+      const int c1 = e % q1x, c2 = (e / q1x) % q1y, r = e / (q1x * q1y), s3 = r % nf, ab = r / nf;
+      double v = 0.0;
+      for (int s2 = 0; s2 < nf; ++s2) v += Pm[1][c2 * nf + s2] * b1[((int64_t)(ab * nf + s3) * nf + s2) * q1x + c1];
+      b0[e] = v;
+    }
+    __syncthreads();
+    // z: b1[ab][C], C = c1 + q1x (c2 + q1y c3): the coefficients of the nine components
+    for (int e = tid; e < 9 * npi; e += 256) {
+      const int C = e % npi, ab = e / npi, c12 = C % (q1x * q1y), c3 = C / (q1x * q1y);
+      double v = 0.0;
+      for (int s3 = 0; s3 < nf; ++s3) v += Pm[2][c3 * nf + s3] * b0[((int64_t)ab * nf + s3) * q1x * q1y + c12];
+      b1[e] = v;
+    }
+    __syncthreads();
+    // evaluation at the samples, one direction at a time: x: b0[ab][(c3, c2), k0]
+    for (int e = tid; e < 9 * q1z * q1y * ns1; e += 256) {
+      const int k0 = e % ns1, r = e / ns1, c23 = r % (q1y * q1z), ab = r / (q1y * q1z);
+      const double *src = b1 + (int64_t)ab * npi + c23 * q1x;
+      double v = 0.0;
+      for (int c1 = 0; c1 < q1x; ++c1) v += Bs[0][k0][c1] * src[c1];
+      b0[e] = v;
+    }
+    __syncthreads();
+    // y: b1[ab][c3, k1, k0]
+    for (int e = tid; e < 9 * q1z * ns1 * ns1; e += 256) {
+      const int k0 = e % ns1, k1 = (e / ns1) % ns1, r = e / (ns1 * ns1), c3 = r % q1z, ab = r / q1z;
+      double v = 0.0;
+      for (int c2 = 0; c2 < q1y; ++c2) v += Bs[1][k1][c2] * b0[((int64_t)(ab * q1z + c3) * q1y + c2) * ns1 + k0];
+      b1[e] = v;
+    }
+    __syncthreads();
+    // z and the per-sample error: thread per sample k = k0 + ns1 (k1 + ns1 k2)
     for (int k = tid; k < nsmp; k += 256) {
-      const int k0 = k % ns1, k1 = (k / ns1) % ns1, k2 = k / (ns1 * ns1);
+      const int k01 = k % (ns1 * ns1), k2 = k / (ns1 * ns1);
       double e2 = 0.0, n2 = 0.0;
       for (int ab = 0; ab < 9; ++ab) {
-        const double ex = field_component(FDs + k * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
-        const double *c = cf + ab * npi;
         double pr = 0.0;
-        int C = 0;
-        for (int c2 = 0; c2 < q1z; ++c2) {
-          const double b2 = Bs[2][k2][c2];
-          for (int c1 = 0; c1 < q1y; ++c1) {
-            const double b12 = b2 * Bs[1][k1][c1];
-            for (int c0 = 0; c0 < q1x; ++c0, ++C) pr += c[C] * b12 * Bs[0][k0][c0];
-          }
-        }
+        for (int c3 = 0; c3 < q1z; ++c3) pr += Bs[2][k2][c3] * b1[((int64_t)ab * q1z + c3) * ns1 * ns1 + k01];
+        const double ex = field_component(FDs + k * 10, i, j, ab / 3, ab % 3, a.lam, a.mu);
         e2 += (ex - pr) * (ex - pr);
         n2 += ex * ex;
       }
@@ -212,8 +239,8 @@ static igamt_status eproj_run(igamt_plan *P, double E, double nu, const int (&q)
   a.mu = E / (2.0 * (1.0 + nu));
   a.tile_e = d_tile_e ? d_tile_e : buf;
   a.flag = P->dev.flag;
-  const int nfit = nf * nf * nf, nsmp = n_s * n_s * n_s, npi = (q[0] + 1) * (q[1] + 1) * (q[2] + 1);
-  const size_t shm = (size_t)(10 * nfit + 10 * nsmp + 9 * npi + 2 * nsmp) * sizeof(double);
+  const int nfit = nf * nf * nf, nsmp = n_s * n_s * n_s;
+  const size_t shm = (size_t)(10 * nfit + 10 * nsmp + 2 * nsmp + 2 * 9 * std::max(nfit, nsmp)) * sizeof(double);
   const dim3 grid((unsigned)P->n_tiles), block(256);
   switch (P->pM[0]) {
 #define EP_CASE(p)                                                                                        \
