@@ -5,7 +5,8 @@
 // F = J^-1 and D = det J in FP64.  The projection coefficients
 //   <A_ij,ab>_C = sum_s P[C, s] A_ij,ab(xi_s),  P = P1 (x) P1 (x) P1,
 // (eq. (42) with the 1-D operator of eq. (23)-(24)) are applied sum-factorised,
-// one direction at a time, for one (i, j) block of A at a time, with
+// one direction at a time, for one component (a, b) of A at a time (its nine (i, j) blocks
+// side by side, so that each coefficient row is written contiguously), with
 //   A_ij,ab = D (lam F_ia F_jb + mu (F_i . F_j) delta_ab + mu F_ib F_ja),
 // the Cartesian form of eq. (37) (F_i is row i of F).  The result is written in
 // the column-major layout the contraction reads: coef[t][3a+b][9C+3i+j].
@@ -61,8 +62,6 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   double *buf0 = FD + ns * 10;    // [ns][9]
   double *buf1 = buf0 + ns * 9;   // [ns][9]
   __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
-  __shared__ double colmax[64][9];
-  __shared__ double scale[9];
   const int tid = threadIdx.x;
   const int64_t t = a.t0 + blockIdx.x;
   const int64_t tbase = t * 9 * (int64_t)a.Kp;
@@ -81,9 +80,6 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   const int tz = (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]));
   const double ax[3] = {a.box_a[0][tx], a.box_a[1][ty], a.box_a[2][tz]};
   const double hx[3] = {a.box_h[0][tx], a.box_h[1][ty], a.box_h[2][tz]};
-  double cmax[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) cmax[k] = 0.0;
 
   // Jacobians at the samples
   for (int s = tid; s < ns; s += 64) {
@@ -105,27 +101,11 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) FD[s * 10 + 3 * r + c] = F[r][c];
     FD[s * 10 + 9] = D;
-    if (a.prec == IGAMT_F16X3) {
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          const double fij = F[i][0] * F[j][0] + F[i][1] * F[j][1] + F[i][2] * F[j][2];
-          for (int aa = 0; aa < 3; ++aa)
-            for (int bb = 0; bb < 3; ++bb) {
-              const double v = D * (a.lam * F[i][aa] * F[j][bb] + (aa == bb ? a.mu * fij : 0.0) + a.mu * F[i][bb] * F[j][aa]);
-              cmax[3 * aa + bb] = fmax(cmax[3 * aa + bb], fabs(v));
-            }
-        }
-    }
-  }
-  if (a.prec == IGAMT_F16X3) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) colmax[tid][k] = cmax[k];
   }
   __syncthreads();
-  if (a.prec == IGAMT_F16X3 && tid < 9) {
-    double m = 0.0;
-    for (int r = 0; r < 64; ++r) m = fmax(m, colmax[r][tid]);
-    double L3 = 1.0;  // product of the max row sums of |P_k|: |coef| <= L_x L_y L_z max|A|
+  // F16X3: |coef| <= L_x L_y L_z max|A_ij,ab| with L_k the max row sum of |P_k| (same in every lane)
+  double L3 = 1.0;
+  if (a.prec == IGAMT_F16X3) {
     for (int k = 0; k < 3; ++k) {
       double L = 0.0;
       for (int c = 0; c < a.q1[k]; ++c) {
@@ -135,45 +115,54 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
       }
       L3 *= L;
     }
-    scale[tid] = f16_scale_for(m * L3);
-    ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = (float)(1.0 / scale[tid]);
   }
-  __syncthreads();
 
-  for (int ij = 0; ij < 9; ++ij) {
-    const int i = ij / 3, j = ij % 3;
-    // A_ij at every sample
+  // One component (a, b) of A at a time, its nine blocks (i, j) side by side: the last pass then
+  // writes the coefficient row [ab][9 C + ij] contiguously (coalesced stores; each row's lines are
+  // written once).
+  for (int ab = 0; ab < 9; ++ab) {
+    const int aa = ab / 3, bb = ab % 3;
+    // A_ij,ab at every sample, buf0[s][ij]
     for (int e = tid; e < ns * 9; e += 64) {
-      const int s = e / 9, ab = e % 9, aa = ab / 3, bb = ab % 3;
+      const int s = e / 9, ij = e % 9, i = ij / 3, j = ij % 3;
       const double *Fs = FD + s * 10;
       const double fij = Fs[3 * i] * Fs[3 * j] + Fs[3 * i + 1] * Fs[3 * j + 1] + Fs[3 * i + 2] * Fs[3 * j + 2];
       buf0[e] = Fs[9] * (a.lam * Fs[3 * i + aa] * Fs[3 * j + bb] + (aa == bb ? a.mu * fij : 0.0) +
                          a.mu * Fs[3 * i + bb] * Fs[3 * j + aa]);
     }
     __syncthreads();
-    // x direction: buf1[(s3, s2, c1)][ab]
+    double sc = 1.0;
+    if (a.prec == IGAMT_F16X3) {  // the column's scale from max |A_ij,ab| over the tile (one wave)
+      double m = 0.0;
+      for (int e = tid; e < ns * 9; e += 64) m = fmax(m, fabs(buf0[e]));
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      sc = f16_scale_for(m * L3);
+      if (tid == 0) ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + ab] = (float)(1.0 / sc);
+    }
+    // x direction: buf1[(s3, s2, c1)][ij]
     for (int e = tid; e < q1x * nf * nf * 9; e += 64) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1x, s23 = r / q1x;
+      const int ij = e % 9, r = e / 9, c1 = r % q1x, s23 = r / q1x;
       double v = 0.0;
-      for (int s1 = 0; s1 < nf; ++s1) v += Pm[0][c1 * nf + s1] * buf0[(s23 * nf + s1) * 9 + ab];
+      for (int s1 = 0; s1 < nf; ++s1) v += Pm[0][c1 * nf + s1] * buf0[(s23 * nf + s1) * 9 + ij];
       buf1[e] = v;
     }
     __syncthreads();
-    // y direction: buf0[(s3, c2, c1)][ab]
+    // y direction: buf0[(s3, c2, c1)][ij]
     for (int e = tid; e < q1x * q1y * nf * 9; e += 64) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1x, c2 = (r / q1x) % q1y, s3 = r / (q1x * q1y);
+      const int ij = e % 9, r = e / 9, c1 = r % q1x, c2 = (r / q1x) % q1y, s3 = r / (q1x * q1y);
       double v = 0.0;
-      for (int s2 = 0; s2 < nf; ++s2) v += Pm[1][c2 * nf + s2] * buf1[(((s3 * nf + s2) * q1x) + c1) * 9 + ab];
+      for (int s2 = 0; s2 < nf; ++s2) v += Pm[1][c2 * nf + s2] * buf1[(((s3 * nf + s2) * q1x) + c1) * 9 + ij];
       buf0[e] = v;
     }
     __syncthreads();
-    // z direction and store: C = c1 + q1x (c2 + q1y c3)
+    // z direction and store: C = c1 + q1x (c2 + q1y c3), column k = 9 C + ij = e
     for (int e = tid; e < npi * 9; e += 64) {
-      const int C = e % npi, ab = e / npi;
+      const int ij = e % 9, C = e / 9;
       const int c1 = C % q1x, c2 = (C / q1x) % q1y, c3 = C / (q1x * q1y);
       double v = 0.0;
-      for (int s3 = 0; s3 < nf; ++s3) v += Pm[2][c3 * nf + s3] * buf0[(((s3 * q1y + c2) * q1x) + c1) * 9 + ab];
-      store_coef<double>(a, tbase + (int64_t)ab * a.Kp + 9 * C + ij, v, a.prec == IGAMT_F16X3 ? scale[ab] : 1.0);
+      for (int s3 = 0; s3 < nf; ++s3) v += Pm[2][c3 * nf + s3] * buf0[(((s3 * q1y + c2) * q1x) + c1) * 9 + ij];
+      store_coef<double>(a, tbase + (int64_t)ab * a.Kp + e, v, sc);
     }
     __syncthreads();
   }
