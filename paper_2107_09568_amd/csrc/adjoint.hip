@@ -85,6 +85,8 @@ struct FitAdjArgs {
   double *local_grad;   // [n_tiles][Lz][Ly][Lx][3]
   double *uKu_part;     // [n_tiles]
   int32_t *flag;
+  int Lm;               // max(Lc): row length of the 1-D factor tables
+  int64_t xt_off;       // doubles of dynamic LDS before the 1-D factor tables
 };
 
 constexpr int kFitAdjThreads = 256;   // threads per tile in the fit adjoint
@@ -143,12 +145,23 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
   }
   // this tile's share of u^T K u (fixed-order block reduction)
   {
+    // e = tid + 256 j in ascending j, four terms' loads issued before their products are added
+    const int n9 = 9 * a.Kp;
     double part = 0.0;
-    for (int64_t e = tid; e < 9 * (int64_t)a.Kp; e += kFitAdjThreads) {
-      const int64_t ab = e / a.Kp, k = e - ab * a.Kp;
-      const int64_t wi = (t * a.Kp + k) * 9 + ab;   // W is stored [t][k][ab]
-      const double w = a.w_f64 ? ((const double *)a.W)[wi] : (double)((const float *)a.W)[wi];
-      part += a.coef[tbase + e] * w;
+    for (int e0 = 0; e0 < n9; e0 += 4 * kFitAdjThreads) {
+      double cv[4], wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kFitAdjThreads + tid;
+        const bool in = e < n9;
+        const int ab = in ? e / a.Kp : 0, k = in ? e - ab * a.Kp : 0;
+        const int64_t wi = (t * a.Kp + k) * 9 + ab;   // W is stored [t][k][ab]
+        cv[u] = in ? a.coef[tbase + e] : 0.0;
+        wv[u] = in ? (a.w_f64 ? ((const double *)a.W)[wi] : (double)((const float *)a.W)[wi]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * kFitAdjThreads + tid < n9) part += cv[u] * wv[u];
     }
     red[tid] = part;
   }
@@ -256,28 +269,39 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
     __syncthreads();
   }
   // local control-point gradients: mbar[i][c] = sum_s sum_n JbarH[s][c][n] d_n R_i(s)
-  // (R_i = N_i for a B-spline map; w_i (d_n N_i - N_i d_n W / W) / W for a NURBS map)
-  const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2];
+  // (R_i = N_i for a B-spline map; w_i (d_n N_i - N_i d_n W / W) / W for a NURBS map).  The basis
+  // is a tensor product, so its factors are tabulated per direction: XV[k][s][l] = N_r(x_s) and
+  // XD[k][s][l] = N_r'(x_s) with r = lo_k + l - (span_s - p), zero where l is outside the support
+  // of the sample (such samples add an exact zero).
+  const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2], Lm = a.Lm;
   const int lo[3] = {a.ctrl_lo[0][tt[0]], a.ctrl_lo[1][tt[1]], a.ctrl_lo[2][tt[2]]};
+  double *XV = smem + a.xt_off, *XD = XV + 3 * nf * Lm;   // [3][nf][Lm] each
+  for (int e = tid; e < 3 * nf * Lm; e += kFitAdjThreads) {
+    const int k = e / (nf * Lm), rem = e - k * nf * Lm, sk = rem / Lm, l = rem - sk * Lm;
+    const int r = lo[k] + l - (SP[k][sk] - PM);
+    const bool on = r >= 0 && r <= PM;
+    const int rc = on ? r : 0;
+    XV[e] = on ? NB[k][sk][rc] : 0.0;
+    XD[e] = on ? DB[k][sk][rc] : 0.0;
+  }
+  __syncthreads();
   double *lg = a.local_grad + t * (int64_t)L0 * L1 * L2 * 3;
   for (int e = tid; e < L0 * L1 * L2 * 3; e += kFitAdjThreads) {
     const int c = e % 3, li = e / 3;
     const int l[3] = {li % L0, (li / L0) % L1, li / (L0 * L1)};
     double g = 0.0;
-    for (int s = 0; s < ns; ++s) {
-      const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-      double v[3], d[3];
-      bool on = true;
-      for (int k = 0; k < 3; ++k) {
-        const int r = lo[k] + l[k] - (SP[k][si[k]] - PM);
-        if (r < 0 || r > PM) { on = false; break; }
-        v[k] = NB[k][si[k]][r];
-        d[k] = DB[k][si[k]][r];
+    for (int s3 = 0; s3 < nf; ++s3) {
+      const double v2 = XV[(2 * nf + s3) * Lm + l[2]], d2 = XD[(2 * nf + s3) * Lm + l[2]];
+      for (int s2 = 0; s2 < nf; ++s2) {
+        const double v1 = XV[(nf + s2) * Lm + l[1]], d1 = XD[(nf + s2) * Lm + l[1]];
+        for (int s1 = 0; s1 < nf; ++s1) {
+          const double v0 = XV[s1 * Lm + l[0]], d0 = XD[s1 * Lm + l[0]];
+          const int s = (s3 * nf + s2) * nf + s1;
+          const double *jb = FB + s * 10 + 3 * c;
+          const double tb = jb[0] * d0 * v1 * v2 + jb[1] * v0 * d1 * v2 + jb[2] * v0 * v1 * d2;
+          g += a.wts ? tb * WQ[s * 4] - v0 * v1 * v2 * WQ[s * 4 + 1 + c] : tb;
+        }
       }
-      if (!on) continue;
-      const double *jb = FB + s * 10 + 3 * c;
-      const double tb = jb[0] * d[0] * v[1] * v[2] + jb[1] * v[0] * d[1] * v[2] + jb[2] * v[0] * v[1] * d[2];
-      g += a.wts ? tb * WQ[s * 4] - v[0] * v[1] * v[2] * WQ[s * 4 + 1 + c] : tb;
     }
     lg[e] = a.wts ? g * a.wts[(lo[0] + l[0]) + (int64_t)a.nM[0] * ((lo[1] + l[1]) + (int64_t)a.nM[1] * (lo[2] + l[2]))]
                   : g;
@@ -458,7 +482,10 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   f.uKu_part = part;
   f.flag = P->dev.flag;
   const int ns = P->n_fit * P->n_fit * P->n_fit;
-  const size_t shm = (size_t)(10 + 10 + 9 + 9) * std::max(ns, P->npi) * sizeof(double);
+  f.Lm = std::max(P->Lc[0], std::max(P->Lc[1], P->Lc[2]));
+  f.xt_off = (int64_t)(10 + 10 + 9 + 9) * std::max(ns, P->npi);
+  const size_t shm = (size_t)(f.xt_off + 6 * (int64_t)P->n_fit * f.Lm) * sizeof(double);
+  if (shm > 150 * 1024) { set_error("tile samples or macro control points per tile too many for the fit adjoint"); return IGAMT_EUNSUPPORTED; }
   const dim3 fgrid((unsigned)P->n_tiles), fblock(kFitAdjThreads);
   switch (P->pM[0]) {
 #define FA_CASE(p)                                                                                      \
