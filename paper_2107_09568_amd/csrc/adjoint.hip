@@ -91,15 +91,17 @@ struct FitAdjArgs {
 
 constexpr int kFitAdjThreads = 256;   // threads per tile in the fit adjoint
 
-template <int PM>
+// GJ (1 or 3): (i, j) blocks carried through the passes together (the same i, consecutive j)
+template <int PM, int GJ>
 __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs a) {
+  constexpr int NC = 9 * GJ;         // components per pass: (j, a, b)
   extern __shared__ double smem[];
   const int nf = a.nf, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
   const int ns = nf * nf * nf, npi = q1x * q1y * q1z;
   double *FD = smem;                 // [ns][10]  F, D
   double *FB = FD + ns * 10;         // [ns][10]  Fbar (before the factor D), Dbar
-  double *buf0 = FB + ns * 10;       // [max(ns, npi)][9]
-  double *buf1 = buf0 + ns * 9;      // [ns][9]
+  double *buf0 = FB + ns * 10;       // [max(ns, npi)][NC]
+  double *buf1 = buf0 + ns * NC;     // [ns][NC]
   __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
   __shared__ double NB[3][kMaxFit][kMaxDegree + 1], DB[3][kMaxFit][kMaxDegree + 1];
   __shared__ int SP[3][kMaxFit];
@@ -172,44 +174,46 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
   }
   if (tid == 0) a.uKu_part[t] = red[0];
 
-  for (int ij = 0; ij < 9; ++ij) {
-    const int i = ij / 3, j = ij % 3;
-    // W block of (i, j): buf0[C][ab]
-    for (int e = tid; e < npi * 9; e += kFitAdjThreads) {
-      const int C = e / 9, ab = e % 9;
-      const int64_t idx = (t * a.Kp + 9 * C + ij) * 9 + ab;   // W is stored [t][k][ab]
+  for (int ij0 = 0; ij0 < 9; ij0 += GJ) {
+    // W blocks of (ij0 .. ij0 + GJ - 1): buf0[C][jj 9 + ab], contiguous in W ([t][9 C + ij][ab])
+    for (int e = tid; e < npi * NC; e += kFitAdjThreads) {
+      const int C = e / NC, q = e - C * NC;
+      const int64_t idx = (t * a.Kp + 9 * C + ij0) * 9 + q;
       buf0[e] = a.w_f64 ? ((const double *)a.W)[idx] : (double)((const float *)a.W)[idx];
     }
     __syncthreads();
-    // transpose of the z pass: buf1[(s3, c2, c1)][ab] = sum_c3 P[c3][s3] W[(c3, c2, c1)]
-    for (int e = tid; e < nf * q1y * q1x * 9; e += kFitAdjThreads) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1x, c2 = (r / q1x) % q1y, s3 = r / (q1x * q1y);
+    // transpose of the z pass: buf1[(s3, c2, c1)][q] = sum_c3 P[c3][s3] W[(c3, c2, c1)][q]
+    for (int e = tid; e < nf * q1y * q1x * NC; e += kFitAdjThreads) {
+      const int q = e % NC, r = e / NC, c1 = r % q1x, c2 = (r / q1x) % q1y, s3 = r / (q1x * q1y);
       double v = 0.0;
-      for (int c3 = 0; c3 < q1z; ++c3) v += Pm[2][c3 * nf + s3] * buf0[((c3 * q1y + c2) * q1x + c1) * 9 + ab];
+      for (int c3 = 0; c3 < q1z; ++c3) v += Pm[2][c3 * nf + s3] * buf0[((c3 * q1y + c2) * q1x + c1) * NC + q];
       buf1[e] = v;
     }
     __syncthreads();
-    // transpose of the y pass: buf0[(s3, s2, c1)][ab]
-    for (int e = tid; e < nf * nf * q1x * 9; e += kFitAdjThreads) {
-      const int ab = e % 9, r = e / 9, c1 = r % q1x, s2 = (r / q1x) % nf, s3 = r / (q1x * nf);
+    // transpose of the y pass: buf0[(s3, s2, c1)][q]
+    for (int e = tid; e < nf * nf * q1x * NC; e += kFitAdjThreads) {
+      const int q = e % NC, r = e / NC, c1 = r % q1x, s2 = (r / q1x) % nf, s3 = r / (q1x * nf);
       double v = 0.0;
-      for (int c2 = 0; c2 < q1y; ++c2) v += Pm[1][c2 * nf + s2] * buf1[((s3 * q1y + c2) * q1x + c1) * 9 + ab];
+      for (int c2 = 0; c2 < q1y; ++c2) v += Pm[1][c2 * nf + s2] * buf1[((s3 * q1y + c2) * q1x + c1) * NC + q];
       buf0[e] = v;
     }
     __syncthreads();
-    // transpose of the x pass: buf1[(s3, s2, s1)][ab] = Abar_ij at sample s
-    for (int e = tid; e < ns * 9; e += kFitAdjThreads) {
-      const int ab = e % 9, s = e / 9, s1 = s % nf, s23 = s / nf;
+    // transpose of the x pass: buf1[(s3, s2, s1)][q] = Abar at sample s
+    for (int e = tid; e < ns * NC; e += kFitAdjThreads) {
+      const int q = e % NC, s = e / NC, s1 = s % nf, s23 = s / nf;
       double v = 0.0;
-      for (int c1 = 0; c1 < q1x; ++c1) v += Pm[0][c1 * nf + s1] * buf0[(s23 * q1x + c1) * 9 + ab];
+      for (int c1 = 0; c1 < q1x; ++c1) v += Pm[0][c1 * nf + s1] * buf0[(s23 * q1x + c1) * NC + q];
       buf1[e] = v;
     }
     __syncthreads();
-    // accumulate the adjoint of A_ij = D G_ij(F) into (Fbar / D, Dbar), one sample per thread
-    for (int s = tid; s < ns; s += kFitAdjThreads) {
+    // accumulate the adjoint of A_ij = D G_ij(F) into (Fbar / D, Dbar), one sample per thread,
+    // (i, j) in ascending order
+    for (int s = tid; s < ns; s += kFitAdjThreads)
+    for (int jj = 0; jj < GJ; ++jj) {
+      const int i = (ij0 + jj) / 3, j = (ij0 + jj) % 3;
       const double *F = FD + s * 10;
       const double D = F[9];
-      const double *Ab = buf1 + s * 9;     // Abar_ij[a][b]
+      const double *Ab = buf1 + s * NC + 9 * jj;     // Abar_ij[a][b]
       double *fb = FB + s * 10;
       const double fij = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
       double T = 0.0, dbar = 0.0;
@@ -483,16 +487,23 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   f.flag = P->dev.flag;
   const int ns = P->n_fit * P->n_fit * P->n_fit;
   f.Lm = std::max(P->Lc[0], std::max(P->Lc[1], P->Lc[2]));
-  f.xt_off = (int64_t)(10 + 10 + 9 + 9) * std::max(ns, P->npi);
-  const size_t shm = (size_t)(f.xt_off + 6 * (int64_t)P->n_fit * f.Lm) * sizeof(double);
+  // three (i, j) blocks per pass where the buffers leave room for three workgroups per CU
+  const int64_t nsp = std::max(ns, P->npi), xt = 6 * (int64_t)P->n_fit * f.Lm;
+  const int gj = (20 + 2 * 27) * nsp + xt <= 6 * 1024 ? 3 : 1;
+  f.xt_off = (20 + 2 * 9 * gj) * nsp;
+  const size_t shm = (size_t)(f.xt_off + xt) * sizeof(double);
   if (shm > 150 * 1024) { set_error("tile samples or macro control points per tile too many for the fit adjoint"); return IGAMT_EUNSUPPORTED; }
   const dim3 fgrid((unsigned)P->n_tiles), fblock(kFitAdjThreads);
   switch (P->pM[0]) {
+#define FA_LAUNCH(p, g)                                                                                 \
+  do {                                                                                                  \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_adjoint_kernel<p, g>,              \
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
+    hipLaunchKernelGGL((fit_adjoint_kernel<p, g>), fgrid, fblock, shm, s, f);                           \
+  } while (0)
 #define FA_CASE(p)                                                                                      \
   case p:                                                                                               \
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_adjoint_kernel<p>,                 \
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
-    hipLaunchKernelGGL(fit_adjoint_kernel<p>, fgrid, fblock, shm, s, f);                                \
+    if (gj == 3) FA_LAUNCH(p, 3); else FA_LAUNCH(p, 1);                                                 \
     break;
     FA_CASE(1)
     FA_CASE(2)
@@ -501,6 +512,7 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
     FA_CASE(5)
     FA_CASE(6)
 #undef FA_CASE
+#undef FA_LAUNCH
     default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();
