@@ -27,6 +27,7 @@ struct FitArgs {
   const double *fP3;    // per-direction 1-D operators [(q1[0]) nf][(q1[1]) nf][(q1[2]) nf]
   int q1[3], nf, Kp, prec;
   double lam, mu;
+  double L3;            // product over directions of the largest row sum of |P_k| (F16X3 scale bound)
   void *out;
   int64_t plane;        // n_tiles_pad * 9 * Kp elements per stored plane
   int64_t t0;           // first tile of the launch
@@ -103,19 +104,8 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
     FD[s * 10 + 9] = D;
   }
   __syncthreads();
-  // F16X3: |coef| <= L_x L_y L_z max|A_ij,ab| with L_k the max row sum of |P_k| (same in every lane)
-  double L3 = 1.0;
-  if (a.prec == IGAMT_F16X3) {
-    for (int k = 0; k < 3; ++k) {
-      double L = 0.0;
-      for (int c = 0; c < a.q1[k]; ++c) {
-        double rs = 0.0;
-        for (int s = 0; s < nf; ++s) rs += fabs(Pm[k][c * nf + s]);
-        L = fmax(L, rs);
-      }
-      L3 *= L;
-    }
-  }
+  // F16X3: |coef| <= L_x L_y L_z max|A_ij,ab| with L_k the max row sum of |P_k| (a.L3)
+  const double L3 = a.L3;
 
   // One component (a, b) of A at a time, its nine blocks (i, j) side by side: the last pass then
   // writes the coefficient row [ab][9 C + ij] contiguously (coalesced stores; each row's lines are
@@ -216,6 +206,16 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.prec = prec;
   a.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   a.mu = E / (2.0 * (1.0 + nu));
+  a.L3 = 1.0;
+  for (int k = 0, off = 0; k < 3; off += a.q1[k] * a.nf, ++k) {
+    double L = 0.0;
+    for (int c = 0; c < a.q1[k]; ++c) {
+      double rs = 0.0;
+      for (int s = 0; s < a.nf; ++s) rs += std::fabs(P->fit_P3[off + c * a.nf + s]);
+      L = std::fmax(L, rs);
+    }
+    a.L3 *= L;
+  }
   a.out = d_coef;
   a.plane = P->n_tiles_pad * 9 * (int64_t)P->Kp;
   a.flag = P->dev.flag;
