@@ -185,6 +185,7 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
   double A[3] = {0.0, 0.0, 0.0}, W = 0.0, dW[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) J[c][0] = J[c][1] = J[c][2] = 0.0;
+#pragma unroll 1
   for (int rz = 0; rz <= P; ++rz) {
     const int iz = span[2] - P + rz;
     for (int ry = 0; ry <= P; ++ry) {
