@@ -1,6 +1,8 @@
 """GPU parity of the shape-sensitivity path (Section 4.1.2): d(u^T K u)/d(macro control points)
 against the oracle's independent chain (complex-step dA/dJ) and against central finite
 differences of the GPU's own u^T K u (h = 1e-6, FP64)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -47,6 +49,24 @@ def test_grad_small_vs_oracle(env):
     e32 = np.abs(grad32.cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
     _say(f"small cfg4 grad f32 vs oracle: {e32:.2e}")
     assert e32 < 1e-4
+
+
+def test_grad_q4_vs_oracle(env):
+    """q = 4 with 5 fit nodes per direction (125 per tile): the fit adjoint's passes carry one (i, j)
+    block at a time here (three blocks at q <= 3), so both pass layouts meet the oracle."""
+    torch, P = env
+    w = dataclasses.replace(W.make("cfg4", n_boxes=2), q=4, n_fit=5)
+    plan, u, ud = _setup(P, torch, w)
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    g_ref = adjoint.grad_uKu(w, T, pairs, u)
+    v_ref = adjoint.uKu(w, T, pairs, u)
+    val, grad = plan.uKu_grad(w.E, w.nu, ud, "f64")
+    plan.check()
+    err = np.abs(grad.cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    _say(f"q=4 cfg4 (2^3 boxes) grad f64 vs oracle: {err:.2e}; uKu {val.item():.6e} vs {v_ref:.6e}")
+    assert err < 1e-10
+    assert val.item() == pytest.approx(v_ref, rel=1e-12)
 
 
 def test_grad_cfg4_vs_fd_and_oracle(env):
