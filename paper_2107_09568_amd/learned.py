@@ -4,7 +4,7 @@ The paper builds one lookup table per reference tile (eq. (52)) in an offline
 step.  For a family of tiles described by a few design parameters this module
 replaces the per-design build by a POD basis of the family's tables and a small
 MLP from the parameters to the POD coefficients; the exact table builder stays
-the fallback and the judge: a seeded subset of table rows is built exactly and
+the fallback and the check: a seeded subset of table rows is built exactly and
 compared with the learned table, and the exact table replaces it when the
 estimated relative error exceeds the tolerance.  The per-design path queues
 everything on the stream, the fallback decision included.
