@@ -7,8 +7,12 @@ into the CSR structure (plan, CSR structure and lookup table are built once,
 outside the timed region, as in the paper's timing convention).  Inputs are
 resident in HBM before timing starts.
 
-Prints ONE JSON line (rank 0).  See the design doc for the roofline figures and the
-CPU-baseline protocol.
+Prints ONE JSON line (rank 0): the tile-block rate of the FP64 step, the
+contraction kernel's roofline figures (algorithmic FLOPs per launch over its
+average launch time from HIP events on its stream, against the FP64 MFMA peak,
+with the HBM bytes of the committed byte-counter summary when its source hash
+matches), the split-precision variants, the next rows' kernels, and the oracle
+timed on a bounded sample of tiles on the host cores.
 """
 import argparse
 import hashlib
