@@ -246,6 +246,8 @@ __global__ __launch_bounds__(256) void load_gather_kernel(LoadGatherArgs a) {
             if (tt[d] != (side ? a.tiles[d] - 1 : 0)) continue;   // the tile does not touch face f
           }
           const double *cs = co + (int64_t)slot * 3 * a.npi;
+          // unrolled so that the loads run ahead of the (sequential, fixed-order) sum
+#pragma unroll 9
           for (int C = 0; C < a.npi; ++C) sum += cs[C] * tb[C * kLoadSlots + slot];
         }
       }
