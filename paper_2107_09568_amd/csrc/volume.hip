@@ -83,6 +83,7 @@ struct VolumeTileArgs {
   double *tile_vol;         // [n_tiles]
   double *local_grad;       // [n_tiles][Lz][Ly][Lx][3] or null
   int32_t *flag;
+  int Lm;                   // max(Lc): row length of the 1-D factor tables
 };
 
 template <int PM>
@@ -153,28 +154,39 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
   }
   if (tid == 0) a.tile_vol[t] = red[0];
   if (!grad) return;
-  // local control-point gradients: g[i][c] = sum_s sum_n GS[s][c][n] d_n N_i(s)
-  const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2];
+  // local control-point gradients: g[i][c] = sum_s sum_n GS[s][c][n] d_n N_i(s).  The basis is a
+  // tensor product, so its factors are tabulated per direction: XV[k][s][l] = N_r(x_s) and
+  // XD[k][s][l] = N_r'(x_s) with r = lo_k + l - (span_s - p), zero where l is outside the support
+  // of the sample (such samples add an exact zero).
+  const int L0 = a.Lc[0], L1 = a.Lc[1], L2 = a.Lc[2], Lm = a.Lm;
   const int lo[3] = {a.ctrl_lo[0][tt[0]], a.ctrl_lo[1][tt[1]], a.ctrl_lo[2][tt[2]]};
+  double *XV = GS + ns * 13, *XD = XV + 3 * nf * Lm;   // [3][nf][Lm] each, after GS and WQ
+  for (int e = tid; e < 3 * nf * Lm; e += 64) {
+    const int k = e / (nf * Lm), rem = e - k * nf * Lm, sk = rem / Lm, l = rem - sk * Lm;
+    const int r = lo[k] + l - (SP[k][sk] - PM);
+    const bool on = r >= 0 && r <= PM;
+    const int rc = on ? r : 0;
+    XV[e] = on ? NB[k][sk][rc] : 0.0;
+    XD[e] = on ? DB[k][sk][rc] : 0.0;
+  }
+  __syncthreads();
   double *lg = a.local_grad + t * (int64_t)L0 * L1 * L2 * 3;
   for (int e = tid; e < L0 * L1 * L2 * 3; e += 64) {
     const int c = e % 3, li = e / 3;
     const int l[3] = {li % L0, (li / L0) % L1, li / (L0 * L1)};
     double gsum = 0.0;
-    for (int s = 0; s < ns; ++s) {
-      const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-      double v[3], d[3];
-      bool on = true;
-      for (int k = 0; k < 3; ++k) {
-        const int r = lo[k] + l[k] - (SP[k][si[k]] - PM);
-        if (r < 0 || r > PM) { on = false; break; }
-        v[k] = NB[k][si[k]][r];
-        d[k] = DB[k][si[k]][r];
+    for (int s3 = 0; s3 < nf; ++s3) {
+      const double v2 = XV[(2 * nf + s3) * Lm + l[2]], d2 = XD[(2 * nf + s3) * Lm + l[2]];
+      for (int s2 = 0; s2 < nf; ++s2) {
+        const double v1 = XV[(nf + s2) * Lm + l[1]], d1 = XD[(nf + s2) * Lm + l[1]];
+        for (int s1 = 0; s1 < nf; ++s1) {
+          const double v0 = XV[s1 * Lm + l[0]], d0 = XD[s1 * Lm + l[0]];
+          const int s = (s3 * nf + s2) * nf + s1;
+          const double *gc = GS + s * 9 + 3 * c;
+          const double tb = gc[0] * d0 * v1 * v2 + gc[1] * v0 * d1 * v2 + gc[2] * v0 * v1 * d2;
+          gsum += a.wts ? tb * WQ[s * 4] - v0 * v1 * v2 * WQ[s * 4 + 1 + c] : tb;
+        }
       }
-      if (!on) continue;
-      const double *gc = GS + s * 9 + 3 * c;
-      const double tb = gc[0] * d[0] * v[1] * v[2] + gc[1] * v[0] * d[1] * v[2] + gc[2] * v[0] * v[1] * d[2];
-      gsum += a.wts ? tb * WQ[s * 4] - v[0] * v[1] * v[2] * WQ[s * 4 + 1 + c] : tb;
     }
     lg[e] = a.wts ? gsum * a.wts[(lo[0] + l[0]) + (int64_t)a.nM[0] * ((lo[1] + l[1]) + (int64_t)a.nM[1] * (lo[2] + l[2]))]
                   : gsum;
@@ -306,7 +318,9 @@ extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, doub
   a.local_grad = d_grad ? lg : nullptr;
   a.flag = P->dev.flag;
   const int ns = P->n_fit * P->n_fit * P->n_fit;
-  const size_t shm = d_grad ? (size_t)ns * (9 + 4) * sizeof(double) : 0;
+  a.Lm = std::max(P->Lc[0], std::max(P->Lc[1], P->Lc[2]));
+  const size_t shm = d_grad ? (size_t)(ns * (9 + 4) + 6 * (int64_t)P->n_fit * a.Lm) * sizeof(double) : 0;
+  if (shm > 60 * 1024) { set_error("tile samples or macro control points per tile too many for the volume gradient"); return IGAMT_EUNSUPPORTED; }
   const dim3 grid((unsigned)P->n_tiles), block(64);
   switch (P->pM[0]) {
     case 1: hipLaunchKernelGGL(volume_tile_kernel<1>, grid, block, shm, s, a); break;
