@@ -161,10 +161,10 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
     const int comp = e / npi, C = e - comp * npi;
     const int c1 = C % q1[0], c2 = (C / q1[0]) % q1[1], c3 = C / (q1[0] * q1[1]);
     double v = 0.0;
-    for (int s = 0; s < ns; ++s) {
-      const int s1 = s % nf, s2 = (s / nf) % nf, s3 = s / (nf * nf);
-      v += Pk[0][c1 * nf + s1] * Pk[1][c2 * nf + s2] * Pk[2][c3 * nf + s3] * vals[s];
-    }
+    for (int s3 = 0, s = 0; s3 < nf; ++s3)   // s = s1 + nf (s2 + nf s3), ascending
+      for (int s2 = 0; s2 < nf; ++s2)
+        for (int s1 = 0; s1 < nf; ++s1, ++s)
+          v += Pk[0][c1 * nf + s1] * Pk[1][c2 * nf + s2] * Pk[2][c3 * nf + s3] * vals[s];
     co[e] = a.body[comp] * v;
   }
   // faces
@@ -197,10 +197,8 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
       const int c[3] = {C % q1[0], (C / q1[0]) % q1[1], C / (q1[0] * q1[1])};
       double r = 0.0;
       if (touched && c[d] == (side ? a.qd[d] : 0)) {
-        for (int s = 0; s < nf * nf; ++s) {
-          const int su = s % nf, sv = s / nf;
-          r += Pk[u][c[u] * nf + su] * Pk[v][c[v] * nf + sv] * vals[s];
-        }
+        for (int sv = 0, s = 0; sv < nf; ++sv)   // s = su + nf sv, ascending
+          for (int su = 0; su < nf; ++su, ++s) r += Pk[u][c[u] * nf + su] * Pk[v][c[v] * nf + sv] * vals[s];
         r *= a.traction[f][comp];
       }
       cf[e] = r;
