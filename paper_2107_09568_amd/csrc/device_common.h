@@ -188,6 +188,7 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
 #pragma unroll 1
   for (int rz = 0; rz <= P; ++rz) {
     const int iz = span[2] - P + rz;
+#pragma unroll 1
     for (int ry = 0; ry <= P; ++ry) {
       const int iy = span[1] - P + ry;
       const double wyz = N[1][ry] * N[2][rz];
