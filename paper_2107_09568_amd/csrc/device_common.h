@@ -173,7 +173,9 @@ __device__ inline double f16_scale_for(double bound) {
 // parameter x (degree P in every direction); also returns the span and the 1-D basis values and
 // derivatives used.  w: NULL for a B-spline map, else the NURBS weights ([n2][n1][n0]); the map is
 // then A / W with A = sum w_i N_i P_i, W = sum w_i N_i, and dM/dx_k = (dA/dx_k - M dW/dx_k) / W.
-template <int P>
+// ROLL_X keeps the innermost (x) control-point loop rolled too: fewer registers (more waves per SIMD)
+// for kernels whose occupancy the Jacobian limits, the same sums in the same order.
+template <int P, bool ROLL_X = false>
 __device__ inline void spline_jacobian(const double *const *knots, const int *n, const double *__restrict__ ctrl,
                                        const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
                                        int (&span)[3], double (&N)[3][P + 1], double (&dN)[3][P + 1]) {
@@ -194,8 +196,7 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
       const double wyz = N[1][ry] * N[2][rz];
       const double dy = dN[1][ry] * N[2][rz];
       const double dz = N[1][ry] * dN[2][rz];
-#pragma unroll
-      for (int rx = 0; rx <= P; ++rx) {
+      auto point = [&](int rx) {
         const int ix = span[0] - P + rx;
         const int64_t id = ix + (int64_t)n[0] * (iy + (int64_t)n[1] * iz);
         const double *c = ctrl + 3 * id;
@@ -213,6 +214,13 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
         dW[0] += g0;
         dW[1] += g1;
         dW[2] += g2;
+      };
+      if constexpr (ROLL_X) {
+#pragma unroll 1
+        for (int rx = 0; rx <= P; ++rx) point(rx);
+      } else {
+#pragma unroll
+        for (int rx = 0; rx <= P; ++rx) point(rx);
       }
     }
   }

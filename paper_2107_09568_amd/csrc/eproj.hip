@@ -50,7 +50,7 @@ __device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const
   const double xh[3] = {ax[0] + hx[0] * x[0], ax[1] + hx[1] * x[1], ax[2] + hx[2] * x[2]};
   double J[3][3], N[3][PM + 1], dN[3][PM + 1];
   int span[3];
-  spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+  spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll

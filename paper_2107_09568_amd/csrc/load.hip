@@ -147,7 +147,7 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PM + 1], dN[3][PM + 1];
     int span[3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
         xh[v] = ax[v] + hx[v] * a.fx[sv];
         double J[3][3], N[3][PM + 1], dN[3][PM + 1];
         int span[3];
-        spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+        spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
         const double gu[3] = {J[0][u] * hx[u], J[1][u] * hx[u], J[2][u] * hx[u]};
         const double gv[3] = {J[0][v] * hx[v], J[1][v] * hx[v], J[2][v] * hx[v]};
         const double n0 = gu[1] * gv[2] - gu[2] * gv[1], n1 = gu[2] * gv[0] - gu[0] * gv[2],
