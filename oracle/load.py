@@ -243,3 +243,96 @@ def standard_load(w, body, traction, n_g: int = None) -> np.ndarray:
         for c in range(3):
             np.add.at(f, 3 * G + c, ft[:, c])
     return f
+
+
+def _abs_det(J):
+    """|det J| of (S, 3, 3) Jacobians, continued analytically for the complex step: the sign of the
+    real part's determinant times the (complex) determinant."""
+    d = np.linalg.det(J)
+    return np.sign(np.linalg.det(J.real)) * d
+
+
+def _face_area(J, u, v):
+    """|J e_u x J e_v| of (S, 3, 3) Jacobians as sqrt(n . n) (analytic in J for the complex step)."""
+    n = np.cross(J[:, :, u], J[:, :, v])
+    return np.sqrt(np.sum(n * n, axis=1))
+
+
+def _complex_step_grad(fun, J, h=1e-30):
+    """d fun(J)/dJ_mn for a scalar-per-sample function of (S, 3, 3) Jacobians, shape (S, 3, 3)."""
+    out = np.empty(J.shape)
+    for m in range(3):
+        for n in range(3):
+            Jc = J.astype(np.complex128)
+            Jc[:, m, n] += 1j * h
+            out[:, m, n] = fun(Jc).imag / h
+    return out
+
+
+def uf(w, table, body, traction, u) -> float:
+    """u . f^pi as the sum of the tile terms u^(t) . f^(t) (eq. (53) glued)."""
+    P = projection_operator(w.q, w.n_fit)
+    total = 0.0
+    for t in range(w.n_tiles):
+        ut = u[3 * tile_global_indices(w, t)[:, None] + np.arange(3)[None, :]]
+        total += float(np.sum(ut * tile_load(table, load_coefficients(w, t, body, traction, P))))
+    return total
+
+
+def grad_uf(w, table, body, traction, u) -> np.ndarray:
+    """d(u . f^pi)/dm for a fixed vector u, shape like w.macro.ctrl (NURBS: weights fixed).
+
+    The external work of eq. (69) differentiated through its projections (eq. (40)-(41), (44)-(45)):
+    per tile, Y[slot, a, C] = sum_A u_(A,a) F[A, C, slot] is the adjoint of the lookup (eq. (53));
+    the projection's transpose gives the adjoint of the sampled fields, d(u.f)/d|det J_s| and
+    d(u.f)/d area_s; the derivatives of |det J| and of the face area element by J come from a
+    complex step of their definitions (no hand-derived formula); J = J_M(a + h xi) diag(h) gives
+    dJ/dm_k,c = e_c (grad N_k * h)^T, summed over the sample grids as for the stiffness gradient."""
+    from .geometry import control_point_gradient
+    body = np.asarray(body, dtype=np.float64)
+    traction = np.asarray(traction, dtype=np.float64).reshape(N_FACES, 3)
+    qd = degrees(w.q)
+    P = projection_operator(w.q, w.n_fit)
+    x, _ = gauss01(w.n_fit)
+    nf = len(x)
+    wts = getattr(w.macro, "weights", None)
+    g = np.zeros_like(w.macro.ctrl)
+    for t in range(w.n_tiles):
+        a, h, _ = _box(w, t)
+        ut = u[3 * tile_global_indices(w, t)[:, None] + np.arange(3)[None, :]]   # (n_T, 3)
+        Y = np.einsum("Aa,ACs->saC", ut, table)                                     # (7, 3, n_pi)
+        # body: coef[0][a][C] = b_a sum_s P[C, s] |det J_s|
+        gbar = P.T @ (body @ Y[0])                                                  # (S,)
+        _, JM = eval_volume_grid(w.macro.degree, w.macro.knots, w.macro.ctrl, a[0] + h[0] * x, a[1] + h[1] * x,
+                                 a[2] + h[2] * x, weights=wts)
+        J = JM.reshape(-1, 3, 3) * h[None, None, :]
+        Jbar = gbar[:, None, None] * _complex_step_grad(_abs_det, J) * h[None, None, :]
+        g += control_point_gradient(w.macro.knots, w.macro.degree, wts, a[0] + h[0] * x, a[1] + h[1] * x,
+                                    a[2] + h[2] * x, Jbar.reshape(nf, nf, nf, 3, 3))
+        for f in touched_faces(w, t):
+            d, side, uu, vv = face_axes(f)
+            P2f = face_projection_operator((qd[uu], qd[vv]), nf)                    # [(c_u, c_v), (s_v, s_u)]
+            ybar = np.zeros(P2f.shape[0])
+            for cv in range(qd[vv] + 1):
+                for cu in range(qd[uu] + 1):
+                    c = [0, 0, 0]
+                    c[d] = qd[d] if side else 0
+                    c[uu], c[vv] = cu, cv
+                    C = c[0] + (qd[0] + 1) * (c[1] + (qd[1] + 1) * c[2])
+                    ybar[cu + (qd[uu] + 1) * cv] = traction[f] @ Y[1 + f, :, C]
+            abar = P2f.T @ ybar                                                     # (nf^2,) s = s_u + nf s_v
+            pts = np.zeros((nf * nf, 3))
+            PV, PU = np.meshgrid(x, x, indexing="ij")
+            pts[:, d] = side
+            pts[:, uu] = PU.ravel()
+            pts[:, vv] = PV.ravel()
+            _, Jp = eval_volume_points(w.macro.degree, w.macro.knots, w.macro.ctrl, a + h * pts, weights=wts)
+            Jp = Jp * h[None, None, :]
+            Jbar = abar[:, None, None] * _complex_step_grad(lambda Jc: _face_area(Jc, uu, vv), Jp) * h[None, None, :]
+            # the face grid as (z, y, x) with one point along d; v is the slower in-face axis
+            shape = [nf, nf, nf]
+            shape[2 - d] = 1
+            axes = [a[k] + h[k] * (x if k != d else np.array([float(side)])) for k in range(3)]
+            g += control_point_gradient(w.macro.knots, w.macro.degree, wts, axes[0], axes[1], axes[2],
+                                        Jbar.reshape(shape[0], shape[1], shape[2], 3, 3))
+    return g
