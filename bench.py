@@ -347,6 +347,43 @@ def bench_adjoint(torch, W, P, steps):
         out[prec] = {"ms_per_gradient": ms, "tile_gradients_per_s": plan.n_tiles / (ms * 1e-3),
                      "contraction_flops": 2.0 * plan.n_pairs * plan.n_cols * 9 * plan.n_tiles}
         del ws
+    # the compliance c = f^T K^-1 f as stated: clamp on xi_1 = 0, traction (0, 0, -1) on xi_1 = 1,
+    # f = f^pi (moves with the geometry), FP64 blocks, CG to 1e-10, dc/dm = 2 u.df/dm - u^T dK/dm u
+    import time
+    traction = np.zeros((6, 3))
+    traction[1] = [0.0, 0.0, -1.0]
+    body = np.zeros(3)
+    plan.load_table_build()
+    fixed = plan.face_mask([0])
+    gws = plan.grad_workspace("f32")
+
+    def chain():
+        f = plan.load_assemble(body, traction)
+        blocks = plan.contract(plan.fit(w.E, w.nu, "f64"), "f64")
+        u, it, res = plan.pcg(blocks, f, fixed, rtol=1e-10, max_iter=20000)
+        t1 = time.perf_counter()
+        _, gf = plan.uf_grad(body, traction, u)
+        _, gk = plan.uKu_grad(w.E, w.nu, u, "f32", workspace=gws)
+        g = 2.0 * gf - gk
+        torch.cuda.synchronize()
+        return u, it, res, time.perf_counter() - t1
+
+    chain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, it, res, t_grad = chain()
+    total = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        plan.uf_grad(body, traction, u)
+        b.record()
+    torch.cuda.synchronize()
+    out["compliance"] = {"load": "traction (0, 0, -1) on xi_1 = 1, clamp xi_1 = 0, f = f^pi(ctrl)",
+                         "cg_iterations": it, "rel_residual": res,
+                         "ms_total_assemble_solve_gradient": total * 1e3,
+                         "ms_gradient_after_solve_f32": t_grad * 1e3,
+                         "ms_load_gradient": float(np.median([a.elapsed_time(b) for a, b in ev]))}
     plan.check()
     return out
 

@@ -131,7 +131,12 @@ igamt_status igamt_plan_csr_device(igamt_plan *plan, int64_t *d_row_ptr, int32_t
 
 /* --- design updates (same topology) ------------------------------------------
  * New macro control points [n_ctrl z][y][x][3], from host (on_device = 0) or
- * device memory (on_device = 1).                                              */
+ * device memory (on_device = 1).  The plan's device copy of the control points
+ * is the current one: every kernel reads it, and nothing is uploaded again
+ * from the host copy once the first call has placed the plan on the device (a
+ * device-side set leaves the host copy behind, unused).  Host input must be
+ * finite (IGAMT_EINVAL); device input is queued unchecked, and a non-finite
+ * point shows up as a degenerate Jacobian (the flag igamt_check reports).     */
 igamt_status igamt_set_macro_ctrl(igamt_plan *plan, const double *ctrl, int32_t on_device, void *stream);
 /* New reference-tile control points (host), same knots; tables must be rebuilt.
  * Boundary points must stay at their Greville positions (IGAMT_EINVAL).       */
@@ -230,8 +235,10 @@ igamt_status igamt_spmv(igamt_precision prec, int64_t n_rows, const int64_t *d_r
  * POD basis of a set of tables (not in the paper; replaces one table build per
  * design of a parameterised tile family).  d_snap double [n_s][n_e] (n_e =
  * n_pairs * n_cols, row-major tables).  Computes the mean, the Gram matrix of
- * the centred snapshots (FP64, device), its eigenpairs (host, cyclic Jacobi),
- * and the r leading modes.  Outputs: d_mean float [n_e], d_basis float
+ * the centred snapshots (FP64, device), its eigenpairs (host: Householder
+ * tridiagonalisation, then implicit QR steps with Wilkinson shifts; an
+ * iteration that does not converge within 64 n_s steps returns
+ * IGAMT_EDEGENERATE), and the r leading modes.  Outputs: d_mean float [n_e], d_basis float
  * [r][n_e] (orthonormal rows), h_sigma double [n_s] singular values
  * (descending), h_coeffs double [n_s][r] (may be NULL): the coefficients of
  * each centred snapshot in the basis (= V Sigma).  d_work double:
@@ -324,6 +331,23 @@ igamt_status igamt_load_fit(igamt_plan *plan, const double *body, const double *
 igamt_status igamt_load_gather(igamt_plan *plan, const double *d_coef, double *d_f, void *stream);
 igamt_status igamt_load_assemble(igamt_plan *plan, const double *body, const double *traction, double *d_f,
                                  void *d_workspace, void *stream);
+
+/* Shape derivative of the external work (Section 4.1.2, eq. (69), through the
+ * load projections of eq. (40)-(41), (44)-(45) and the lookup of eq. (53)):
+ * d(u . f^pi)/d m for every macro control point m, u fixed, f^pi the load vector
+ * igamt_load_assemble computes for the same body force and tractions (host
+ * arrays as there).  Its body term carries |det J_M| and its face terms the face
+ * area element, both of which move with m; with u = K^-1 f the compliance
+ * c = f^T K^-1 f has dc/dm = 2 d(u . f)/dm - d(u^T K u)/dm.  FP64 throughout.
+ * d_u double [n_dofs]; d_grad double [n_macro_ctrl][3] (z, y, x order as ctrl);
+ * d_uf double [1] receives u . f^pi (may be NULL).  d_workspace:
+ * igamt_uf_grad_workspace_bytes (per-tile local gradients and shares, reduced
+ * over the tiles in a fixed order: bitwise reproducible).  Needs the load table
+ * (igamt_load_table_build); IGAMT_ESTATE otherwise.  A det J <= 0 at a sample
+ * raises the degeneracy flag.  NURBS maps: weights held fixed.               */
+igamt_status igamt_uf_grad_workspace_bytes(const igamt_plan *plan, int64_t *bytes);
+igamt_status igamt_uf_grad(igamt_plan *plan, const double *body, const double *traction, const double *d_u,
+                           double *d_grad, double *d_uf, void *d_workspace, void *stream);
 
 /* --- matrix-free product (Section 4.2, eq. (74)) ------------------------------
  * y = K u for the full symmetric stiffness matrix K (the CSR matrix igamt_assemble

@@ -333,6 +333,22 @@ class Plan:
                                         _ptr(out), _ptr(workspace), _stream()))
         return out
 
+    def uf_grad(self, body, traction, u, workspace=None):
+        """(u . f^pi, d(u . f^pi)/d macro control points) with u fixed; f^pi is the load vector of
+        load_assemble for the same body force and tractions (needs load_table_build)."""
+        torch = _torch()
+        b, t = self._loads(body, traction)
+        u = self._vec(u)
+        grad = torch.empty(self.macro_ctrl_shape, dtype=torch.float64, device="cuda")
+        val = torch.empty(1, dtype=torch.float64, device="cuda")
+        if workspace is None:
+            nb = C.c_int64()
+            check(lib().igamt_uf_grad_workspace_bytes(self._h, C.byref(nb)))
+            workspace = self._empty_bytes(nb.value)
+        check(lib().igamt_uf_grad(self._h, b.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), _ptr(u),
+                                  _ptr(grad), _ptr(val), _ptr(workspace), _stream()))
+        return val, grad
+
     # ---- matrix-free product K u (eq. (74)) -----------------------------------------------
     def linop_workspace(self, prec="f64", slab_tiles=0):
         nb = C.c_int64()

@@ -73,6 +73,8 @@ SIGNATURES = {
     "igamt_load_fit": (status, [vp, vp, vp, vp, vp]),
     "igamt_load_gather": (status, [vp, vp, vp, vp]),
     "igamt_load_assemble": (status, [vp, vp, vp, vp, vp, vp]),
+    "igamt_uf_grad_workspace_bytes": (status, [vp, P_i64]),
+    "igamt_uf_grad": (status, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "igamt_linop_workspace_bytes": (status, [vp, i32, i64, P_i64]),
     "igamt_apply_blocks": (status, [vp, i32, vp, vp, vp, vp, vp]),
     "igamt_linop": (status, [vp, i32, i64, vp, vp, vp, vp, vp]),

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
         }
       }
     }
-    lg[e] = a.wts ? g * a.wts[(lo[0] + l[0]) + (int64_t)a.nM[0] * ((lo[1] + l[1]) + (int64_t)a.nM[1] * (lo[2] + l[2]))]
+    lg[e] = a.wts ? g * local_weight(a.wts, a.nM, lo, l)
                   : g;
   }
 }

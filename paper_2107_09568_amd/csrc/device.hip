@@ -122,6 +122,8 @@ static __global__ void tile_boundary_kernel(const double *__restrict__ ctrl, con
   if (!(e <= 1e-12)) atomicMin(flag + 2, id);
 }
 
+// The device copy is the current one once ensure_device has run (it is the only upload from the
+// host copy P->ctrlM); a device-side set leaves P->ctrlM behind, and nothing reads it afterwards.
 igamt_status upload_macro_ctrl(igamt_plan *P, const double *ctrl, int on_device, void *stream) {
   const int64_t n = 3LL * P->nM[0] * P->nM[1] * P->nM[2];
   hipStream_t s = (hipStream_t)stream;

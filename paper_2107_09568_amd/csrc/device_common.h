@@ -260,6 +260,15 @@ __device__ inline void rational_terms(const double *__restrict__ wts, const int 
   for (int c = 0; c < 3; ++c) out[1 + c] = (G[3 * c] * dW[0] + G[3 * c + 1] * dW[1] + G[3 * c + 2] * dW[2]) * r * r;
 }
 
+// NURBS weight of the tile-local macro control point lo + l, or 0 where lo + l lies past the net (a
+// tile whose samples meet fewer spans than the widest tile: no sample lies in such a point's
+// support, so its local gradient is an exact zero anyway).
+__device__ inline double local_weight(const double *__restrict__ w, const int *nM, const int (&lo)[3], const int (&l)[3]) {
+  const int i0 = lo[0] + l[0], i1 = lo[1] + l[1], i2 = lo[2] + l[2];
+  if (i0 >= nM[0] || i1 >= nM[1] || i2 >= nM[2]) return 0.0;
+  return w[i0 + (int64_t)nM[0] * (i1 + (int64_t)nM[1] * i2)];
+}
+
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace igamt

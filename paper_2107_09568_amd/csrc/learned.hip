@@ -115,8 +115,9 @@ __global__ __launch_bounds__(256) void pod_basis_kernel(const double *__restrict
 // form T = Q^T A Q, then implicit symmetric QR steps with the Wilkinson shift on T, each step a
 // chase of the bulge by Givens rotations that are also applied to Q (the method of Golub and
 // Van Loan, Matrix Computations, sections 8.3.1-8.3.3).  On return A's diagonal holds the
-// eigenvalues and V's columns (V[i n + k]) the eigenvectors.
-static void sym_eigen(std::vector<double> &A, int n, std::vector<double> &V) {
+// eigenvalues and V's columns (V[i n + k]) the eigenvectors.  Returns false if the QR steps hit
+// their cap (64 n) before every off-diagonal entry was deflated.
+static bool sym_eigen(std::vector<double> &A, int n, std::vector<double> &V) {
   auto at = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
   V.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
@@ -197,6 +198,7 @@ static void sym_eigen(std::vector<double> &A, int n, std::vector<double> &V) {
     }
   }
   for (int i = 0; i < n; ++i) at(i, i) = d[i];
+  return hi == 0;
 }
 
 // table[p][k] = mean[e] + sum_r basis[r][e] c[r], e = p * K + k
@@ -449,7 +451,10 @@ extern "C" igamt_status igamt_pod_build(const double *d_snap, int32_t n_s, int64
   std::vector<double> A((size_t)n_s * n_s), V;
   IGAMT_HIP(hipMemcpyAsync(A.data(), G, A.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   IGAMT_HIP(hipStreamSynchronize(s));
-  sym_eigen(A, n_s, V);
+  if (!sym_eigen(A, n_s, V)) {
+    set_error("POD: the symmetric QR iteration did not converge within its step cap");
+    return IGAMT_EDEGENERATE;
+  }
   std::vector<int> order(n_s);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(),

@@ -399,6 +399,9 @@ static igamt_status build_plan(igamt_plan *P, const igamt_spline3d *macro, const
         smin = std::min(smin, sp);
         smax = std::max(smax, sp);
       }
+      // tiles on a macro face also take samples on that face (the traction's area element)
+      if (t == 0) smin = std::min(smin, find_span_host(P->kM[d], n, p, P->box_a[d][t]));
+      if (t == T - 1) smax = std::max(smax, find_span_host(P->kM[d], n, p, P->box_a[d][t] + P->box_h[d][t]));
       P->ctrl_lo[d][t] = smin - p;
       cnt[t] = smax - smin + p + 1;
       L = std::max(L, cnt[t]);

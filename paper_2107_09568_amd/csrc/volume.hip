@@ -188,7 +188,7 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
         }
       }
     }
-    lg[e] = a.wts ? gsum * a.wts[(lo[0] + l[0]) + (int64_t)a.nM[0] * ((lo[1] + l[1]) + (int64_t)a.nM[1] * (lo[2] + l[2]))]
+    lg[e] = a.wts ? gsum * local_weight(a.wts, a.nM, lo, l)
                   : gsum;
   }
 }
