@@ -420,6 +420,26 @@ igamt_status igamt_volume_workspace_bytes(const igamt_plan *plan, int64_t *bytes
 igamt_status igamt_volume(igamt_plan *plan, double *d_tile_volumes, double *d_volume, double *d_grad,
                           void *d_workspace, void *stream);
 
+/* igamt_volume_noalloc: igamt_volume without a workspace and without any
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * tile volumes and local gradients go to a static device array of
+ * IGAMT_VOLUME_SCRATCH_BYTES (32 MiB) that the library holds on every GPU it
+ * runs on until the process ends: 8 n_tiles bytes (256-aligned), plus
+ * 24 n_tiles Lx Ly Lz bytes with d_grad (L_k the macro control points a tile's
+ * samples touch per direction: 27 at a degree-2 map on its knot spans, so
+ * about 250 000 tiles without the gradient and 51 000 with it).  A plan that
+ * needs more returns IGAMT_ESHAPE and queues nothing.  Same arguments, kernels
+ * and results (bit for bit) as igamt_volume.  The volume table must be built
+ * (IGAMT_ESTATE otherwise; the plan is then already on its device, so this
+ * call sets nothing up).  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap on one GPU (other streams, other plans) race and must be
+ * ordered by the caller.                                                      */
+#define IGAMT_VOLUME_SCRATCH_BYTES (32LL << 20)
+igamt_status igamt_volume_noalloc(igamt_plan *plan, double *d_tile_volumes, double *d_volume, double *d_grad,
+                                  void *stream);
+
 /* --- projection error and adaptive degree (Section 3.2.2 after eq. (48);
  *     Section 3.3.1, eq. (59), (65)) --------------------------------------------
  * igamt_eproj: E_proj(q) = max over tiles and samples of |A - Pi_q A|_F / |A|_F

@@ -438,6 +438,17 @@ class Plan:
                                  _stream()))
         return v, tv, g
 
+    def volume_noalloc(self, grad=False, v=None, tv=None, g=None):
+        """volume() through igamt_volume_noalloc: the library's static device scratch replaces the
+        workspace (no allocation inside the call; outputs may be passed in to allocate none here)."""
+        torch = _torch()
+        v = torch.empty(1, dtype=torch.float64, device="cuda") if v is None else v
+        tv = torch.empty(self.n_tiles, dtype=torch.float64, device="cuda") if tv is None else tv
+        if grad and g is None:
+            g = torch.empty((self.n_macro_ctrl, 3), dtype=torch.float64, device="cuda")
+        check(lib().igamt_volume_noalloc(self._h, _ptr(tv), _ptr(v), _ptr(g) if grad else None, _stream()))
+        return v, tv, g if grad else None
+
     # ---- projection error and adaptive degree (eq. (59), (65)) -----------------------------
     def eproj(self, E, nu, q=None, n_sample=5, per_tile=False):
         """E_proj (eq. (59)) at degree q (an int or a triple; default the plan's); with per_tile, also

@@ -83,6 +83,7 @@ SIGNATURES = {
     "igamt_volume_table_get": (status, [vp, vp, vp, vp]),
     "igamt_volume_workspace_bytes": (status, [vp, P_i64]),
     "igamt_volume": (status, [vp, vp, vp, vp, vp, vp]),
+    "igamt_volume_noalloc": (status, [vp, vp, vp, vp, vp]),
     "igamt_eproj": (status, [vp, f64, f64, i32, i32, vp, C.POINTER(f64), vp]),
     "igamt_select_q": (status, [vp, f64, f64, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
     "igamt_eproj_aniso": (status, [vp, f64, f64, vp, i32, vp, C.POINTER(f64), vp]),

@@ -74,6 +74,8 @@ igamt_status ensure_device(igamt_plan *P) {
   IGAMT_HIP(hipMalloc((void **)&d.table_h, 2 * MK * sizeof(uint16_t)));
   IGAMT_HIP(hipMalloc((void **)&d.table_h_scale, P->Mp * sizeof(float)));
   IGAMT_HIP(hipDeviceSynchronize());
+  // the allocation-free volume entry point reports a failed lookup itself; nothing else needs it
+  (void)volume_scratch_setup(cur);
   d.ready = true;
   return IGAMT_OK;
 }

@@ -177,6 +177,9 @@ igamt_status launch_gemm_tiles(igamt_precision prec, const void *A, const void *
 // fixed-order reductions of the shape gradients (adjoint.hip): per-tile local gradients
 // [n_tiles][Lc2][Lc1][Lc0][3] summed per macro control point into grad [n_macro_ctrl][3]; and a
 // one-workgroup sum of x [n] into out[0]
+// Looks up this device's address of the static scratch of igamt_volume_noalloc (once per device,
+// with that device current); called by ensure_device.
+igamt_status volume_scratch_setup(int device);
 igamt_status launch_grad_reduce(igamt_plan *plan, const double *local_grad, double *grad, void *stream);
 igamt_status launch_sum(const double *x, int64_t n, double *out, void *stream);
 // rows of the transposed table (table columns padded to a multiple of the contraction's row block)

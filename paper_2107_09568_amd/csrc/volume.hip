@@ -16,6 +16,7 @@
 // samples touch, then the fixed-order per-control-point reduction shared with the compliance
 // sensitivity.  V = sum of the tile volumes in a fixed order: bitwise reproducible.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -275,6 +276,38 @@ extern "C" igamt_status igamt_volume_table_get(const igamt_plan *P, double *d_ta
   return IGAMT_OK;
 }
 
+// ---- scratch of igamt_volume_noalloc ------------------------------------------------------
+// One file-scope device array per GPU (the tile volumes, then the tiles' local control-point
+// gradients), held until the process ends.  In host code `scratch` names a host-side stand-in, not
+// a device address: every use goes through the per-device address looked up by
+// volume_scratch_setup, which ensure_device calls once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[IGAMT_VOLUME_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+namespace igamt {
+igamt_status volume_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) { set_error("device index out of range"); return IGAMT_EINVAL; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return IGAMT_OK;
+  void *ptr = nullptr;
+  IGAMT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) { set_error("no device address for the volume scratch"); return IGAMT_EHIP; }
+  g_scratch_ptr[device] = ptr;
+  return IGAMT_OK;
+}
+}  // namespace igamt
+
+static void *volume_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 static int64_t volume_local_bytes(const igamt_plan *P) {
   return align256(P->n_tiles * (int64_t)P->Lc[0] * P->Lc[1] * P->Lc[2] * 3 * sizeof(double));
 }
@@ -285,12 +318,11 @@ extern "C" igamt_status igamt_volume_workspace_bytes(const igamt_plan *P, int64_
   return IGAMT_OK;
 }
 
-extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, double *d_volume, double *d_grad,
-                                     void *d_workspace, void *stream) {
-  if (!P || !d_volume || !d_workspace) { set_error("NULL argument"); return IGAMT_EINVAL; }
-  igamt_status st = ensure_device(P);
-  if (st) return st;
-  if (!P->volume_ready) { set_error("volume table not built"); return IGAMT_ESTATE; }
+// The tile kernel, the fixed-order volume sum and, with d_grad, the per-control-point reduction,
+// with the tile volumes and local gradients in the workspace ws.
+static igamt_status volume_run(igamt_plan *P, double *d_tile_volumes, double *d_volume, double *d_grad, void *d_workspace,
+                               void *stream) {
+  igamt_status st;
   if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
     set_error("macro maps with different degrees per direction are not supported");
     return IGAMT_EUNSUPPORTED;
@@ -335,4 +367,34 @@ extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, doub
   if ((st = launch_sum(tv, P->n_tiles, d_volume, stream))) return st;
   if (d_grad && (st = launch_grad_reduce(P, lg, d_grad, stream))) return st;
   return IGAMT_OK;
+}
+
+extern "C" igamt_status igamt_volume(igamt_plan *P, double *d_tile_volumes, double *d_volume, double *d_grad,
+                                     void *d_workspace, void *stream) {
+  if (!P || !d_volume || !d_workspace) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  if (!P->volume_ready) { set_error("volume table not built"); return IGAMT_ESTATE; }
+  return volume_run(P, d_tile_volumes, d_volume, d_grad, d_workspace, stream);
+}
+
+extern "C" igamt_status igamt_volume_noalloc(igamt_plan *P, double *d_tile_volumes, double *d_volume, double *d_grad,
+                                             void *stream) {
+  if (!P || !d_volume) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  // the volume table exists, so the plan is already on its device: no set-up (and no allocation) here
+  if (!P->dev.ready || !P->volume_ready) { set_error("volume table not built"); return IGAMT_ESTATE; }
+  int cur = 0;
+  IGAMT_HIP(hipGetDevice(&cur));
+  if (cur != P->dev.device) { set_error("plan used on a different device than it was set up on"); return IGAMT_ESTATE; }
+  const int64_t need = align256(P->n_tiles * (int64_t)sizeof(double)) + (d_grad ? volume_local_bytes(P) : 0);
+  if (need > (int64_t)IGAMT_VOLUME_SCRATCH_BYTES) {
+    set_error("igamt_volume_noalloc: the plan needs " + std::to_string(need) + " bytes of scratch (" +
+              (d_grad ? std::string("tile volumes and local gradients") : std::string("tile volumes")) +
+              "), the library's static scratch holds " + std::to_string((int64_t)IGAMT_VOLUME_SCRATCH_BYTES) +
+              "; use igamt_volume with a workspace");
+    return IGAMT_ESHAPE;
+  }
+  void *ws = volume_scratch_ptr(cur);
+  if (!ws) { set_error("the volume scratch's device address could not be looked up on this device"); return IGAMT_EHIP; }
+  return volume_run(P, d_tile_volumes, d_volume, d_grad, ws, stream);
 }
