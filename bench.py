@@ -114,6 +114,80 @@ def time_stages(torch, plan, w, prec, steps, warmup, ws):
             "serial_step_ms": st.sum(axis=1), "step_ms": step}, vals, blocks
 
 
+def rigid_residuals(torch, P, rp, ci, vals):
+    """K times the three rigid translations t_a (1 on every dof of component a): the translations lie
+    in the kernel of K exactly (the table's row sums vanish), so the residual measures the rounding of
+    the assembled values.  Reported as |K t_a| / (|K|_F |t_a|) and as the worst row's
+    |(K t_a)_i| / sum_j |K_ij| (the cancellation left in one row), maxima over a."""
+    import math
+    n = rp.numel() - 1
+    dt = vals.dtype
+    kf = torch.linalg.vector_norm(vals, dtype=torch.float64).item()
+    rowabs = P.spmv(rp, ci, vals.abs(), torch.ones(n, dtype=dt, device="cuda")).double()
+    p6 = row = 0.0
+    for a in range(3):
+        t = torch.zeros(n, dtype=dt, device="cuda")
+        t[a::3] = 1
+        y = P.spmv(rp, ci, vals, t)
+        p6 = max(p6, torch.linalg.vector_norm(y, dtype=torch.float64).item() / (kf * math.sqrt(n / 3)))
+        row = max(row, (y.abs().double() / rowabs.clamp_min(1e-300)).max().item())
+        del t, y
+    return {"normalized": p6, "worst_row": row}
+
+
+def oracle_comparisons(w, sample, gpu_sample_blocks, cfg1_gpu):
+    """The precision study against the FP64 oracle (part of the CPU-baseline leg): per-tile relative
+    Frobenius error of every precision's blocks on the sampled tiles, and on the 2x2x2-tile workload
+    E_mat (eq. (62)) and E_vec (eq. (63)) of the GPU's K^pi and f^pi against the oracle's plain
+    Gauss-quadrature K and f."""
+    from oracle import assembly, load, projection, standard, tables
+    pairs = tables.pair_set(w.tile)
+    table = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    ref = assembly.tile_blocks(table, projection.all_coefficients(w, sample))
+    rn = np.linalg.norm(ref.reshape(len(sample), -1), axis=1)
+    out = {"sample_tiles": int(len(sample))}
+    for name, blk in gpu_sample_blocks.items():
+        e = np.linalg.norm((blk - ref).reshape(len(sample), -1), axis=1) / rn
+        out[name] = {"max_tile_block_rel_err": float(e.max()), "median_tile_block_rel_err": float(np.median(e))}
+    # E_mat / E_vec on the small workload, for each projection degree the GPU ran
+    w1 = cfg1_gpu["workload"]
+    pairs1 = tables.pair_set(w1.tile)
+    kb = np.stack([standard.tile_block_standard(w1, t, pairs1) for t in range(w1.n_tiles)])
+    rp, ci, kbull = assembly.assemble_csr(w1, pairs1, kb)
+    fb = load.standard_load(w1, cfg1_gpu["body"], cfg1_gpu["traction"])
+    em = {}
+    for q, (vals, blocks, f) in cfg1_gpu["by_q"].items():
+        tile_err = np.linalg.norm((blocks - kb).reshape(w1.n_tiles, -1), axis=1) / \
+            np.linalg.norm(kb.reshape(w1.n_tiles, -1), axis=1)
+        em[f"q{q}"] = {"E_mat": float(np.linalg.norm(vals - kbull) / np.linalg.norm(kbull)),
+                       "E_mat_max_tile": float(tile_err.max()),
+                       "E_vec": float(np.linalg.norm(f - fb) / np.linalg.norm(fb))}
+    out["E_mat_E_vec_2x2x2_tiles"] = em
+    return out
+
+
+def cfg1_gpu_results(torch, W, P):
+    """GPU K^pi (FP64 CSR values and tile blocks) and f^pi on the 2x2x2-tile workload at q = 1..4, for
+    E_mat and E_vec against the oracle's Gauss-quadrature operators."""
+    import dataclasses
+    w = W.make("cfg1")
+    body = np.array([0.0, 0.0, -1.0])
+    traction = np.zeros((6, 3))
+    traction[1] = [0.0, 0.0, -1.0]
+    by_q = {}
+    for q in (1, 2, 3, 4):
+        wq = dataclasses.replace(w, q=q, n_fit=q + 1)
+        plan = P.Plan.from_workload(wq)
+        plan.tables_build()
+        plan.load_table_build()
+        blocks = plan.contract(plan.fit(wq.E, wq.nu, "f64"), "f64")
+        vals = plan.scatter(blocks, "f64")
+        f = plan.load_assemble(body, traction)
+        plan.check()
+        by_q[q] = (vals.cpu().numpy(), blocks.cpu().numpy(), f.cpu().numpy())
+    return {"workload": w, "body": body, "traction": traction, "by_q": by_q}
+
+
 def cpu_baseline(w, n_sample, seed=11, one_thread=False):
     """The CPU oracle on a seeded sample of tiles: fit + table contraction + CSR scatter of the sample
     (with all host threads, or with one BLAS thread)."""
@@ -489,6 +563,8 @@ def main():
     ap.add_argument("--cpu-tiles", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient and learned-table sections")
+    ap.add_argument("--assembly-only", action="store_true",
+                    help="only the assembly step and its precision variants (for profiler passes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -520,6 +596,12 @@ def main():
     ref_blocks = None
     rng = np.random.default_rng(5)
     sample = torch.from_numpy(np.sort(rng.choice(plan.n_tiles, size=min(512, plan.n_tiles), replace=False))).cuda()
+    host_blocks = {}          # sampled tiles' blocks per precision, for the oracle comparison
+    rigid = {}
+    ablations = {}
+    rp_d = ci_d = None
+    if not args.assembly_only:
+        rp_d, ci_d = plan.csr_device()
     for prec in precs:
         log(f"bench: {prec}")
         cb, bb = plan.workspace_bytes(prec)
@@ -529,12 +611,31 @@ def main():
         if prec == "f64":
             ref_blocks = blk
             err = 0.0
+        elif ref_blocks is None:
+            err = None
         else:
             d = (blk - ref_blocks).reshape(len(sample), -1).norm(dim=1) / ref_blocks.reshape(len(sample), -1).norm(dim=1)
             err = d.max().item()
+        host_blocks[prec] = blk.cpu().numpy()
+        if rp_d is not None:
+            rigid[prec] = rigid_residuals(torch, P, rp_d, ci_d, vals)
+        if prec == "bf16x3" and not args.assembly_only:
+            # ablations of the split: the table split alone (coefficients rounded once), and four products
+            coef = ws
+            bview = blocks[: plan.n_tiles * M * 9].view(plan.n_tiles, M, 9)
+            for prods in (2, 4):
+                plan.contract_products(coef, prods, out=bview)
+                st = _timed(torch, args.steps, [lambda: plan.contract_products(coef, prods, out=bview)])
+                ab = bview[sample].double()
+                dd = (ab - ref_blocks).reshape(len(sample), -1).norm(dim=1) / ref_blocks.reshape(len(sample), -1).norm(dim=1)
+                name = {2: "bf16_table_split_only", 4: "bf16x4_products"}[prods]
+                ablations[name] = {"contract_ms": float(np.mean(st[:, 0])), "max_block_rel_err_vs_f64": dd.max().item()}
+                host_blocks[name] = ab.cpu().numpy()
         results[prec] = (r, err)
         del ws, vals, blocks, blk
         torch.cuda.empty_cache()
+    del rp_d, ci_d
+    torch.cuda.empty_cache()
 
     main_prec = precs[0]
     r, _ = results[main_prec]
@@ -575,10 +676,15 @@ def main():
                           "contract_ms": cm, "contract_tflops": flops / (cm * 1e-3) / 1e12,
                           "mfma_frac": flops / (cm * 1e-3) / PEAK[prec],
                           "scatter_ms": float(np.median(rr["scatter_ms"])), "fit_ms": float(np.median(rr["fit_ms"])),
-                          "max_block_rel_err_vs_f64": err}
+                          "max_block_rel_err_vs_f64": err, "rigid_residual": rigid.get(prec)}
     out["variants"] = variants
+    if ablations:
+        out["ablations"] = ablations
     out["blocks_3x3_per_s"] = plan.n_pairs * out["value"]
     out["ms_per_step_min"] = float(np.min(r["step_ms"]))
+    if args.assembly_only:
+        print(json.dumps(out))
+        return
     log("bench: load vector")
     out["load_vector"] = bench_load(torch, plan, args.steps, args.warmup)
     log("bench: matrix-free product")
@@ -597,9 +703,18 @@ def main():
         out["adjoint"] = bench_adjoint(torch, W, P, args.steps)
         log("bench: learned tables")
         out["learned"] = bench_learned(torch, W, P)
+    cfg1 = cfg1_gpu_results(torch, W, P) if not args.no_cpu else None
     if not args.no_cpu:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_tiles)
+        log("bench: precision study against the oracle")
+        study = oracle_comparisons(w, sample.cpu().numpy(), host_blocks, cfg1)
+        for name, v in study.items():
+            if name in out["variants"]:
+                out["variants"][name]["max_block_rel_err_vs_oracle"] = v["max_tile_block_rel_err"]
+            elif name in out.get("ablations", {}):
+                out["ablations"][name]["max_block_rel_err_vs_oracle"] = v["max_tile_block_rel_err"]
+        out["precision_study"] = study
         log("bench: cpu baseline, one thread")
         out["cpu_baseline_1thread"] = cpu_baseline(w, max(256, args.cpu_tiles // 8), one_thread=True)
         out["cpu_baseline"]["note"] = ("cores counts the BLAS threads the oracle's table contraction may use; the "

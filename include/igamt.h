@@ -195,6 +195,18 @@ igamt_status igamt_fit(igamt_plan *plan, double E, double nu, igamt_precision pr
  * sum_k table[p][k] coef[t][ab][k].  Requires tables (ESTATE otherwise).     */
 igamt_status igamt_contract(igamt_plan *plan, igamt_precision prec, const void *d_coef,
                             void *d_blocks, void *stream);
+/* Ablations of the BF16 split contraction (precision study, not a production
+ * path): on the coefficients igamt_fit writes for IGAMT_BF16X3 (hi and lo
+ * planes), FP32 blocks as igamt_contract writes them, with
+ *   products = 3: lo*hi + hi*lo + hi*hi (what IGAMT_BF16X3 computes);
+ *   products = 2: the table split only, the coefficients rounded once to BF16
+ *                 (lo*hi + hi*hi; the lo plane of the coefficients is ignored);
+ *   products = 4: all four products (lo*lo added).
+ * Requires tables (IGAMT_ESTATE) and a padded table width of 128 or 256
+ * columns (q <= 2 isotropic; IGAMT_EUNSUPPORTED otherwise); IGAMT_EINVAL for
+ * other product counts.                                                      */
+igamt_status igamt_contract_products(igamt_plan *plan, int32_t products, const void *d_coef, void *d_blocks,
+                                     void *stream);
 /* Stage 3, deterministic scatter into the fixed CSR structure (step 4 of
  * Section 3.2.4): value(3 G_A + a, 3 G_B + b) = sum over the tiles that hold both
  * control points, in ascending tile index, of the block entry ((A,B) upper

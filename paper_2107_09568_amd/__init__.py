@@ -218,6 +218,15 @@ class Plan:
         check(lib().igamt_contract(self._h, _prec(prec), _ptr(coef), _ptr(out), _stream()))
         return out
 
+    def contract_products(self, coef, products, out=None):
+        """Ablations of the BF16 split contraction on BF16X3 coefficients: products = 2 (table split
+        only), 3 (the split mode) or 4 (with lo*lo); FP32 blocks [n_tiles, n_pairs, 9]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n_tiles, self.n_pairs, 9), dtype=torch.float32, device="cuda")
+        check(lib().igamt_contract_products(self._h, int(products), _ptr(coef), _ptr(out), _stream()))
+        return out
+
     def scatter(self, blocks, prec="f64", out=None):
         torch = _torch()
         dt = torch.float64 if _prec(prec) == F64 else torch.float32

@@ -55,6 +55,7 @@ SIGNATURES = {
     "igamt_workspace_bytes": (status, [vp, i32, P_i64, P_i64]),
     "igamt_fit": (status, [vp, f64, f64, i32, vp, vp]),
     "igamt_contract": (status, [vp, i32, vp, vp, vp]),
+    "igamt_contract_products": (status, [vp, i32, vp, vp, vp]),
     "igamt_scatter": (status, [vp, i32, vp, vp, vp]),
     "igamt_assemble": (status, [vp, f64, f64, i32, vp, vp, vp]),
     "igamt_check": (status, [vp, vp, P_i64]),

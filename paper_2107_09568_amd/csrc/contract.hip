@@ -422,6 +422,294 @@ __global__ __launch_bounds__(64 * kWaves<MODE>, kMinGroups<MODE>) void contract_
   }
 }
 
+// ---- split modes with the table resident in LDS ------------------------------------------------
+// The split products need three MFMAs per operand pair, so their operands must reach the matrix
+// cores at three times the FP32 rate.  This variant keeps a block of 112 table rows (hi and lo
+// planes, all k) in LDS for the whole life of a workgroup (one per CU), and streams the
+// coefficient columns straight from global memory into each wave's registers, a few k-steps
+// ahead: the table is read from L2 once per workgroup instead of once per column group, there is
+// no barrier after the table is staged, and every wave runs its own loop over passes of
+// 16 NCB columns.  The coefficient planes are stored tiled for it (split_coef_index): the 16
+// columns x 32 k of one MFMA fragment are 1 KB in lane order, so each fragment is one coalesced
+// 16-byte load per lane.  Per k-step (32 k) a wave issues 7 x NCB x P MFMAs (P = 2, 3 or 4
+// products) against 14 LDS fragment reads and NCB or 2 NCB global fragment loads.  Workgroups of
+// one XCD take every row block of one eighth of the columns, so each coefficient column is
+// fetched into that XCD's L2 once and read there by all row blocks.
+//   PROD = 3: lo*hi + hi*lo + hi*hi (the split mode); 2: lo*hi + hi*hi with the coefficients' lo
+//   plane ignored (table split only); 4: lo*lo + lo*hi + hi*lo + hi*hi.
+constexpr int kSplitRB16 = 7;                          // 16-row blocks per workgroup
+constexpr int kSplitRows = 16 * kSplitRB16;            // 112 table rows
+#ifndef IGAMT_SPLIT_WAVES
+#define IGAMT_SPLIT_WAVES 12
+#endif
+#ifndef IGAMT_SPLIT_NCB
+#define IGAMT_SPLIT_NCB 2
+#endif
+#ifndef IGAMT_SPLIT_NPF
+#define IGAMT_SPLIT_NPF 2
+#endif
+constexpr int kSplitWaves = IGAMT_SPLIT_WAVES;         // waves per workgroup
+constexpr int kSplitNCB = IGAMT_SPLIT_NCB;             // 16-column blocks per wave and pass
+constexpr int kSplitNPF = IGAMT_SPLIT_NPF;             // k-steps of coefficient fragments in flight
+constexpr int kSplitWC = 16 * kSplitNCB;               // columns per wave and pass
+constexpr int kStageCol = 20;                          // words per column of a wave's epilogue stage
+
+struct SplitArgs {
+  const uint16_t *Ah, *Al;   // table planes [Mp][Kp]
+  const float *Ascale;       // F16X3 inverse row scales [Mp]
+  const uint16_t *Bh, *Bl;   // coefficient planes, tiled (split_coef_index)
+  const float *Bscale;       // F16X3 inverse column scales [n_tiles_pad * 9]
+  float *out;                // [n_tiles][M][9], addressed by absolute tile index
+  int64_t M, Mp, Kp;
+  int64_t c_lo, c_hi;        // columns of this launch (tile groups of a slab, or all)
+  int64_t ncol_pad;          // coefficient columns in memory (9 n_tiles_pad, a multiple of 16)
+  int n_rblk, n_split;       // row blocks of 112 rows; column splits (a multiple of 8)
+  int row_bytes;             // LDS bytes of one table row of one plane (2 Kp + 16)
+};
+
+// the two table planes, the row block's 112 inverse row scales (F16X3), then one epilogue stage of
+// 32 columns x 16 rows per wave
+__host__ __device__ inline int64_t split_lds_bytes(int64_t Kp) {
+  return 2 * kSplitRows * (2 * Kp + 16) + 4 * kSplitRows + 4 * kSplitWaves * 32 * kStageCol;
+}
+
+template <int MODE, int KS, int PROD>
+__global__ __launch_bounds__(64 * kSplitWaves, 1) void contract_split_kernel(SplitArgs a) {
+  using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+  const int rb = slot % a.n_rblk, s = (slot / a.n_rblk) * 8 + xcd;
+  if (s >= a.n_split) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
+  const int64_t row0 = (int64_t)rb * kSplitRows;
+  constexpr int64_t Kp = 32 * KS;
+  constexpr int RB = 64 * KS + 16;   // LDS bytes of one table row of one plane (= a.row_bytes)
+  // columns of split s, in whole 16-column units
+  const int64_t units = (a.c_hi - a.c_lo + 15) / 16;
+  const int64_t c0 = a.c_lo + 16 * (units * s / a.n_split);
+  const int64_t c1 = min(a.c_hi, a.c_lo + 16 * (units * (s + 1) / a.n_split));
+  if (c1 <= c0) return;
+  // stage the row block's two table planes (rows past Mp read as zero)
+  {
+    constexpr int ppr = (int)(Kp / 8);   // 16-byte pieces per row and plane
+    for (int i = tid; i < 2 * kSplitRows * ppr; i += 64 * kSplitWaves) {
+      const int plane = i / (kSplitRows * ppr), rem = i - plane * kSplitRows * ppr;
+      const int r = rem / ppr, j = rem - r * ppr;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (row0 + r < a.Mp) v = *(const u32x4 *)((plane ? a.Al : a.Ah) + (row0 + r) * Kp + 8 * j);
+      *(u32x4 *)(lds + (plane * kSplitRows + r) * RB + 16 * j) = v;
+    }
+  }
+  float *rscale = (float *)(lds + 2 * kSplitRows * RB);
+  float *stage = rscale + kSplitRows + wave * 32 * kStageCol;   // this wave's epilogue stage (32 columns)
+  if constexpr (MODE == IGAMT_F16X3)
+    for (int r = tid; r < kSplitRows; r += 64 * kSplitWaves) rscale[r] = row0 + r < a.Mp ? a.Ascale[row0 + r] : 0.0f;
+  __syncthreads();
+  constexpr int64_t PER_PASS = kSplitWC * kSplitWaves;
+  const int n_pass = (int)((c1 - c0 + PER_PASS - 1) / PER_PASS);
+  // A fragment of row block r, k-step ks, plane pl: lane (l16, kq) holds row 16 r + l16, k 32 ks + 8 kq .. + 7;
+  // every fragment is one of two base addresses plus an immediate offset
+  const char *a_hi = lds + l16 * RB + 16 * kq;
+  const char *a_lo = a_hi + kSplitRows * RB;
+  auto a_frag = [&](int pl, int r, int ks) -> V8 {
+    return *(const V8 *)((pl ? a_lo : a_hi) + 16 * r * RB + 64 * ks);
+  };
+  // coefficient fragments: lane (l16, kq) holds column l16 of block cb, k 32 ks + 8 kq .. + 7, which
+  // the tiled planes store at lane * 8 within the fragment's 512 elements
+  V8 bh[kSplitNPF][kSplitNCB], bl[kSplitNPF][kSplitNCB];
+  auto load_b = [&](int slot_, int p, int ks) {
+#pragma unroll
+    for (int cb = 0; cb < kSplitNCB; ++cb) {
+      int64_t col = c0 + p * PER_PASS + wave * kSplitWC + 16 * cb;
+      col = min(col, a.ncol_pad - 16);   // past the range: a valid fragment, its result is not stored
+      const int64_t off = ((col >> 4) * KS + ks) * 512 + 8 * lane;
+      bh[slot_][cb] = *(const V8 *)(a.Bh + off);
+      if constexpr (PROD != 2) bl[slot_][cb] = *(const V8 *)(a.Bl + off);
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < kSplitNPF; ++i) load_b(i, i / KS, i % KS);
+  f4 acc[kSplitRB16][kSplitNCB];
+#pragma unroll
+  for (int r = 0; r < kSplitRB16; ++r)
+#pragma unroll
+    for (int cb = 0; cb < kSplitNCB; ++cb) acc[r][cb] = f4{0.f, 0.f, 0.f, 0.f};
+  auto mma = [&](const V8 &x, const V8 &y, f4 &c) {
+    if constexpr (MODE == IGAMT_BF16X3)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+    else
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+  };
+  for (int p = 0; p < n_pass; ++p) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      // keep each k-step's fragment reads within the k-step (hoisted, they would hold every
+      // k-step's fragments in registers at once)
+      __builtin_amdgcn_sched_barrier(0);
+      const int sl = ks % kSplitNPF;
+      // row blocks in pairs, the next pair's fragments read while this pair's MFMAs run
+      V8 ah[2][2], al[2][2];
+      ah[0][0] = a_frag(0, 0, ks);
+      al[0][0] = a_frag(1, 0, ks);
+      ah[0][1] = a_frag(0, 1, ks);
+      al[0][1] = a_frag(1, 1, ks);
+#pragma unroll
+      for (int rp = 0; rp < (kSplitRB16 + 1) / 2; ++rp) {
+        const int cur = rp & 1, nx = cur ^ 1;
+        if (rp + 1 < (kSplitRB16 + 1) / 2) {
+          const int r2 = 2 * (rp + 1);
+          ah[nx][0] = a_frag(0, r2, ks);
+          al[nx][0] = a_frag(1, r2, ks);
+          if (r2 + 1 < kSplitRB16) {
+            ah[nx][1] = a_frag(0, r2 + 1, ks);
+            al[nx][1] = a_frag(1, r2 + 1, ks);
+          }
+        }
+        const int nr = 2 * rp + 1 < kSplitRB16 ? 2 : 1;
+        if constexpr (PROD == 4) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (q < nr)
+#pragma unroll
+              for (int cb = 0; cb < kSplitNCB; ++cb) mma(al[cur][q], bl[sl][cb], acc[2 * rp + q][cb]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (q < nr)
+#pragma unroll
+            for (int cb = 0; cb < kSplitNCB; ++cb) mma(al[cur][q], bh[sl][cb], acc[2 * rp + q][cb]);
+        if constexpr (PROD != 2) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (q < nr)
+#pragma unroll
+              for (int cb = 0; cb < kSplitNCB; ++cb) mma(ah[cur][q], bl[sl][cb], acc[2 * rp + q][cb]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (q < nr)
+#pragma unroll
+            for (int cb = 0; cb < kSplitNCB; ++cb) mma(ah[cur][q], bh[sl][cb], acc[2 * rp + q][cb]);
+      }
+      // refill this slot with the fragments kSplitNPF k-steps ahead (the next pass past the last),
+      // after the last MFMA that reads it, so the loads can take the slot's registers
+      __builtin_amdgcn_sched_barrier(0);
+      const int kn = ks + kSplitNPF;
+      load_b(sl, p + kn / KS, kn % KS);
+    }
+    // Epilogue through the wave's LDS stage, 32 columns (two column blocks) and one 16-row block at
+    // a time.  Lane (l16, kq) holds C[4 kq + j][16 cb + l16]; the 16 x 32 values are written column
+    // by column, then read back in the order of their addresses in the block array -- tile part,
+    // row, ab, where a tile part is the run of the 32 columns that belong to one tile -- so that
+    // consecutive lanes store consecutive words.  Element e = lane + 64 i of that order is fixed for
+    // the 32 columns: its stage index and its block-array offset at row block 0 (row block r adds
+    // 16 rows, 144 words).
+#pragma unroll
+    for (int h = 0; h < kSplitNCB / 2; ++h) {
+      const int64_t cw = c0 + p * PER_PASS + wave * kSplitWC + 32 * h;
+      const int64_t t0 = cw / 9;
+      float *obase = a.out + (t0 * a.M + row0) * 9;   // tile t0, row row0
+      int spk[8];    // stage index | row within the block << 16
+      int goff[8];   // offset from obase at row block 0, or -1 past the column range
+      {
+        const int ab0 = (int)(cw - 9 * t0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int e = lane + 64 * i;
+          int base = 0, colo = 0, abs = ab0, k = min(9 - ab0, 32), t = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {   // at most five parts (1 + 9 + 9 + 9 + 4 columns)
+            if (e >= base + 16 * k) {
+              base += 16 * k;
+              colo += k;
+              abs = 0;
+              ++t;
+              k = min(9, 32 - colo);
+            }
+          }
+          const int local = e - base;
+          const int rr = (int)((float)local / (float)k);   // exact: local < 144, k <= 9
+          const int ab = abs + local - rr * k;
+          const int cl = colo + ab - abs;
+          spk[i] = (cl * kStageCol + rr) | (rr << 16);
+          goff[i] = cw + cl < c1 ? (int)(((int64_t)t * a.M + rr) * 9 + ab) : -1;
+        }
+      }
+      float cs[2] = {1.0f, 1.0f};
+      if constexpr (MODE == IGAMT_F16X3)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) cs[c] = cw + 16 * c + l16 < c1 ? a.Bscale[cw + 16 * c + l16] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < kSplitRB16; ++r) {
+        f4 rs = f4{1.f, 1.f, 1.f, 1.f};
+        if constexpr (MODE == IGAMT_F16X3) rs = *(const f4 *)(rscale + 16 * r + 4 * kq);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          f4 v = acc[r][2 * h + c];
+          if constexpr (MODE == IGAMT_F16X3)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = v[j] * (rs[j] * cs[c]);
+          *(f4 *)(stage + (16 * c + l16) * kStageCol + 4 * kq) = v;
+          acc[r][2 * h + c] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (goff[i] >= 0 && row0 + 16 * r + (spk[i] >> 16) < a.M) obase[goff[i] + 144 * r] = stage[spk[i] & 0xffff];
+      }
+    }
+  }
+}
+
+static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, int prod, const void *d_coef,
+                                          void *d_blocks, hipStream_t s, int64_t g0, int64_t g1) {
+  SplitArgs a;
+  const int64_t MK = P->Mp * P->Kp;
+  const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
+  const bool bf = prec == IGAMT_BF16X3;
+  a.Ah = bf ? P->dev.table_bf : P->dev.table_h;
+  a.Al = a.Ah + MK;
+  a.Ascale = bf ? nullptr : P->dev.table_h_scale;
+  a.Bh = (const uint16_t *)d_coef;
+  a.Bl = a.Bh + plane;
+  a.Bscale = bf ? nullptr : (const float *)(a.Bh + 2 * plane);
+  a.out = (float *)d_blocks;
+  a.M = P->n_pairs;
+  a.Mp = P->Mp;
+  a.Kp = P->Kp;
+  a.c_lo = g0 * BN;
+  a.c_hi = std::min(g1 * BN, 9 * P->n_tiles);
+  a.ncol_pad = 9 * P->n_tiles_pad;
+  a.n_rblk = (int)((P->Mp + kSplitRows - 1) / kSplitRows);
+  a.n_split = 8 * std::max(1, 32 / a.n_rblk);
+  a.row_bytes = (int)(2 * P->Kp + 16);
+  const size_t shm = (size_t)split_lds_bytes(P->Kp);
+  const dim3 grid((unsigned)(a.n_rblk * a.n_split)), block(64 * kSplitWaves);
+#define SPLIT_LAUNCH(M_, KS_, PR_)                                                                       \
+  do {                                                                                                 \
+    IGAMT_HIP(hipFuncSetAttribute((const void *)contract_split_kernel<M_, KS_, PR_>,                   \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));              \
+    hipLaunchKernelGGL((contract_split_kernel<M_, KS_, PR_>), grid, block, shm, s, a);                 \
+  } while (0)
+  const int ks = (int)(P->Kp / 32);
+  if (bf) {
+    if (ks == 8) {
+      if (prod == 3) SPLIT_LAUNCH(IGAMT_BF16X3, 8, 3);
+      else if (prod == 2) SPLIT_LAUNCH(IGAMT_BF16X3, 8, 2);
+      else SPLIT_LAUNCH(IGAMT_BF16X3, 8, 4);
+    } else {
+      if (prod == 3) SPLIT_LAUNCH(IGAMT_BF16X3, 4, 3);
+      else if (prod == 2) SPLIT_LAUNCH(IGAMT_BF16X3, 4, 2);
+      else SPLIT_LAUNCH(IGAMT_BF16X3, 4, 4);
+    }
+  } else {
+    if (ks == 8) SPLIT_LAUNCH(IGAMT_F16X3, 8, 3);
+    else SPLIT_LAUNCH(IGAMT_F16X3, 4, 3);
+  }
+#undef SPLIT_LAUNCH
+  IGAMT_LAUNCH_CHECK();
+  return IGAMT_OK;
+}
+
 // Grid of the contraction: 8 x (items of the busiest XCD) workgroups, one item each, or for
 // FP64 (one workgroup per CU) a persistent grid of one workgroup per CU, each looping over items.
 static unsigned contract_grid(igamt_precision prec, const ContractArgs &a) {
@@ -477,6 +765,8 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
       break;
     default: set_error("unknown precision"); return IGAMT_EINVAL;
   }
+  if ((prec == IGAMT_BF16X3 || prec == IGAMT_F16X3) && split_tiled(P->Kp))
+    return launch_contract_split(P, prec, 3, d_coef, d_blocks, (hipStream_t)stream, g0, g1);
   const int bm = prec == IGAMT_F64 ? kBM<IGAMT_F64> : prec == IGAMT_F32 ? kBM<IGAMT_F32> : kBM<IGAMT_BF16X3>;
   if (P->Mp % bm != 0) { set_error("padded table rows are not a multiple of the row block"); return IGAMT_EINVAL; }
   a.n_mblk = (int)(P->Mp / bm);
@@ -540,6 +830,20 @@ extern "C" igamt_status igamt_contract(igamt_plan *P, igamt_precision prec, cons
   igamt_status st = ensure_device(P);
   if (st) return st;
   return launch_contract(P, prec, d_coef, d_blocks, stream);
+}
+
+extern "C" igamt_status igamt_contract_products(igamt_plan *P, int32_t products, const void *d_coef, void *d_blocks,
+                                                void *stream) {
+  if (!P || !d_coef || !d_blocks) { set_error("NULL argument"); return IGAMT_EINVAL; }
+  if (products < 2 || products > 4) { set_error("products must be 2, 3 or 4"); return IGAMT_EINVAL; }
+  igamt_status st = ensure_device(P);
+  if (st) return st;
+  if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
+  if (!split_tiled(P->Kp)) {
+    set_error("the product ablations run for padded table widths of 128 or 256 columns");
+    return IGAMT_EUNSUPPORTED;
+  }
+  return launch_contract_split(P, IGAMT_BF16X3, products, d_coef, d_blocks, (hipStream_t)stream, 0, P->n_groups);
 }
 
 extern "C" igamt_status igamt_assemble(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_values,

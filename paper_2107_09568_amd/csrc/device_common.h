@@ -269,6 +269,17 @@ __device__ inline double local_weight(const double *__restrict__ w, const int *n
   return w[i0 + (int64_t)nM[0] * (i1 + (int64_t)nM[1] * i2)];
 }
 
+// The split modes (BF16X3, F16X3) contract with the table resident in LDS when the padded table
+// width is 128 or 256 columns (q <= 2 isotropic); their coefficient planes are then stored tiled:
+// the 16 columns x 32 k of one MFMA fragment contiguous, lane (l16, kq) at (kq 16 + l16) 8, i.e.
+// element (col, k) at ((col / 16) (Kp / 32) + k / 32) 512 + ((k % 32) / 8 16 + col % 16) 8 + k % 8.
+// Other widths keep the column-major layout col Kp + k.
+__host__ __device__ inline bool split_tiled(int64_t Kp) { return Kp == 128 || Kp == 256; }
+__host__ __device__ inline int64_t split_coef_index(int64_t col, int64_t k, int64_t Kp, bool tiled) {
+  if (!tiled) return col * Kp + k;
+  return ((col >> 4) * (Kp >> 5) + (k >> 5)) * 512 + ((((k & 31) >> 3) << 4) + (col & 15)) * 8 + (k & 7);
+}
+
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace igamt

@@ -26,6 +26,7 @@ struct FitArgs {
   const double *fx;
   const double *fP3;    // per-direction 1-D operators [(q1[0]) nf][(q1[1]) nf][(q1[2]) nf]
   int q1[3], nf, Kp, prec;
+  bool tiled;           // split modes: coefficient planes in the tiled layout (split_coef_index)
   double lam, mu;
   double L3;            // product over directions of the largest row sum of |P_k| (F16X3 scale bound)
   void *out;
@@ -40,16 +41,17 @@ __device__ inline void store_coef(const FitArgs &a, int64_t idx, double v, doubl
     ((double *)a.out)[idx] = v;
   } else if (a.prec == IGAMT_F32) {
     ((float *)a.out)[idx] = (float)v;
-  } else if (a.prec == IGAMT_BF16X3) {
-    uint16_t hi, lo;
-    split_bf16(v, hi, lo);
-    ((uint16_t *)a.out)[idx] = hi;
-    ((uint16_t *)a.out)[a.plane + idx] = lo;
   } else {
+    // idx = col Kp + k in the column-major numbering; the planes may be tiled
+    const int64_t col = idx / a.Kp;
+    const int64_t pos = split_coef_index(col, idx - col * a.Kp, a.Kp, a.tiled);
     uint16_t hi, lo;
-    split_f16(v * scale, hi, lo);
-    ((uint16_t *)a.out)[idx] = hi;
-    ((uint16_t *)a.out)[a.plane + idx] = lo;
+    if (a.prec == IGAMT_BF16X3)
+      split_bf16(v, hi, lo);
+    else
+      split_f16(v * scale, hi, lo);
+    ((uint16_t *)a.out)[pos] = hi;
+    ((uint16_t *)a.out)[a.plane + pos] = lo;
   }
 }
 
@@ -204,6 +206,7 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.nf = P->n_fit;
   a.Kp = P->Kp;
   a.prec = prec;
+  a.tiled = split_tiled(P->Kp);
   a.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   a.mu = E / (2.0 * (1.0 + nu));
   a.L3 = 1.0;

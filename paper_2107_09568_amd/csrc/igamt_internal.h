@@ -25,6 +25,7 @@ constexpr int kMaxTileControl = 16;   // tile control points per direction
 
 void set_error(const std::string &msg);
 
+
 // One direction of the glued 1-D structure: for every global index g its sorted
 // neighbour list (g2) and, per neighbour, the tiles holding both (1 or 2) with
 // the tile-local indices of g and g2.

@@ -97,3 +97,59 @@ def test_cfg3_assembly_bit_identical(case, prec):
     v_serial = plan.scatter(blocks, prec)
     torch.cuda.synchronize()
     assert torch.equal(v_pipe, v_serial)
+
+
+# Worst-row cancellation |(K t_a)_i| / sum_j |K_ij| of the rigid translations t_a (exactly in the kernel
+# of K: the table's row sums vanish).  A row's residual is the sum of the entries' errors, so it stays
+# within the entry error of the precision, here bounded by the per-block tolerance.
+RIGID_ROW_TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 1e-4, "f16x3": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_cfg3_rigid_translations(case, prec):
+    """K t_a for the three translations at 32^3 tiles in every precision of the contraction."""
+    torch, P, w, plan, pairs, table, ref_table, sample = case
+    _say(f"cfg3 {prec}: assemble for K t")
+    vals = plan.assemble(w.E, w.nu, prec)
+    rp, ci = plan.csr_device()
+    n = plan.n_dofs
+    dt = vals.dtype
+    rowabs = P.spmv(rp, ci, vals.abs(), torch.ones(n, dtype=dt, device="cuda")).double()
+    kf = torch.linalg.vector_norm(vals, dtype=torch.float64).item()
+    worst_row = worst_p6 = 0.0
+    for a in range(3):
+        t = torch.zeros(n, dtype=dt, device="cuda")
+        t[a::3] = 1
+        y = P.spmv(rp, ci, vals, t)
+        worst_row = max(worst_row, (y.abs().double() / rowabs).max().item())
+        worst_p6 = max(worst_p6, torch.linalg.vector_norm(y, dtype=torch.float64).item() / (kf * (n / 3) ** 0.5))
+    _say(f"cfg3 {prec}: |K t| / (|K|_F |t|) = {worst_p6:.2e}; worst row |(K t)_i| / sum_j |K_ij| = {worst_row:.2e}")
+    assert worst_row < RIGID_ROW_TOL[prec]
+    if prec == "f64":
+        assert worst_p6 < 1e-14
+    del vals, rp, ci, rowabs
+    torch.cuda.empty_cache()
+
+
+def test_cfg3_split_ablations(case):
+    """Precision study: splitting only the table (coefficients rounded once to BF16) leaves the
+    coefficients' 2^-9 rounding and misses the mixed tolerance; four products meet it like three."""
+    torch, P, w, plan, pairs, table, ref_table, sample = case
+    coef = plan.fit(w.E, w.nu, "bf16x3")
+    P_ = projection.projection_operator(w.q, w.n_fit)
+    refs = {t: ref_table @ projection.tile_coefficients(w, t, P_) for t in sample}
+    errs = {}
+    for prods in (2, 3, 4):
+        blocks = plan.contract_products(coef, prods)
+        errs[prods] = max(np.linalg.norm(blocks[t].double().cpu().numpy() - refs[t]) / np.linalg.norm(refs[t])
+                          for t in sample)
+        del blocks
+    b3 = plan.contract(coef, "bf16x3")
+    e_default = max(np.linalg.norm(b3[t].double().cpu().numpy() - refs[t]) / np.linalg.norm(refs[t]) for t in sample)
+    _say(f"cfg3 BF16 ablations: products 2 (table split only) {errs[2]:.2e}, 3 {errs[3]:.2e}, 4 {errs[4]:.2e}; "
+         f"contract bf16x3 {e_default:.2e}")
+    assert errs[2] > 1e-4
+    assert errs[3] < 1e-4 and errs[4] < 1e-4
+    assert e_default < 1e-4
+    del b3, coef
+    torch.cuda.empty_cache()

@@ -29,16 +29,19 @@ def _flat(params):
     return np.concatenate([p.ravel() for p in params])
 
 
-def test_mlp_kernels_vs_oracle(env):
+@pytest.mark.parametrize("widths,batch", [([4, 16, 12, 8], 10), ([4, 128, 128, 64], 512)],
+                         ids=["small", "trained_shape"])
+def test_mlp_kernels_vs_oracle(env, widths, batch):
+    """Forward, loss, backward and one Adam step against the FP64 oracle, at a small shape and at the
+    trained network's shape (4-128-128-64, the full training batch of 512 designs)."""
     torch, P, L = env
-    widths = [4, 16, 12, 8]
-    mlp = L.MLP(widths, batch=10, seed=3)
+    mlp = L.MLP(widths, batch=batch, seed=3)
     params64 = OL.init_mlp(widths, seed=3)        # same recipe and seed: identical values
     assert np.allclose(mlp.params.cpu().numpy(), _flat(params64).astype(np.float32))
     params64 = [p.astype(np.float32).astype(np.float64) for p in params64]
     rng = np.random.default_rng(4)
-    x = rng.uniform(-1, 1, size=(10, 4))
-    t = rng.standard_normal((10, 8))
+    x = rng.uniform(-1, 1, size=(batch, widths[0]))
+    t = rng.standard_normal((batch, widths[-1]))
     xd = torch.from_numpy(x.astype(np.float32)).cuda()
     td = torch.from_numpy(t.astype(np.float32)).cuda()
     tr = L.Trainer(mlp, xd, td)
@@ -53,7 +56,7 @@ def test_mlp_kernels_vs_oracle(env):
     g = tr.grads.cpu().numpy()
     gr = _flat(g_ref)
     err = np.abs(g - gr).max() / np.abs(gr).max()
-    _say(f"MLP grads vs FP64 oracle: {err:.2e}")
+    _say(f"MLP {widths} batch {batch}: grads vs FP64 oracle: {err:.2e}")
     assert err < 1e-5
     p_ref = [p.copy() for p in params64]
     m = [np.zeros_like(p) for p in p_ref]
@@ -299,3 +302,53 @@ def test_learned_graph_replay_matches_eager(family):
         assert bool(torch.isfinite(scratch))
     assert int(gate_g.item()) == 0 and int(ref_gate.item()) == 0
     plan.check()
+
+
+def test_pod_reconstruction_vs_host(family):
+    """The reconstruction T = mean + Phi^T (s c) of the trained tables (r = 64 modes of 848 556
+    entries), one design at a time and in a batch, entry by entry against the same sum on the host
+    in FP64 from the same FP32 mean, basis and network outputs."""
+    torch, P, L, w, plan, tn, p_test = family
+    coeffs = tn.predict_coeffs(p_test).clone()                  # [64, r] FP32 network outputs
+    mean = tn.mean.double().cpu().numpy()
+    basis = tn.basis.double().cpu().numpy()                      # [r, n_e]
+    c = coeffs.double().cpu().numpy() * float(tn.coeff_scale)
+    ref = mean[None, :] + c @ basis                              # [64, n_e]
+    scale = np.abs(ref).max()
+    tabs = plan.tables_from_pod_batch(tn.mean, tn.basis, coeffs, float(tn.coeff_scale))
+    got = tabs.reshape(len(p_test), -1).cpu().numpy()
+    err_b = np.abs(got - ref).max() / scale
+    plan.table_from_pod(tn.mean, tn.basis, coeffs[3], float(tn.coeff_scale))
+    one = plan.tables_get().reshape(-1).cpu().numpy()
+    err_1 = np.abs(one - ref[3]).max() / scale
+    _say(f"POD reconstruction vs host FP64: batch {err_b:.2e}, one design {err_1:.2e} (of max |T|)")
+    assert err_b < 1e-6 and err_1 < 1e-6
+
+
+def test_learned_batch_gain_preconditions(family):
+    """What the batched learned path's gain rests on, over all 64 held-out designs: no design falls
+    back, every learned table is within 1e-3 of its exact table, and assembling the 24^3-tile mesh
+    with a learned table stays within 3e-3 of the exact-table assembly (the time ratio itself is a
+    benchmark figure)."""
+    torch, P, L, w, plan, tn, p_test = family
+    ctrls = _family_ctrls(torch, p_test)
+    tabs, err_b, gate_b = tn.tables_for_batch(p_test, ctrls)
+    exact = plan.tables_build_batch(ctrls)
+    plan.check()
+    assert int(gate_b.sum().item()) == 0, "a held-out design fell back to the exact table"
+    true = ((tabs - exact).flatten(1).norm(dim=1) / exact.flatten(1).norm(dim=1)).cpu().numpy()
+    assert true.max() < 1e-3, true.max()
+    ws = plan.workspace("f64")
+    worst = 0.0
+    for b in range(len(p_test)):
+        plan.set_tile_ctrl(ctrls[b])
+        plan.tables_set(exact[b])
+        ref = plan.assemble(w.E, w.nu, "f64", workspace=ws).clone()
+        plan.tables_set(tabs[b])
+        got = plan.assemble(w.E, w.nu, "f64", workspace=ws)
+        worst = max(worst, ((got - ref).norm() / ref.norm()).item())
+        del ref, got
+    plan.check()
+    _say(f"64 held-out designs: no fallback, table err max {true.max():.2e}; "
+         f"24^3 assembly with the learned table vs exact: max CSR rel err {worst:.2e}")
+    assert worst < 3e-3
