@@ -92,8 +92,10 @@ struct FitAdjArgs {
 constexpr int kFitAdjThreads = 256;   // threads per tile in the fit adjoint
 
 // GJ (1 or 3): (i, j) blocks carried through the passes together (the same i, consecutive j)
-template <int PM, int GJ>
+template <int P0, int P1, int P2, int GJ>
 __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs a) {
+  constexpr int PMX = max3(P0, P1, P2);
+  constexpr int PD[3] = {P0, P1, P2};
   constexpr int NC = 9 * GJ;         // components per pass: (j, a, b)
   extern __shared__ double smem[];
   const int nf = a.nf, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
@@ -120,19 +122,19 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
   for (int e = tid; e < 3 * nf; e += kFitAdjThreads) {
     const int k = e / nf, s = e % nf;
     const double x = ax[k] + hx[k] * a.fx[s];
-    const int sp = find_span(a.knots[k], a.nM[k], PM, x);
-    double N[PM + 1], dN[PM + 1];
-    bspline_ders<PM>(a.knots[k], sp, x, N, dN);
+    const int sp = find_span(a.knots[k], a.nM[k], PD[k], x);
+    double N[PMX + 1], dN[PMX + 1];
+    bspline_ders_dir<P0, P1, P2>(k, a.knots[k], sp, x, N, dN);
     SP[k][s] = sp;
-    for (int r = 0; r <= PM; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
+    for (int r = 0; r <= PMX; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
   }
   // F and D at the samples; zero the adjoint accumulators
   for (int s = tid; s < ns; s += kFitAdjThreads) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
-    double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+    double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian3<P0, P1, P2>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
   if (a.wts) {
     for (int s = tid; s < ns; s += kFitAdjThreads) {
       const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-      rational_terms<PM>(a.wts, a.nM, SP, NB, DB, si, FB + s * 10, WQ + s * 4);
+      rational_terms3<P0, P1, P2>(a.wts, a.nM, SP, NB, DB, si, FB + s * 10, WQ + s * 4);
     }
     __syncthreads();
   }
@@ -282,8 +284,8 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
   double *XV = smem + a.xt_off, *XD = XV + 3 * nf * Lm;   // [3][nf][Lm] each
   for (int e = tid; e < 3 * nf * Lm; e += kFitAdjThreads) {
     const int k = e / (nf * Lm), rem = e - k * nf * Lm, sk = rem / Lm, l = rem - sk * Lm;
-    const int r = lo[k] + l - (SP[k][sk] - PM);
-    const bool on = r >= 0 && r <= PM;
+    const int r = lo[k] + l - (SP[k][sk] - PD[k]);
+    const bool on = r >= 0 && r <= PD[k];
     const int rc = on ? r : 0;
     XV[e] = on ? NB[k][sk][rc] : 0.0;
     XD[e] = on ? DB[k][sk][rc] : 0.0;
@@ -420,10 +422,6 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->tables_ready) { set_error("tables are not built or set"); return IGAMT_ESTATE; }
-  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
-    set_error("macro maps with different degrees per direction are not supported");
-    return IGAMT_EUNSUPPORTED;
-  }
   hipStream_t s = (hipStream_t)stream;
   int64_t off[6];
   grad_ws_layout(P, prec, off);
@@ -494,26 +492,21 @@ extern "C" igamt_status igamt_uKu_grad(igamt_plan *P, double E, double nu, igamt
   const size_t shm = (size_t)(f.xt_off + xt) * sizeof(double);
   if (shm > 150 * 1024) { set_error("tile samples or macro control points per tile too many for the fit adjoint"); return IGAMT_EUNSUPPORTED; }
   const dim3 fgrid((unsigned)P->n_tiles), fblock(kFitAdjThreads);
-  switch (P->pM[0]) {
-#define FA_LAUNCH(p, g)                                                                                 \
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define FA_LAUNCH(p0, p1, p2, g)                                                                        \
   do {                                                                                                  \
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_adjoint_kernel<p, g>,              \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_adjoint_kernel<p0, p1, p2, g>,     \
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
-    hipLaunchKernelGGL((fit_adjoint_kernel<p, g>), fgrid, fblock, shm, s, f);                           \
+    hipLaunchKernelGGL((fit_adjoint_kernel<p0, p1, p2, g>), fgrid, fblock, shm, s, f);                  \
   } while (0)
-#define FA_CASE(p)                                                                                      \
-  case p:                                                                                               \
-    if (gj == 3) FA_LAUNCH(p, 3); else FA_LAUNCH(p, 1);                                                 \
+#define FA_CASE(p0, p1, p2)                                                                             \
+  case IGAMT_DEGREE_KEY(p0, p1, p2):                                                                    \
+    if (gj == 3) FA_LAUNCH(p0, p1, p2, 3); else FA_LAUNCH(p0, p1, p2, 1);                               \
     break;
-    FA_CASE(1)
-    FA_CASE(2)
-    FA_CASE(3)
-    FA_CASE(4)
-    FA_CASE(5)
-    FA_CASE(6)
+    IGAMT_FOR_MACRO_DEGREES(FA_CASE)
 #undef FA_CASE
 #undef FA_LAUNCH
-    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+    default: set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)"); return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();
   // (4) reductions

@@ -169,35 +169,66 @@ __device__ inline double f16_scale_for(double bound) {
   return ldexp(1.0, 14 - e);  // bound * scale < 2^14
 }
 
+constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+// Values and first derivatives of the B-splines of degree PD[k] non-zero on span `span` of direction
+// k (a run-time direction, compile-time degrees), padded with zeros to PMX + 1 entries.
+template <int P0, int P1, int P2>
+__device__ inline void bspline_ders_dir(int k, const double *__restrict__ U, int span, double x,
+                                        double (&N)[max3(P0, P1, P2) + 1], double (&dN)[max3(P0, P1, P2) + 1]) {
+  constexpr int PMX = max3(P0, P1, P2);
+#pragma unroll
+  for (int r = 0; r <= PMX; ++r) N[r] = dN[r] = 0.0;
+  if (k == 0) {
+    double a[P0 + 1], b[P0 + 1];
+    bspline_ders<P0>(U, span, x, a, b);
+#pragma unroll
+    for (int r = 0; r <= P0; ++r) { N[r] = a[r]; dN[r] = b[r]; }
+  } else if (k == 1) {
+    double a[P1 + 1], b[P1 + 1];
+    bspline_ders<P1>(U, span, x, a, b);
+#pragma unroll
+    for (int r = 0; r <= P1; ++r) { N[r] = a[r]; dN[r] = b[r]; }
+  } else {
+    double a[P2 + 1], b[P2 + 1];
+    bspline_ders<P2>(U, span, x, a, b);
+#pragma unroll
+    for (int r = 0; r <= P2; ++r) { N[r] = a[r]; dN[r] = b[r]; }
+  }
+}
+
 // Jacobian of the trivariate spline map with control points ctrl ([n2][n1][n0][3], x fastest) at
-// parameter x (degree P in every direction); also returns the span and the 1-D basis values and
-// derivatives used.  w: NULL for a B-spline map, else the NURBS weights ([n2][n1][n0]); the map is
-// then A / W with A = sum w_i N_i P_i, W = sum w_i N_i, and dM/dx_k = (dA/dx_k - M dW/dx_k) / W.
-// ROLL_X keeps the innermost (x) control-point loop rolled too: fewer registers (more waves per SIMD)
-// for kernels whose occupancy the Jacobian limits, the same sums in the same order.
-template <int P, bool ROLL_X = false>
-__device__ inline void spline_jacobian(const double *const *knots, const int *n, const double *__restrict__ ctrl,
-                                       const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
-                                       int (&span)[3], double (&N)[3][P + 1], double (&dN)[3][P + 1]) {
+// parameter x, degree P0, P1, P2 in the three directions; also returns the spans and the 1-D basis
+// values and derivatives used (N[k][r], r <= Pk; zero above).  w: NULL for a B-spline map, else the
+// NURBS weights ([n2][n1][n0]); the map is then A / W with A = sum w_i N_i P_i, W = sum w_i N_i, and
+// dM/dx_k = (dA/dx_k - M dW/dx_k) / W.  ROLL_X keeps the innermost (x) control-point loop rolled
+// too: fewer registers (more waves per SIMD) for kernels whose occupancy the Jacobian limits, the
+// same sums in the same order.
+template <int P0, int P1, int P2, bool ROLL_X = false>
+__device__ inline void spline_jacobian3(const double *const *knots, const int *n, const double *__restrict__ ctrl,
+                                        const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
+                                        int (&span)[3], double (&N)[3][max3(P0, P1, P2) + 1],
+                                        double (&dN)[3][max3(P0, P1, P2) + 1]) {
+  constexpr int PD[3] = {P0, P1, P2};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    span[k] = find_span(knots[k], n[k], P, x[k]);
-    bspline_ders<P>(knots[k], span[k], x[k], N[k], dN[k]);
+    span[k] = find_span(knots[k], n[k], PD[k], x[k]);
+    bspline_ders_dir<P0, P1, P2>(k, knots[k], span[k], x[k], N[k], dN[k]);
   }
   double A[3] = {0.0, 0.0, 0.0}, W = 0.0, dW[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) J[c][0] = J[c][1] = J[c][2] = 0.0;
 #pragma unroll 1
-  for (int rz = 0; rz <= P; ++rz) {
-    const int iz = span[2] - P + rz;
+  for (int rz = 0; rz <= P2; ++rz) {
+    const int iz = span[2] - P2 + rz;
 #pragma unroll 1
-    for (int ry = 0; ry <= P; ++ry) {
-      const int iy = span[1] - P + ry;
+    for (int ry = 0; ry <= P1; ++ry) {
+      const int iy = span[1] - P1 + ry;
       const double wyz = N[1][ry] * N[2][rz];
       const double dy = dN[1][ry] * N[2][rz];
       const double dz = N[1][ry] * dN[2][rz];
       auto point = [&](int rx) {
-        const int ix = span[0] - P + rx;
+        const int ix = span[0] - P0 + rx;
         const int64_t id = ix + (int64_t)n[0] * (iy + (int64_t)n[1] * iz);
         const double *c = ctrl + 3 * id;
         const double wi = w ? w[id] : 1.0;
@@ -217,10 +248,10 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
       };
       if constexpr (ROLL_X) {
 #pragma unroll 1
-        for (int rx = 0; rx <= P; ++rx) point(rx);
+        for (int rx = 0; rx <= P0; ++rx) point(rx);
       } else {
 #pragma unroll
-        for (int rx = 0; rx <= P; ++rx) point(rx);
+        for (int rx = 0; rx <= P0; ++rx) point(rx);
       }
     }
   }
@@ -235,19 +266,27 @@ __device__ inline void spline_jacobian(const double *const *knots, const int *n,
   }
 }
 
+// The same with one degree P in every direction.
+template <int P, bool ROLL_X = false>
+__device__ inline void spline_jacobian(const double *const *knots, const int *n, const double *__restrict__ ctrl,
+                                       const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
+                                       int (&span)[3], double (&N)[3][P + 1], double (&dN)[3][P + 1]) {
+  spline_jacobian3<P, P, P, ROLL_X>(knots, n, ctrl, w, x, J, span, N, dN);
+}
+
 // NURBS control-point derivatives at one sample of a tensor grid: from the 1-D B-spline values NB
 // and derivatives DB at the sample's abscissae si (spans SP), W = sum w N and d_n W; then with
 // G[c][n] the sample's weights of d_n R_i (R_i = w_i N_i / W, d_n R_i = w_i (d_n N_i - N_i d_n W / W) / W):
-// out[0] = 1 / W, out[1 + c] = sum_n G[c][n] d_n W / W^2.
-template <int PM, int MF, int MD>
-__device__ inline void rational_terms(const double *__restrict__ wts, const int *nM, const int (&SP)[3][MF],
-                                      const double (&NB)[3][MF][MD], const double (&DB)[3][MF][MD],
-                                      const int (&si)[3], const double *G, double *out) {
+// out[0] = 1 / W, out[1 + c] = sum_n G[c][n] d_n W / W^2.  Degrees P0, P1, P2 per direction.
+template <int P0, int P1, int P2, int MF, int MD>
+__device__ inline void rational_terms3(const double *__restrict__ wts, const int *nM, const int (&SP)[3][MF],
+                                       const double (&NB)[3][MF][MD], const double (&DB)[3][MF][MD],
+                                       const int (&si)[3], const double *G, double *out) {
   double W = 0.0, dW[3] = {0.0, 0.0, 0.0};
-  for (int rz = 0; rz <= PM; ++rz)
-    for (int ry = 0; ry <= PM; ++ry)
-      for (int rx = 0; rx <= PM; ++rx) {
-        const int ix = SP[0][si[0]] - PM + rx, iy = SP[1][si[1]] - PM + ry, iz = SP[2][si[2]] - PM + rz;
+  for (int rz = 0; rz <= P2; ++rz)
+    for (int ry = 0; ry <= P1; ++ry)
+      for (int rx = 0; rx <= P0; ++rx) {
+        const int ix = SP[0][si[0]] - P0 + rx, iy = SP[1][si[1]] - P1 + ry, iz = SP[2][si[2]] - P2 + rz;
         const double wi = wts[ix + (int64_t)nM[0] * (iy + (int64_t)nM[1] * iz)];
         const double nx = NB[0][si[0]][rx], ny = NB[1][si[1]][ry], nz = NB[2][si[2]][rz];
         W += wi * nx * ny * nz;
@@ -279,6 +318,16 @@ __host__ __device__ inline int64_t split_coef_index(int64_t col, int64_t k, int6
   if (!tiled) return col * Kp + k;
   return ((col >> 4) * (Kp >> 5) + (k >> 5)) * 512 + ((((k & 31) >> 3) << 4) + (col & 15)) * 8 + (k & 7);
 }
+
+// Macro-map degrees (per direction) the kernels are instantiated for: every isotropic degree 1..6,
+// and every combination of degrees 1..3 that differs between directions.  X(p0, p1, p2) per entry;
+// IGAMT_DEGREE_KEY gives the switch key of a degree triple.
+#define IGAMT_DEGREE_KEY(a, b, c) ((a) * 64 + (b) * 8 + (c))
+#define IGAMT_FOR_MACRO_DEGREES(X) \
+  X(1, 1, 1) X(2, 2, 2) X(3, 3, 3) X(4, 4, 4) X(5, 5, 5) X(6, 6, 6) \
+  X(1, 1, 2) X(1, 1, 3) X(1, 2, 1) X(1, 2, 2) X(1, 2, 3) X(1, 3, 1) X(1, 3, 2) X(1, 3, 3) \
+  X(2, 1, 1) X(2, 1, 2) X(2, 1, 3) X(2, 2, 1) X(2, 2, 3) X(2, 3, 1) X(2, 3, 2) X(2, 3, 3) \
+  X(3, 1, 1) X(3, 1, 2) X(3, 1, 3) X(3, 2, 1) X(3, 2, 2) X(3, 2, 3) X(3, 3, 1) X(3, 3, 2)
 
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 

@@ -44,13 +44,14 @@ __device__ inline double field_component(const double *FD, int i, int j, int aa,
   return FD[9] * (lam * Fi[aa] * Fj[bb] + (aa == bb ? mu * fij : 0.0) + mu * Fi[bb] * Fj[aa]);
 }
 
-template <int PM>
+template <int P0, int P1, int P2>
 __device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const double (&hx)[3], const double (&x)[3],
                                 double *FD, int64_t t) {
+  constexpr int PMX = max3(P0, P1, P2);
   const double xh[3] = {ax[0] + hx[0] * x[0], ax[1] + hx[1] * x[1], ax[2] + hx[2] * x[2]};
-  double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+  double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
   int span[3];
-  spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+  spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -65,7 +66,7 @@ __device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const
   FD[9] = D;
 }
 
-template <int PM>
+template <int P0, int P1, int P2>
 __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x, nf = a.nf, ns1 = a.n_s, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
@@ -95,11 +96,11 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
   }
   for (int s = tid; s < nfit; s += 256) {
     const double x[3] = {a.fx[s % nf], a.fx[(s / nf) % nf], a.fx[s / (nf * nf)]};
-    point_FD<PM>(a, ax, hx, x, FDf + s * 10, t);
+    point_FD<P0, P1, P2>(a, ax, hx, x, FDf + s * 10, t);
   }
   for (int k = tid; k < nsmp; k += 256) {
     const double x[3] = {a.sx[k % ns1], a.sx[(k / ns1) % ns1], a.sx[k / (ns1 * ns1)]};
-    point_FD<PM>(a, ax, hx, x, FDs + k * 10, t);
+    point_FD<P0, P1, P2>(a, ax, hx, x, FDs + k * 10, t);
     err2[k] = 0.0;
     nrm2[k] = 0.0;
   }
@@ -242,22 +243,17 @@ static igamt_status eproj_run(igamt_plan *P, double E, double nu, const int (&q)
   const int nfit = nf * nf * nf, nsmp = n_s * n_s * n_s;
   const size_t shm = (size_t)(10 * nfit + 10 * nsmp + 2 * nsmp + 2 * 9 * std::max(nfit, nsmp)) * sizeof(double);
   const dim3 grid((unsigned)P->n_tiles), block(256);
-  switch (P->pM[0]) {
-#define EP_CASE(p)                                                                                        \
-  case p:                                                                                                 \
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define EP_CASE(p0, p1, p2)                                                                               \
+  case IGAMT_DEGREE_KEY(p0, p1, p2):                                                                      \
     if (shm > 65536)                                                                                      \
-      IGAMT_HIP(hipFuncSetAttribute((const void *)eproj_kernel<p>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                    (int)shm));                                                           \
-    hipLaunchKernelGGL(eproj_kernel<p>, grid, block, shm, s, a);                                          \
+      IGAMT_HIP(hipFuncSetAttribute((const void *)eproj_kernel<p0, p1, p2>,                               \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));               \
+    hipLaunchKernelGGL((eproj_kernel<p0, p1, p2>), grid, block, shm, s, a);                               \
     break;
-    EP_CASE(1)
-    EP_CASE(2)
-    EP_CASE(3)
-    EP_CASE(4)
-    EP_CASE(5)
-    EP_CASE(6)
+    IGAMT_FOR_MACRO_DEGREES(EP_CASE)
 #undef EP_CASE
-    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+    default: set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)"); return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();
   hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, a.tile_e, P->n_tiles, d_res);
@@ -273,10 +269,6 @@ static igamt_status eproj_checks(igamt_plan *P, double E, double nu, int n_s) {
     return IGAMT_EINVAL;
   }
   if (n_s < 2 || n_s > kMaxSample) { set_error("samples per direction must be in [2, 8]"); return IGAMT_EINVAL; }
-  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
-    set_error("macro maps with different degrees per direction are not supported");
-    return IGAMT_EUNSUPPORTED;
-  }
   return ensure_device(P);
 }
 
@@ -307,7 +299,7 @@ extern "C" igamt_status igamt_select_q(igamt_plan *P, double E, double nu, doubl
   if (!(tol >= 0.0) || !std::isfinite(tol)) { set_error("tolerance must be finite and non-negative"); return IGAMT_EINVAL; }
   igamt_status st = eproj_checks(P, E, nu, n_sample);
   if (st) return st;
-  const int q0 = P->pM[0];
+  const int q0 = std::max(P->pM[0], std::max(P->pM[1], P->pM[2]));   // the macro degree (largest direction)
   if (q_max < q0 || q_max > kMaxQ) { set_error("q_max must be in [macro degree, 6]"); return IGAMT_EINVAL; }
   double e = 0.0;
   for (int q = q0; q <= q_max; ++q) {
@@ -330,7 +322,10 @@ extern "C" igamt_status igamt_select_q_aniso(igamt_plan *P, double E, double nu,
   if (!(tol >= 0.0) || !std::isfinite(tol)) { set_error("tolerance must be finite and non-negative"); return IGAMT_EINVAL; }
   igamt_status st = eproj_checks(P, E, nu, n_sample);
   if (st) return st;
-  if (q_max < P->pM[0] || q_max > kMaxQ) { set_error("q_max must be in [macro degree, 6]"); return IGAMT_EINVAL; }
+  if (q_max < std::max(P->pM[0], std::max(P->pM[1], P->pM[2])) || q_max > kMaxQ) {
+    set_error("q_max must be in [largest macro degree, 6]");
+    return IGAMT_EINVAL;
+  }
   hipStream_t s = (hipStream_t)stream;
   int q[3] = {P->pM[0], P->pM[1], P->pM[2]};
   double e = 0.0;

@@ -55,8 +55,9 @@ __device__ inline void store_coef(const FitArgs &a, int64_t idx, double v, doubl
   }
 }
 
-template <int PM>
+template <int P0, int P1, int P2>
 __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
+  constexpr int PMX = max3(P0, P1, P2);
   extern __shared__ double smem[];
   const int nf = a.nf, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
   const int ns = nf * nf * nf;
@@ -87,11 +88,11 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   // Jacobians at the samples
   for (int s = tid; s < ns; s += 64) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-    double N[3][PM + 1], dN[3][PM + 1];
+    double N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian3<P0, P1, P2>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -226,27 +227,17 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.t0 = t0;
   const dim3 grid((unsigned)(t1 - t0)), block(64);
   hipStream_t s = (hipStream_t)stream;
-  // all macro directions share one degree in the device evaluator
-  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
-    set_error("macro maps with different degrees per direction are not supported");
-    return IGAMT_EUNSUPPORTED;
-  }
-  switch (P->pM[0]) {
-#define FIT_CASE(p)                                                                                   \
-  case p:                                                                                             \
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p>,                       \
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define FIT_CASE(p0, p1, p2)                                                                          \
+  case IGAMT_DEGREE_KEY(p0, p1, p2):                                                                  \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p0, p1, p2>,              \
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
-    hipLaunchKernelGGL(fit_kernel<p>, grid, block, shm, s, a);                                        \
+    hipLaunchKernelGGL((fit_kernel<p0, p1, p2>), grid, block, shm, s, a);                             \
     break;
-    FIT_CASE(1)
-    FIT_CASE(2)
-    FIT_CASE(3)
-    FIT_CASE(4)
-    FIT_CASE(5)
-    FIT_CASE(6)
+    IGAMT_FOR_MACRO_DEGREES(FIT_CASE)
 #undef FIT_CASE
     default:
-      set_error("unsupported macro degree");
+      set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)");
       return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();

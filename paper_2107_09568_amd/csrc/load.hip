@@ -127,8 +127,10 @@ struct LoadFitArgs {
   int32_t *flag;
 };
 
-template <int PM>
+template <int P0, int P1, int P2>
 __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
+  constexpr int PMX = max3(P0, P1, P2);
+  constexpr int PD[3] = {P0, P1, P2};
   __shared__ double vals[kMaxFit * kMaxFit * kMaxFit];   // |det J| at the body samples / face areas
   const int64_t t = blockIdx.x;
   const int tid = threadIdx.x;
@@ -145,9 +147,9 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
   for (int s = tid; s < ns; s += 64) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
-    double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+    double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -181,9 +183,9 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
         xh[d] = ax[d] + hx[d] * side;
         xh[u] = ax[u] + hx[u] * a.fx[su];
         xh[v] = ax[v] + hx[v] * a.fx[sv];
-        double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+        double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
         int span[3];
-        spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+        spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
         const double gu[3] = {J[0][u] * hx[u], J[1][u] * hx[u], J[2][u] * hx[u]};
         const double gv[3] = {J[0][v] * hx[v], J[1][v] * hx[v], J[2][v] * hx[v]};
         const double n0 = gu[1] * gv[2] - gu[2] * gv[1], n1 = gu[2] * gv[0] - gu[0] * gv[2],
@@ -294,8 +296,10 @@ __host__ __device__ inline int64_t load_adj_lds_doubles(int nTt, int npi, int nf
          kLoadAdjThreads;
 }
 
-template <int PM>
+template <int P0, int P1, int P2>
 __global__ __launch_bounds__(kLoadAdjThreads) void load_adjoint_kernel(LoadAdjArgs a) {
+  constexpr int PMX = max3(P0, P1, P2);
+  constexpr int PD[3] = {P0, P1, P2};
   extern __shared__ double smem[];
   __shared__ double NB[3][kAbsc][kMaxDegree + 1], DB[3][kAbsc][kMaxDegree + 1];
   __shared__ int SP[3][kAbsc];
@@ -327,11 +331,11 @@ __global__ __launch_bounds__(kLoadAdjThreads) void load_adjoint_kernel(LoadAdjAr
     const int k = e / (nf + 2), s = e % (nf + 2);
     const double xi = s < nf ? a.fx[s] : (double)(s - nf);
     const double x = ax[k] + hx[k] * xi;
-    const int sp = find_span(a.knots[k], a.nM[k], PM, x);
-    double N[PM + 1], dN[PM + 1];
-    bspline_ders<PM>(a.knots[k], sp, x, N, dN);
+    const int sp = find_span(a.knots[k], a.nM[k], PD[k], x);
+    double N[PMX + 1], dN[PMX + 1];
+    bspline_ders_dir<P0, P1, P2>(k, a.knots[k], sp, x, N, dN);
     SP[k][s] = sp;
-    for (int r = 0; r <= PM; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
+    for (int r = 0; r <= PMX; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
   }
   // the loads paired with the tile's displacement
   for (int A = tid; A < nTt; A += kLoadAdjThreads) {
@@ -363,9 +367,9 @@ __global__ __launch_bounds__(kLoadAdjThreads) void load_adjoint_kernel(LoadAdjAr
         for (int c1 = 0; c1 < q1[0]; ++c1, ++C)
           gbar += Pk[0][c1 * nf + si[0]] * Pk[1][c2 * nf + si[1]] * Pk[2][c3 * nf + si[2]] * Y[C];
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
-    double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+    double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -408,9 +412,9 @@ __global__ __launch_bounds__(kLoadAdjThreads) void load_adjoint_kernel(LoadAdjAr
       xh[d] = ax[d] + hx[d] * side;
       xh[u] = ax[u] + hx[u] * a.fx[su];
       xh[v] = ax[v] + hx[v] * a.fx[sv];
-      double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+      double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
       int span[3];
-      spline_jacobian<PM, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+      spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
       const double gu[3] = {J[0][u] * hx[u], J[1][u] * hx[u], J[2][u] * hx[u]};
       const double gv[3] = {J[0][v] * hx[v], J[1][v] * hx[v], J[2][v] * hx[v]};
       const double n[3] = {gu[1] * gv[2] - gu[2] * gv[1], gu[2] * gv[0] - gu[0] * gv[2], gu[0] * gv[1] - gu[1] * gv[0]};
@@ -453,7 +457,7 @@ __global__ __launch_bounds__(kLoadAdjThreads) void load_adjoint_kernel(LoadAdjAr
       if (s >= ns && !touched((s - ns) / (nf * nf))) continue;
       int si[3];
       sample_index(s, si);
-      rational_terms<PM>(a.wts, a.nM, SP, NB, DB, si, JH + s * 9, WQ + s * 4);
+      rational_terms3<P0, P1, P2>(a.wts, a.nM, SP, NB, DB, si, JH + s * 9, WQ + s * 4);
     }
   }
   // per-direction factor tables: XV[k][s][l] = N_r(x_s), XD = N_r'(x_s), r the local function l's
@@ -462,8 +466,8 @@ __global__ __launch_bounds__(kLoadAdjThreads) void load_adjoint_kernel(LoadAdjAr
   const int lo[3] = {a.ctrl_lo[0][tt[0]], a.ctrl_lo[1][tt[1]], a.ctrl_lo[2][tt[2]]};
   for (int e = tid; e < 3 * (nf + 2) * Lm; e += kLoadAdjThreads) {
     const int k = e / ((nf + 2) * Lm), rem = e - k * (nf + 2) * Lm, sk = rem / Lm, l = rem - sk * Lm;
-    const int r = lo[k] + l - (SP[k][sk] - PM);
-    const bool on = r >= 0 && r <= PM;
+    const int r = lo[k] + l - (SP[k][sk] - PD[k]);
+    const bool on = r >= 0 && r <= PD[k];
     const int rc = on ? r : 0;
     XV[e] = on ? NB[k][sk][rc] : 0.0;
     XD[e] = on ? DB[k][sk][rc] : 0.0;
@@ -521,19 +525,13 @@ static igamt_status load_fit_launch(igamt_plan *P, const double *body, const dou
   a.npi = P->npi;
   a.coef = d_coef;
   a.flag = P->dev.flag;
-  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
-    set_error("macro maps with different degrees per direction are not supported");
-    return IGAMT_EUNSUPPORTED;
-  }
   const dim3 grid((unsigned)P->n_tiles), block(64);
-  switch (P->pM[0]) {
-    case 1: hipLaunchKernelGGL(load_fit_kernel<1>, grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(load_fit_kernel<2>, grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(load_fit_kernel<3>, grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(load_fit_kernel<4>, grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL(load_fit_kernel<5>, grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL(load_fit_kernel<6>, grid, block, 0, s, a); break;
-    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define LF_CASE(p0, p1, p2)                                                                               \
+  case IGAMT_DEGREE_KEY(p0, p1, p2): hipLaunchKernelGGL((load_fit_kernel<p0, p1, p2>), grid, block, 0, s, a); break;
+    IGAMT_FOR_MACRO_DEGREES(LF_CASE)
+#undef LF_CASE
+    default: set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)"); return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
@@ -663,10 +661,6 @@ extern "C" igamt_status igamt_uf_grad(igamt_plan *P, const double *body, const d
   igamt_status st = ensure_device(P);
   if (st) return st;
   if (!P->load_table_ready) { set_error("load table not built"); return IGAMT_ESTATE; }
-  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
-    set_error("macro maps with different degrees per direction are not supported");
-    return IGAMT_EUNSUPPORTED;
-  }
   hipStream_t s = (hipStream_t)stream;
   int64_t off[3];
   uf_grad_ws_layout(P, off);
@@ -702,21 +696,16 @@ extern "C" igamt_status igamt_uf_grad(igamt_plan *P, const double *body, const d
   const size_t shm = (size_t)load_adj_lds_doubles((int)P->nTt, P->npi, P->n_fit, a.Lm) * sizeof(double);
   if (shm > 150 * 1024) { set_error("tile control points or fit samples too many for the load adjoint"); return IGAMT_EUNSUPPORTED; }
   const dim3 grid((unsigned)P->n_tiles), block(kLoadAdjThreads);
-  switch (P->pM[0]) {
-#define LA_CASE(p)                                                                                      \
-  case p:                                                                                               \
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)load_adjoint_kernel<p>,                \
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define LA_CASE(p0, p1, p2)                                                                             \
+  case IGAMT_DEGREE_KEY(p0, p1, p2):                                                                    \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)load_adjoint_kernel<p0, p1, p2>,       \
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
-    hipLaunchKernelGGL(load_adjoint_kernel<p>, grid, block, shm, s, a);                                 \
+    hipLaunchKernelGGL((load_adjoint_kernel<p0, p1, p2>), grid, block, shm, s, a);                      \
     break;
-    LA_CASE(1)
-    LA_CASE(2)
-    LA_CASE(3)
-    LA_CASE(4)
-    LA_CASE(5)
-    LA_CASE(6)
+    IGAMT_FOR_MACRO_DEGREES(LA_CASE)
 #undef LA_CASE
-    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+    default: set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)"); return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();
   if ((st = launch_grad_reduce(P, (const double *)(ws + off[0]), d_grad, stream))) return st;

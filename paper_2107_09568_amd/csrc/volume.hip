@@ -87,8 +87,10 @@ struct VolumeTileArgs {
   int Lm;                   // max(Lc): row length of the 1-D factor tables
 };
 
-template <int PM>
+template <int P0, int P1, int P2>
 __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
+  constexpr int PMX = max3(P0, P1, P2);
+  constexpr int PD[3] = {P0, P1, P2};
   extern __shared__ double GS[];    // [ns][9]: g_s D_s (J^-1)[n][c] h_n at [3 c + n]; NURBS: then WQ [ns][4]
   __shared__ double NB[3][kMaxFit][kMaxDegree + 1], DB[3][kMaxFit][kMaxDegree + 1];
   __shared__ int SP[3][kMaxFit];
@@ -105,20 +107,20 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
     for (int e = tid; e < 3 * nf; e += 64) {
       const int k = e / nf, s = e % nf;
       const double x = ax[k] + hx[k] * a.fx[s];
-      const int sp = find_span(a.knots[k], a.nM[k], PM, x);
-      double N[PM + 1], dN[PM + 1];
-      bspline_ders<PM>(a.knots[k], sp, x, N, dN);
+      const int sp = find_span(a.knots[k], a.nM[k], PD[k], x);
+      double N[PMX + 1], dN[PMX + 1];
+      bspline_ders_dir<P0, P1, P2>(k, a.knots[k], sp, x, N, dN);
       SP[k][s] = sp;
-      for (int r = 0; r <= PM; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
+      for (int r = 0; r <= PMX; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
     }
   __syncthreads();   // the basis tables are read by the sample loop (NURBS) and the local gradients
   double vol = 0.0;
   for (int s = tid; s < ns; s += 64) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
-    double J[3][3], N[3][PM + 1], dN[3][PM + 1];
+    double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian<PM>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian3<P0, P1, P2>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int n = 0; n < 3; ++n) GS[s * 9 + 3 * c + n] = gs * cof[c][n] * hx[n];
-      if (a.wts) rational_terms<PM>(a.wts, a.nM, SP, NB, DB, si, GS + s * 9, WQ + s * 4);
+      if (a.wts) rational_terms3<P0, P1, P2>(a.wts, a.nM, SP, NB, DB, si, GS + s * 9, WQ + s * 4);
     }
   }
   red[tid] = vol;
@@ -164,8 +166,8 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
   double *XV = GS + ns * 13, *XD = XV + 3 * nf * Lm;   // [3][nf][Lm] each, after GS and WQ
   for (int e = tid; e < 3 * nf * Lm; e += 64) {
     const int k = e / (nf * Lm), rem = e - k * nf * Lm, sk = rem / Lm, l = rem - sk * Lm;
-    const int r = lo[k] + l - (SP[k][sk] - PM);
-    const bool on = r >= 0 && r <= PM;
+    const int r = lo[k] + l - (SP[k][sk] - PD[k]);
+    const bool on = r >= 0 && r <= PD[k];
     const int rc = on ? r : 0;
     XV[e] = on ? NB[k][sk][rc] : 0.0;
     XD[e] = on ? DB[k][sk][rc] : 0.0;
@@ -323,10 +325,6 @@ extern "C" igamt_status igamt_volume_workspace_bytes(const igamt_plan *P, int64_
 static igamt_status volume_run(igamt_plan *P, double *d_tile_volumes, double *d_volume, double *d_grad, void *d_workspace,
                                void *stream) {
   igamt_status st;
-  if (P->pM[0] != P->pM[1] || P->pM[0] != P->pM[2]) {
-    set_error("macro maps with different degrees per direction are not supported");
-    return IGAMT_EUNSUPPORTED;
-  }
   hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)d_workspace;
   double *tv = d_tile_volumes ? d_tile_volumes : (double *)ws;
@@ -354,14 +352,12 @@ static igamt_status volume_run(igamt_plan *P, double *d_tile_volumes, double *d_
   const size_t shm = d_grad ? (size_t)(ns * (9 + 4) + 6 * (int64_t)P->n_fit * a.Lm) * sizeof(double) : 0;
   if (shm > 60 * 1024) { set_error("tile samples or macro control points per tile too many for the volume gradient"); return IGAMT_EUNSUPPORTED; }
   const dim3 grid((unsigned)P->n_tiles), block(64);
-  switch (P->pM[0]) {
-    case 1: hipLaunchKernelGGL(volume_tile_kernel<1>, grid, block, shm, s, a); break;
-    case 2: hipLaunchKernelGGL(volume_tile_kernel<2>, grid, block, shm, s, a); break;
-    case 3: hipLaunchKernelGGL(volume_tile_kernel<3>, grid, block, shm, s, a); break;
-    case 4: hipLaunchKernelGGL(volume_tile_kernel<4>, grid, block, shm, s, a); break;
-    case 5: hipLaunchKernelGGL(volume_tile_kernel<5>, grid, block, shm, s, a); break;
-    case 6: hipLaunchKernelGGL(volume_tile_kernel<6>, grid, block, shm, s, a); break;
-    default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define VOL_CASE(p0, p1, p2)                                                                              \
+  case IGAMT_DEGREE_KEY(p0, p1, p2): hipLaunchKernelGGL((volume_tile_kernel<p0, p1, p2>), grid, block, shm, s, a); break;
+    IGAMT_FOR_MACRO_DEGREES(VOL_CASE)
+#undef VOL_CASE
+    default: set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)"); return IGAMT_EUNSUPPORTED;
   }
   IGAMT_LAUNCH_CHECK();
   if ((st = launch_sum(tv, P->n_tiles, d_volume, stream))) return st;

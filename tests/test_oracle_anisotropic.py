@@ -153,3 +153,50 @@ def test_anisotropic_compliance_gradient_against_differences():
             c[idx] += sgn * eps
             vals.append(adjoint.uKu(dataclasses.replace(w, macro=dataclasses.replace(w.macro, ctrl=c)), T, pairs, u))
         assert g[idx] == pytest.approx((vals[0] - vals[1]) / (2 * eps), rel=1e-6)
+
+
+# ---- macro maps with a different degree per direction (the twisted square of Section 3.3: a NURBS
+#      of degrees (1, 1, 2)) -------------------------------------------------------------------------
+def test_affine_macro_map_with_per_direction_degrees_is_exact():
+    """An affine map written as a B-spline of degrees (1, 2, 3): the macro field is constant on every
+    tile, so K^pi equals the Gauss-quadrature matrix of the composed map (eq. (62) = 0)."""
+    A = np.array([[1.1, 0.15, -0.2], [0.05, 0.9, 0.1], [0.1, -0.05, 1.3]])
+    macro = W.affine_macro((1, 2, 3), (2, 1, 2), A, np.array([0.2, 0.1, -0.3]))
+    w = W.Workload("affine123", macro, W.make("cfg1").tile, (2, 1, 2), 0, 1, 2, 3)
+    pairs = tables.pair_set(w.tile)
+    T = tables.stiffness_table(w.tile, w.q, w.n_gauss, pairs)
+    blocks = assembly.tile_blocks(T, projection.all_coefficients(w))
+    for t in range(w.n_tiles):
+        ref = standard.tile_block_standard(w, t, pairs)
+        assert np.linalg.norm(blocks[t] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_nurbs_twisted_square_is_an_exact_twist():
+    """Every section point keeps its distance to the axis, the section turns by 45 degrees half way
+    and by 90 degrees at the end, and the volume (eq. (14) by full quadrature) is the length."""
+    from oracle import geometry, volume
+    w = W.make("twisted_square_nurbs")
+    m = w.macro
+    assert tuple(m.degree) == (1, 1, 2)
+    t = np.linspace(0.0, 1.0, 9)
+    X, J = geometry.eval_volume_grid(m.degree, m.knots, m.ctrl, np.array([0.0, 1.0]), np.array([0.0, 1.0]), t,
+                                     weights=m.weights)
+    r = np.linalg.norm(X[..., :2], axis=-1)
+    np.testing.assert_allclose(r, np.sqrt(0.5), rtol=0, atol=1e-15)
+    ang = np.unwrap(np.arctan2(X[:, 0, 0, 1], X[:, 0, 0, 0]) - np.arctan2(-0.5, -0.5))
+    assert ang[0] == pytest.approx(0.0, abs=1e-15)
+    assert ang[4] == pytest.approx(np.pi / 4, abs=1e-14)
+    assert ang[-1] == pytest.approx(np.pi / 2, abs=1e-14)
+    assert np.all(np.diff(ang) > 0)
+    assert np.linalg.det(J).min() > 0
+    assert volume.volume_standard(w, 6) == pytest.approx(3.0, rel=1e-13)
+
+
+def test_twisted_square_nurbs_degrees_start_at_the_macro_degrees():
+    """Eq. (65) on the (1, 1, 2) NURBS twist: the search starts at the macro map's own degrees and
+    raises the axis direction most, the section directions stay lower."""
+    w = W.make("twisted_square_nurbs")
+    q, e = adaptive.select_q_aniso(w, 1e-3)
+    assert e <= 1e-3
+    assert q[2] > max(q[0], q[1]) >= 1
+    assert adaptive.eproj(w, (1, 1, 2)) > 1e-3

@@ -25,7 +25,7 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "Spline3D", "Workload", "open_knots", "greville", "make", "CONFIGS", "nurbs_quarter_torus",
+    "Spline3D", "Workload", "open_knots", "greville", "make", "CONFIGS", "nurbs_quarter_torus", "nurbs_twisted_square",
     "tile_family", "family_params", "random_displacement",
 ]
 
@@ -48,7 +48,8 @@ class Spline3D:
         return (self.ctrl.shape[2], self.ctrl.shape[1], self.ctrl.shape[0])
 
     def copy(self) -> "Spline3D":
-        return Spline3D(tuple(self.degree), tuple(k.copy() for k in self.knots), self.ctrl.copy())
+        return Spline3D(tuple(self.degree), tuple(k.copy() for k in self.knots), self.ctrl.copy(),
+                        None if self.weights is None else self.weights.copy())
 
 
 @dataclass
@@ -172,6 +173,37 @@ def nurbs_quarter_torus(R: float = 2.0, r1: float = 0.5, r2: float = 1.0) -> Spl
     return Spline3D((2, 2, 2), knots, ctrl, wts)
 
 
+def nurbs_twisted_square(length: float = 3.0) -> Spline3D:
+    """A unit square section twisted by a quarter turn along an axis of the given length, exact as a
+    NURBS of degrees (1, 1, 2) with one element: bilinear across the section, and along the axis the
+    rational quadratic of a quarter circle (each section point travels on its own circular arc about
+    the axis: control layers at 0, 45 and 90 degrees, the middle one scaled by 1 / cos 45 degrees,
+    weights 1, cos 45 degrees, 1).  The twist keeps every section's area, so the volume is the length."""
+    c = np.sqrt(0.5)
+    ang = [0.0, 0.25 * np.pi, 0.5 * np.pi]
+    scale = [1.0, 1.0 / c, 1.0]
+    wz = [1.0, c, 1.0]
+    ctrl = np.zeros((3, 2, 2, 3))
+    wts = np.zeros((3, 2, 2))
+    for k in range(3):
+        ca, sa = np.cos(ang[k]), np.sin(ang[k])
+        for j in range(2):
+            for i in range(2):
+                x, y = i - 0.5, j - 0.5
+                ctrl[k, j, i] = (scale[k] * (x * ca - y * sa), scale[k] * (x * sa + y * ca), 0.5 * length * k)
+                wts[k, j, i] = wz[k]
+    knots = (np.array([0.0, 0.0, 1.0, 1.0]), np.array([0.0, 0.0, 1.0, 1.0]), np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0]))
+    return Spline3D((1, 1, 2), knots, ctrl, wts)
+
+
+def _twisted_square_nurbs(seed: int, n_boxes: int = 3, length: float = 3.0) -> Workload:
+    rng = np.random.default_rng(seed)
+    macro = nurbs_twisted_square(length)
+    tile = identity_spline((2, 2, 2), (2, 2, 2))
+    _pull_interior(tile, rng, 0.2)
+    return Workload("twisted_square_nurbs", macro, tile, (1, 1, n_boxes), 1, 2, 3, 3, seed=seed)
+
+
 def _twist(u, v, w):
     # a square section 1 x 1 twisted by a quarter turn along a length-3 axis
     a = 0.5 * np.pi * w
@@ -276,11 +308,14 @@ def make(name: str, **kw) -> Workload:
     """Build a named workload.  Keyword arguments shrink the large ones for CPU-side tests:
     cfg3(n_el=...), cfg4(n_boxes=...), cfg5(n_el=...); nurbs_torus(n_boxes=...) is the exact NURBS
     quarter torus under uniform boxes; twisted_square is a square section twisted along its axis
-    (a macro field far smoother across the section than along the axis)."""
+    (a macro field far smoother across the section than along the axis), as a degree-2 B-spline;
+    twisted_square_nurbs(n_boxes=...) is the exact twist as a NURBS of degrees (1, 1, 2) under
+    1 x 1 x n_boxes uniform boxes."""
     seeds = {"cfg1": 1001, "cfg2": 1002, "cfg3": 1003, "cfg4": 1004, "cfg5": 1005, "nurbs_torus": 1006,
-             "twisted_square": 1007}
+             "twisted_square": 1007, "twisted_square_nurbs": 1008}
     fn = {"cfg1": _cfg1, "cfg2": _cfg2, "cfg3": _cfg3, "cfg4": _cfg4, "cfg5": _cfg5,
-          "nurbs_torus": _nurbs_torus, "twisted_square": _twisted_square}[name]
+          "nurbs_torus": _nurbs_torus, "twisted_square": _twisted_square,
+          "twisted_square_nurbs": _twisted_square_nurbs}[name]
     return fn(seeds[name], **kw)
 
 
