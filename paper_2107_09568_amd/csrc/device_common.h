@@ -324,7 +324,8 @@ __host__ __device__ inline int64_t split_coef_index(int64_t col, int64_t k, int6
 // IGAMT_DEGREE_KEY gives the switch key of a degree triple.
 #define IGAMT_DEGREE_KEY(a, b, c) ((a) * 64 + (b) * 8 + (c))
 #define IGAMT_FOR_MACRO_DEGREES(X) \
-  X(1, 1, 1) X(2, 2, 2) X(3, 3, 3) X(4, 4, 4) X(5, 5, 5) X(6, 6, 6) \
+  X(1, 1, 1) X(2, 2, 2) X(3, 3, 3) X(4, 4, 4) X(5, 5, 5) X(6, 6, 6) IGAMT_FOR_ANISO_MACRO_DEGREES(X)
+#define IGAMT_FOR_ANISO_MACRO_DEGREES(X) \
   X(1, 1, 2) X(1, 1, 3) X(1, 2, 1) X(1, 2, 2) X(1, 2, 3) X(1, 3, 1) X(1, 3, 2) X(1, 3, 3) \
   X(2, 1, 1) X(2, 1, 2) X(2, 1, 3) X(2, 2, 1) X(2, 2, 3) X(2, 3, 1) X(2, 3, 2) X(2, 3, 3) \
   X(3, 1, 1) X(3, 1, 2) X(3, 1, 3) X(3, 2, 1) X(3, 2, 2) X(3, 2, 3) X(3, 3, 1) X(3, 3, 2)

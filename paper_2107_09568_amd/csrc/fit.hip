@@ -35,16 +35,14 @@ struct FitArgs {
   int32_t *flag;
 };
 
-template <typename F>
-__device__ inline void store_coef(const FitArgs &a, int64_t idx, double v, double scale) {
+// coefficient (column col = 9 t + ab, k) of the stored planes in the contraction's precision
+__device__ inline void store_coef(const FitArgs &a, int Kp, int64_t col, int k, double v, double scale) {
   if (a.prec == IGAMT_F64) {
-    ((double *)a.out)[idx] = v;
+    ((double *)a.out)[col * Kp + k] = v;
   } else if (a.prec == IGAMT_F32) {
-    ((float *)a.out)[idx] = (float)v;
+    ((float *)a.out)[col * Kp + k] = (float)v;
   } else {
-    // idx = col Kp + k in the column-major numbering; the planes may be tiled
-    const int64_t col = idx / a.Kp;
-    const int64_t pos = split_coef_index(col, idx - col * a.Kp, a.Kp, a.tiled);
+    const int64_t pos = split_coef_index(col, k, Kp, a.tiled);   // the split planes may be tiled
     uint16_t hi, lo;
     if (a.prec == IGAMT_BF16X3)
       split_bf16(v, hi, lo);
@@ -55,11 +53,16 @@ __device__ inline void store_coef(const FitArgs &a, int64_t idx, double v, doubl
   }
 }
 
-template <int P0, int P1, int P2>
+// QC > 0: the projection degree is QC in every direction with QC + 1 fit nodes, known at compile
+// time (every index division of the passes by a constant); QC = 0: degrees and nodes from the
+// arguments.  Both compute the same sums in the same order.
+template <int P0, int P1, int P2, int QC>
 __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   constexpr int PMX = max3(P0, P1, P2);
   extern __shared__ double smem[];
-  const int nf = a.nf, q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
+  const int nf = QC ? QC + 1 : a.nf;
+  const int q1x = QC ? QC + 1 : a.q1[0], q1y = QC ? QC + 1 : a.q1[1], q1z = QC ? QC + 1 : a.q1[2];
+  const int Kp = QC ? (9 * (QC + 1) * (QC + 1) * (QC + 1) + kColPad - 1) / kColPad * kColPad : a.Kp;
   const int ns = nf * nf * nf;
   const int npi = q1x * q1y * q1z;
   double *FD = smem;              // [ns][10]
@@ -68,10 +71,9 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   __shared__ double Pm[3][(kMaxQ + 1) * kMaxFit];
   const int tid = threadIdx.x;
   const int64_t t = a.t0 + blockIdx.x;
-  const int64_t tbase = t * 9 * (int64_t)a.Kp;
 
   if (t >= a.n_tiles) {  // padding tile: zeros
-    for (int64_t e = tid; e < 9 * (int64_t)a.Kp; e += 64) store_coef<double>(a, tbase + e, 0.0, 1.0);
+    for (int e = tid; e < 9 * Kp; e += 64) store_coef(a, Kp, t * 9 + e / Kp, e % Kp, 0.0, 1.0);
     if (a.prec == IGAMT_F16X3 && tid < 9)
       ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = 1.0f;
     return;
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
     int span[3];
     const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3];
-    spline_jacobian3<P0, P1, P2>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+    spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -155,15 +157,15 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
       const int c1 = C % q1x, c2 = (C / q1x) % q1y, c3 = C / (q1x * q1y);
       double v = 0.0;
       for (int s3 = 0; s3 < nf; ++s3) v += Pm[2][c3 * nf + s3] * buf0[(((s3 * q1y + c2) * q1x) + c1) * 9 + ij];
-      store_coef<double>(a, tbase + (int64_t)ab * a.Kp + e, v, sc);
+      store_coef(a, Kp, t * 9 + ab, e, v, sc);
     }
     __syncthreads();
   }
   // zero the padded columns
   const int K = 9 * npi;
-  for (int e = tid; e < 9 * (a.Kp - K); e += 64) {
-    const int ab = e / (a.Kp - K), k = K + e % (a.Kp - K);
-    store_coef<double>(a, tbase + (int64_t)ab * a.Kp + k, 0.0, 1.0);
+  for (int e = tid; e < 9 * (Kp - K); e += 64) {
+    const int ab = e / (Kp - K), k = K + e % (Kp - K);
+    store_coef(a, Kp, t * 9 + ab, k, 0.0, 1.0);
   }
 }
 
@@ -227,15 +229,30 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.t0 = t0;
   const dim3 grid((unsigned)(t1 - t0)), block(64);
   hipStream_t s = (hipStream_t)stream;
-  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
-#define FIT_CASE(p0, p1, p2)                                                                          \
-  case IGAMT_DEGREE_KEY(p0, p1, p2):                                                                  \
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p0, p1, p2>,              \
+#define FIT_LAUNCH(p0, p1, p2, qc)                                                                    \
+  do {                                                                                                \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p0, p1, p2, qc>,          \
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
-    hipLaunchKernelGGL((fit_kernel<p0, p1, p2>), grid, block, shm, s, a);                             \
+    hipLaunchKernelGGL((fit_kernel<p0, p1, p2, qc>), grid, block, shm, s, a);                         \
+  } while (0)
+  // isotropic macro map and projection degree q <= 3 on q + 1 nodes: the compile-time shape
+  const int qc = (P->qd[0] == P->qd[1] && P->qd[0] == P->qd[2] && P->n_fit == P->qd[0] + 1 && P->qd[0] >= 1 &&
+                  P->qd[0] <= 3) ? P->qd[0] : 0;
+  switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
+#define FIT_ISO(p)                                                                                    \
+  case IGAMT_DEGREE_KEY(p, p, p):                                                                     \
+    if (qc == 1) FIT_LAUNCH(p, p, p, 1);                                                              \
+    else if (qc == 2) FIT_LAUNCH(p, p, p, 2);                                                         \
+    else if (qc == 3) FIT_LAUNCH(p, p, p, 3);                                                         \
+    else FIT_LAUNCH(p, p, p, 0);                                                                      \
     break;
-    IGAMT_FOR_MACRO_DEGREES(FIT_CASE)
+#define FIT_CASE(p0, p1, p2)                                                                          \
+  case IGAMT_DEGREE_KEY(p0, p1, p2): FIT_LAUNCH(p0, p1, p2, 0); break;
+    FIT_ISO(1) FIT_ISO(2) FIT_ISO(3) FIT_ISO(4) FIT_ISO(5) FIT_ISO(6)
+    IGAMT_FOR_ANISO_MACRO_DEGREES(FIT_CASE)
 #undef FIT_CASE
+#undef FIT_ISO
+#undef FIT_LAUNCH
     default:
       set_error("unsupported macro degrees (isotropic 1..6, or 1..3 per direction)");
       return IGAMT_EUNSUPPORTED;
