@@ -143,6 +143,10 @@ __device__ inline uint16_t f32_to_bf16_bits(float f) {
 __device__ inline float bf16_bits_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 __device__ inline uint16_t f32_to_f16_bits(float f) {
+  // an empty asm keeps the compiler from merging a preceding double -> float rounding into one
+  // double -> half rounding, which it expands into a long integer sequence; this way the two
+  // roundings stay as written, each one hardware conversion
+  asm("" : "+v"(f));
   _Float16 h = (_Float16)f;
   return *reinterpret_cast<uint16_t *>(&h);
 }
@@ -197,24 +201,11 @@ __device__ inline void bspline_ders_dir(int k, const double *__restrict__ U, int
   }
 }
 
-// Jacobian of the trivariate spline map with control points ctrl ([n2][n1][n0][3], x fastest) at
-// parameter x, degree P0, P1, P2 in the three directions; also returns the spans and the 1-D basis
-// values and derivatives used (N[k][r], r <= Pk; zero above).  w: NULL for a B-spline map, else the
-// NURBS weights ([n2][n1][n0]); the map is then A / W with A = sum w_i N_i P_i, W = sum w_i N_i, and
-// dM/dx_k = (dA/dx_k - M dW/dx_k) / W.  ROLL_X keeps the innermost (x) control-point loop rolled
-// too: fewer registers (more waves per SIMD) for kernels whose occupancy the Jacobian limits, the
-// same sums in the same order.
+// The tensor sum of spline_jacobian3 (below) from given spans and 1-D basis values and derivatives.
 template <int P0, int P1, int P2, bool ROLL_X = false>
-__device__ inline void spline_jacobian3(const double *const *knots, const int *n, const double *__restrict__ ctrl,
-                                        const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
-                                        int (&span)[3], double (&N)[3][max3(P0, P1, P2) + 1],
-                                        double (&dN)[3][max3(P0, P1, P2) + 1]) {
-  constexpr int PD[3] = {P0, P1, P2};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    span[k] = find_span(knots[k], n[k], PD[k], x[k]);
-    bspline_ders_dir<P0, P1, P2>(k, knots[k], span[k], x[k], N[k], dN[k]);
-  }
+__device__ inline void spline_jacobian_sum(const int *n, const double *__restrict__ ctrl, const double *__restrict__ w,
+                                           const int (&span)[3], const double (&N)[3][max3(P0, P1, P2) + 1],
+                                           const double (&dN)[3][max3(P0, P1, P2) + 1], double (&J)[3][3]) {
   double A[3] = {0.0, 0.0, 0.0}, W = 0.0, dW[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) J[c][0] = J[c][1] = J[c][2] = 0.0;
@@ -266,6 +257,27 @@ __device__ inline void spline_jacobian3(const double *const *knots, const int *n
   }
 }
 
+// Jacobian of the trivariate spline map with control points ctrl ([n2][n1][n0][3], x fastest) at
+// parameter x, degree P0, P1, P2 in the three directions; also returns the spans and the 1-D basis
+// values and derivatives used (N[k][r], r <= Pk; zero above).  w: NULL for a B-spline map, else the
+// NURBS weights ([n2][n1][n0]); the map is then A / W with A = sum w_i N_i P_i, W = sum w_i N_i, and
+// dM/dx_k = (dA/dx_k - M dW/dx_k) / W.  ROLL_X keeps the innermost (x) control-point loop rolled
+// too: fewer registers (more waves per SIMD) for kernels whose occupancy the Jacobian limits, the
+// same sums in the same order.
+template <int P0, int P1, int P2, bool ROLL_X = false>
+__device__ inline void spline_jacobian3(const double *const *knots, const int *n, const double *__restrict__ ctrl,
+                                        const double *__restrict__ w, const double (&x)[3], double (&J)[3][3],
+                                        int (&span)[3], double (&N)[3][max3(P0, P1, P2) + 1],
+                                        double (&dN)[3][max3(P0, P1, P2) + 1]) {
+  constexpr int PD[3] = {P0, P1, P2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    span[k] = find_span(knots[k], n[k], PD[k], x[k]);
+    bspline_ders_dir<P0, P1, P2>(k, knots[k], span[k], x[k], N[k], dN[k]);
+  }
+  spline_jacobian_sum<P0, P1, P2, ROLL_X>(n, ctrl, w, span, N, dN, J);
+}
+
 // The same with one degree P in every direction.
 template <int P, bool ROLL_X = false>
 __device__ inline void spline_jacobian(const double *const *knots, const int *n, const double *__restrict__ ctrl,
@@ -313,7 +325,7 @@ __device__ inline double local_weight(const double *__restrict__ w, const int *n
 // the 16 columns x 32 k of one MFMA fragment contiguous, lane (l16, kq) at (kq 16 + l16) 8, i.e.
 // element (col, k) at ((col / 16) (Kp / 32) + k / 32) 512 + ((k % 32) / 8 16 + col % 16) 8 + k % 8.
 // Other widths keep the column-major layout col Kp + k.
-__host__ __device__ inline bool split_tiled(int64_t Kp) { return Kp == 128 || Kp == 256; }
+__host__ __device__ constexpr bool split_tiled(int64_t Kp) { return Kp == 128 || Kp == 256; }
 __host__ __device__ inline int64_t split_coef_index(int64_t col, int64_t k, int64_t Kp, bool tiled) {
   if (!tiled) return col * Kp + k;
   return ((col >> 4) * (Kp >> 5) + (k >> 5)) * 512 + ((((k & 31) >> 3) << 4) + (col & 15)) * 8 + (k & 7);

@@ -5,11 +5,15 @@
 // F = J^-1 and D = det J in FP64.  The projection coefficients
 //   <A_ij,ab>_C = sum_s P[C, s] A_ij,ab(xi_s),  P = P1 (x) P1 (x) P1,
 // (eq. (42) with the 1-D operator of eq. (23)-(24)) are applied sum-factorised,
-// one direction at a time, for one component (a, b) of A at a time (its nine (i, j) blocks
-// side by side, so that each coefficient row is written contiguously), with
+// one direction at a time, with
 //   A_ij,ab = D (lam F_ia F_jb + mu (F_i . F_j) delta_ab + mu F_ib F_ja),
 // the Cartesian form of eq. (37) (F_i is row i of F).  The result is written in
-// the column-major layout the contraction reads: coef[t][3a+b][9C+3i+j].
+// the column-major layout the contraction reads: coef[t][3a+b][9C+3i+j] (the split modes' planes
+// tiled where the contraction keeps the table in LDS).  Two kernels: fit_q_kernel for an isotropic
+// map and degree q <= 3 on q + 1 nodes (compile-time shape, passes in registers), fit_kernel for
+// every other shape (passes through LDS).
+#include <cstring>
+
 #include "device_common.h"
 
 namespace igamt {
@@ -53,16 +57,55 @@ __device__ inline void store_coef(const FitArgs &a, int Kp, int64_t col, int k, 
   }
 }
 
-// QC > 0: the projection degree is QC in every direction with QC + 1 fit nodes, known at compile
-// time (every index division of the passes by a constant); QC = 0: degrees and nodes from the
-// arguments.  Both compute the same sums in the same order.
-template <int P0, int P1, int P2, int QC>
-__global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
+// A_ij,ab at one sample from the rows F_i, F_j of F = J^-1 and D = det J (the Cartesian form of
+// eq. (37)).  The elasticity tensor's symmetry gives A_ij,ab = A_ji,ba; callers pass (i, a) and
+// (j, b) ordered so that 3 i + a <= 3 j + b, and the two entries come out bit-identical.
+__device__ inline double elastic_density(const double *Fi, const double *Fj, double D, int aa, int bb, double lam,
+                                         double mu) {
+  const double fij = Fi[0] * Fj[0] + Fi[1] * Fj[1] + Fi[2] * Fj[2];
+  return D * (lam * Fi[aa] * Fj[bb] + (aa == bb ? mu * fij : 0.0) + mu * Fi[bb] * Fj[aa]);
+}
+
+// J diag(h) from the macro map's parameter Jacobian J, its inverse and determinant into FDs[0..9];
+// a tile whose map folds (D <= 0) is flagged.
+__device__ inline void fit_store_inverse(const FitArgs &a, int64_t t, const double (&hx)[3], double (&J)[3][3],
+                                         double *FDs) {
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) J[cc][k] *= hx[k];
+  double F[3][3];
+  const double D = inv3(J, F);
+  if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag, (int32_t)t);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) FDs[3 * r + c] = F[r][c];
+  FDs[9] = D;
+}
+
+// Jacobian, inverse and determinant at the fit sample xi_s = (fx[s1], fx[s2], fx[s3]) of tile t, into
+// FD[s][0..8] (F row-major) and FD[s][9] (D); a tile whose map folds (D <= 0) is flagged.
+template <int P0, int P1, int P2>
+__device__ inline void fit_sample_jacobian(const FitArgs &a, int64_t t, const double (&ax)[3], const double (&hx)[3],
+                                           int s1, int s2, int s3, double *FDs) {
   constexpr int PMX = max3(P0, P1, P2);
+  double N[3][PMX + 1], dN[3][PMX + 1];
+  int span[3];
+  const double xh[3] = {ax[0] + hx[0] * a.fx[s1], ax[1] + hx[1] * a.fx[s2], ax[2] + hx[2] * a.fx[s3]};
+  double J[3][3];
+  spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+  fit_store_inverse(a, t, hx, J, FDs);
+}
+
+// General shapes: projection degrees and fit nodes from the arguments (q_k + 1 <= n_fit per
+// direction), the passes through LDS, one component (a, b) of A at a time.
+template <int P0, int P1, int P2>
+__global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   extern __shared__ double smem[];
-  const int nf = QC ? QC + 1 : a.nf;
-  const int q1x = QC ? QC + 1 : a.q1[0], q1y = QC ? QC + 1 : a.q1[1], q1z = QC ? QC + 1 : a.q1[2];
-  const int Kp = QC ? (9 * (QC + 1) * (QC + 1) * (QC + 1) + kColPad - 1) / kColPad * kColPad : a.Kp;
+  const int nf = a.nf;
+  const int q1x = a.q1[0], q1y = a.q1[1], q1z = a.q1[2];
+  const int Kp = a.Kp;
   const int ns = nf * nf * nf;
   const int npi = q1x * q1y * q1z;
   double *FD = smem;              // [ns][10]
@@ -88,26 +131,8 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   const double hx[3] = {a.box_h[0][tx], a.box_h[1][ty], a.box_h[2][tz]};
 
   // Jacobians at the samples
-  for (int s = tid; s < ns; s += 64) {
-    const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-    double N[3][PMX + 1], dN[3][PMX + 1];
-    int span[3];
-    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
-    double J[3][3];
-    spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) J[cc][k] *= hx[k];
-    double F[3][3];
-    const double D = inv3(J, F);
-    if (!(D > 0.0) || !isfinite(D)) atomicMin(a.flag, (int32_t)t);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) FD[s * 10 + 3 * r + c] = F[r][c];
-    FD[s * 10 + 9] = D;
-  }
+  for (int s = tid; s < ns; s += 64)
+    fit_sample_jacobian<P0, P1, P2>(a, t, ax, hx, s % nf, (s / nf) % nf, s / (nf * nf), FD + s * 10);
   __syncthreads();
   // F16X3: |coef| <= L_x L_y L_z max|A_ij,ab| with L_k the max row sum of |P_k| (a.L3)
   const double L3 = a.L3;
@@ -121,9 +146,8 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
     for (int e = tid; e < ns * 9; e += 64) {
       const int s = e / 9, ij = e % 9, i = ij / 3, j = ij % 3;
       const double *Fs = FD + s * 10;
-      const double fij = Fs[3 * i] * Fs[3 * j] + Fs[3 * i + 1] * Fs[3 * j + 1] + Fs[3 * i + 2] * Fs[3 * j + 2];
-      buf0[e] = Fs[9] * (a.lam * Fs[3 * i + aa] * Fs[3 * j + bb] + (aa == bb ? a.mu * fij : 0.0) +
-                         a.mu * Fs[3 * i + bb] * Fs[3 * j + aa]);
+      buf0[e] = 3 * i + aa <= 3 * j + bb ? elastic_density(Fs + 3 * i, Fs + 3 * j, Fs[9], aa, bb, a.lam, a.mu)
+                                         : elastic_density(Fs + 3 * j, Fs + 3 * i, Fs[9], bb, aa, a.lam, a.mu);
     }
     __syncthreads();
     double sc = 1.0;
@@ -169,6 +193,222 @@ __global__ __launch_bounds__(64) void fit_kernel(FitArgs a) {
   }
 }
 
+// a wave-uniform double moved to scalar registers
+__device__ inline double uniform_f64(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Projection degree Q in every direction on Q + 1 fit nodes (the interpolating case), with the
+// shape known at compile time.  After the Jacobians, lane l < 45 takes one of the 45 index pairs
+// (u, v) = (3 i + a, 3 j + b) with u <= v: it evaluates A_ij,ab at every sample, which is also
+// A_ji,ba, and runs the three 1-D passes on them in registers (the same sums in the same order as
+// the LDS passes of fit_kernel).  The results go into an LDS image of the tile's nine coefficient
+// rows in the stored precision (entry (ab, 9 C + ij) from lane (u, v), entry (ba, 9 C + ji) from
+// the same lane; FP64 in two passes of at most five rows), which the workgroup then writes out as
+// 16-byte pieces, consecutive lanes on consecutive pieces.  F16X3: the column scale is the maximum
+// of |A_ij,ab| over the column's lanes (an LDS atomic maximum on the bits of non-negative doubles),
+// the same for (a, b) and (b, a).
+template <int Q, int PREC>
+struct FitShape {
+  static constexpr int NF = Q + 1, NS = NF * NF * NF, K = 9 * NS;
+  static constexpr int KP = (K + kColPad - 1) / kColPad * kColPad;
+  static constexpr int ROWS = PREC == IGAMT_F64 ? 5 : 9;              // coefficient rows per LDS image
+  static constexpr int STAGE = ROWS * KP * (PREC == IGAMT_F64 ? 8 : 4);  // bytes: values, or hi and lo planes
+};
+
+template <int P0, int P1, int P2, int Q, int PREC>
+__global__ __launch_bounds__(64) void fit_q_kernel(FitArgs a) {
+  using S = FitShape<Q, PREC>;
+  constexpr int NF = S::NF, NS = S::NS, K = S::K, KP = S::KP;
+  extern __shared__ __align__(16) unsigned char stage[];
+  __shared__ double FD[NS * 10];
+  __shared__ unsigned long long cmax[9];  // F16X3: bits of the column maxima (non-negative doubles)
+  __shared__ double NB[3][NF][2][P0 + 1];   // per direction and node: B-spline values, derivatives
+  __shared__ int SP[3][NF];                 // and spans
+  static_assert(P0 == P1 && P1 == P2, "isotropic macro maps only");
+  const int tid = threadIdx.x;
+  const int64_t t = a.t0 + blockIdx.x;
+
+  if (t >= a.n_tiles) {  // padding tile: zeros
+    for (int e = tid; e < 9 * KP; e += 64) store_coef(a, KP, t * 9 + e / KP, e % KP, 0.0, 1.0);
+    if (PREC == IGAMT_F16X3 && tid < 9) ((float *)((uint16_t *)a.out + 2 * a.plane))[t * 9 + tid] = 1.0f;
+    return;
+  }
+  const int tx = (int)(t % a.tiles[0]);
+  const int ty = (int)((t / a.tiles[0]) % a.tiles[1]);
+  const int tz = (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]));
+  const double ax[3] = {a.box_a[0][tx], a.box_a[1][ty], a.box_a[2][tz]};
+  const double hx[3] = {a.box_h[0][tx], a.box_h[1][ty], a.box_h[2][tz]};
+  // the spans and 1-D basis values and derivatives at the Q + 1 nodes of each direction, one lane
+  // each, shared by the samples (the values spline_jacobian3 would compute at every sample)
+  if (tid < 3 * NF) {
+    const int d = tid / NF, sn = tid % NF;
+    const double x = (d == 0 ? ax[0] : d == 1 ? ax[1] : ax[2]) + (d == 0 ? hx[0] : d == 1 ? hx[1] : hx[2]) * a.fx[sn];
+    const double *U = d == 0 ? a.knots[0] : d == 1 ? a.knots[1] : a.knots[2];
+    const int sp = find_span(U, d == 0 ? a.nM[0] : d == 1 ? a.nM[1] : a.nM[2], P0, x);
+    double N[P0 + 1], dN[P0 + 1];
+    bspline_ders<P0>(U, sp, x, N, dN);
+    SP[d][sn] = sp;
+#pragma unroll
+    for (int r = 0; r <= P0; ++r) {
+      NB[d][sn][0][r] = N[r];
+      NB[d][sn][1][r] = dN[r];
+    }
+  }
+  if (PREC == IGAMT_F16X3 && tid < 9) cmax[tid] = 0;
+  __syncthreads();
+  if (tid < NS) {
+    const int si[3] = {tid % NF, (tid / NF) % NF, tid / (NF * NF)};
+    int span[3];
+    double N[3][P0 + 1], dN[3][P0 + 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      span[k] = SP[k][si[k]];
+#pragma unroll
+      for (int r = 0; r <= P0; ++r) {
+        N[k][r] = NB[k][si[k]][0][r];
+        dN[k][r] = NB[k][si[k]][1][r];
+      }
+    }
+    double J[3][3];
+    spline_jacobian_sum<P0, P1, P2, (P0 > 3)>(a.nM, a.ctrl, a.wts, span, N, dN, J);
+    fit_store_inverse(a, t, hx, J, FD + tid * 10);
+  }
+
+  // this lane's pair (u, v), u <= v (lanes 45..63 repeat pair 44 and store nothing)
+  int u = 0, rem = min(tid, 44);
+  while (rem >= 9 - u) { rem -= 9 - u; ++u; }
+  const int v = u + rem;
+  const int i = u / 3, aa = u % 3, j = v / 3, bb = v % 3;
+  const bool act = tid < 45;
+  // the 1-D operator, the same in every direction here (checked by the launcher), in scalar registers
+  double P[NF][NF];
+#pragma unroll
+  for (int c = 0; c < NF; ++c)
+#pragma unroll
+    for (int s = 0; s < NF; ++s) P[c][s] = uniform_f64(a.fP3[c * NF + s]);
+  __syncthreads();
+
+  double val[NS];
+  double m = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    val[s] = elastic_density(FD + s * 10 + 3 * i, FD + s * 10 + 3 * j, FD[s * 10 + 9], aa, bb, a.lam, a.mu);
+    m = fmax(m, fabs(val[s]));
+  }
+  // x: (s3, s2, s1) -> (s3, s2, c1); y: (s3, s2, c1) -> (s3, c2, c1); z: (s3, c2, c1) -> (c3, c2, c1)
+#pragma unroll
+  for (int l = 0; l < NF * NF; ++l) {
+    double o[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+      double w = 0.0;
+#pragma unroll
+      for (int s = 0; s < NF; ++s) w += P[c][s] * val[l * NF + s];
+      o[c] = w;
+    }
+#pragma unroll
+    for (int c = 0; c < NF; ++c) val[l * NF + c] = o[c];
+  }
+#pragma unroll
+  for (int s3 = 0; s3 < NF; ++s3)
+#pragma unroll
+    for (int c1 = 0; c1 < NF; ++c1) {
+      double o[NF];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        double w = 0.0;
+#pragma unroll
+        for (int s = 0; s < NF; ++s) w += P[c][s] * val[(s3 * NF + s) * NF + c1];
+        o[c] = w;
+      }
+#pragma unroll
+      for (int c = 0; c < NF; ++c) val[(s3 * NF + c) * NF + c1] = o[c];
+    }
+#pragma unroll
+  for (int l = 0; l < NF * NF; ++l) {
+    double o[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+      double w = 0.0;
+#pragma unroll
+      for (int s = 0; s < NF; ++s) w += P[c][s] * val[s * NF * NF + l];
+      o[c] = w;
+    }
+#pragma unroll
+    for (int c = 0; c < NF; ++c) val[c * NF * NF + l] = o[c];
+  }
+
+  double sc = 1.0;
+  if (PREC == IGAMT_F16X3) {  // |coef| <= L_x L_y L_z max|A_ij,ab| with L_k the max row sum of |P_k|
+    const int col = min(3 * aa + bb, 3 * bb + aa);  // (a, b) and (b, a) share the maximum
+    if (act) atomicMax(&cmax[col], (unsigned long long)__double_as_longlong(m));
+    __syncthreads();
+    sc = f16_scale_for(__longlong_as_double((long long)cmax[col]) * a.L3);
+    if (act && i == 0 && j == 0) {
+      float *inv = (float *)((uint16_t *)a.out + 2 * a.plane) + t * 9;
+      inv[3 * aa + bb] = (float)(1.0 / sc);
+      inv[3 * bb + aa] = (float)(1.0 / sc);
+    }
+  }
+
+  // LDS image of the nine rows in the stored precision
+  auto put = [&](int r, int k, double x, double scale) {
+    if (PREC == IGAMT_F64) {
+      ((double *)stage)[r * KP + k] = x;
+    } else if (PREC == IGAMT_F32) {
+      ((float *)stage)[r * KP + k] = (float)x;
+    } else {
+      uint16_t hi, lo;
+      if (PREC == IGAMT_BF16X3)
+        split_bf16(x, hi, lo);
+      else
+        split_f16(x * scale, hi, lo);
+      ((uint16_t *)stage)[r * KP + k] = hi;
+      ((uint16_t *)stage)[9 * KP + r * KP + k] = lo;
+    }
+  };
+  // FP64: the rows in two passes of at most five, which halves the image (and the LDS a workgroup holds)
+  constexpr int RH = S::ROWS;
+#pragma unroll
+  for (int r0 = 0; r0 < 9; r0 += RH) {
+    if (r0) __syncthreads();  // the previous pass's pieces are read out
+    if (act) {
+      const int r1 = 3 * aa + bb - r0, r2 = 3 * bb + aa - r0;
+#pragma unroll
+      for (int C = 0; C < NS; ++C) {
+        if (r1 >= 0 && r1 < RH) put(r1, 9 * C + 3 * i + j, val[C], sc);
+        if (u != v && r2 >= 0 && r2 < RH) put(r2, 9 * C + 3 * j + i, val[C], sc);
+      }
+    }
+    const int nr = min(RH, 9 - r0);  // rows in this pass
+    if constexpr (KP > K)
+      for (int e = tid; e < nr * (KP - K); e += 64) put(e / (KP - K), K + e % (KP - K), 0.0, 1.0);
+    __syncthreads();
+
+    // 16-byte pieces: rows of doubles / floats, or runs of 8 split entries of one column
+    if (PREC == IGAMT_F64 || PREC == IGAMT_F32) {
+      constexpr int W = PREC == IGAMT_F64 ? 2 : 4;  // entries per piece
+      for (int e = tid; e < nr * KP / W; e += 64) {
+        const int r = e / (KP / W), k = (e % (KP / W)) * W;
+        const uint4 x = *(const uint4 *)(stage + (r * KP + k) * (16 / W));
+        *(uint4 *)((unsigned char *)a.out + ((t * 9 + r0 + r) * KP + k) * (16 / W)) = x;
+      }
+    } else {
+      constexpr bool TILED = split_tiled(KP);
+      for (int e = tid; e < 2 * 9 * KP / 8; e += 64) {
+        // tiled: the columns of one 8-entry run adjacent in memory, so the row index runs fastest
+        const int pl = e / (9 * KP / 8), f = e % (9 * KP / 8);
+        const int r = TILED ? f % 9 : f / (KP / 8), k = (TILED ? f / 9 : f % (KP / 8)) * 8;
+        const uint4 x = *(const uint4 *)((const uint16_t *)stage + pl * 9 * KP + r * KP + k);
+        *(uint4 *)((uint16_t *)a.out + pl * a.plane + split_coef_index(t * 9 + r, k, KP, TILED)) = x;
+      }
+    }
+  }
+}
+
 int64_t coef_elem_bytes(igamt_precision prec) {
   return prec == IGAMT_F64 ? 8 : prec == IGAMT_F32 ? 4 : 4;  // split modes: two 2-byte planes
 }
@@ -182,6 +422,26 @@ int64_t coef_bytes(const igamt_plan *P, igamt_precision prec) {
 
 int64_t blocks_bytes(const igamt_plan *P, igamt_precision prec) {
   return align256(P->n_tiles * P->n_pairs * 9 * (prec == IGAMT_F64 ? 8 : 4));
+}
+
+template <int PM, int Q>
+void launch_fit_q(const FitArgs &a, igamt_precision prec, dim3 grid, hipStream_t s) {
+  switch (prec) {
+    case IGAMT_F64:
+      hipLaunchKernelGGL((fit_q_kernel<PM, PM, PM, Q, IGAMT_F64>), grid, dim3(64), (FitShape<Q, IGAMT_F64>::STAGE), s, a);
+      break;
+    case IGAMT_F32:
+      hipLaunchKernelGGL((fit_q_kernel<PM, PM, PM, Q, IGAMT_F32>), grid, dim3(64), (FitShape<Q, IGAMT_F32>::STAGE), s, a);
+      break;
+    case IGAMT_BF16X3:
+      hipLaunchKernelGGL((fit_q_kernel<PM, PM, PM, Q, IGAMT_BF16X3>), grid, dim3(64), (FitShape<Q, IGAMT_BF16X3>::STAGE), s,
+                         a);
+      break;
+    default:
+      hipLaunchKernelGGL((fit_q_kernel<PM, PM, PM, Q, IGAMT_F16X3>), grid, dim3(64), (FitShape<Q, IGAMT_F16X3>::STAGE), s,
+                         a);
+      break;
+  }
 }
 
 igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec, void *d_coef, void *stream,
@@ -229,25 +489,32 @@ igamt_status launch_fit(igamt_plan *P, double E, double nu, igamt_precision prec
   a.t0 = t0;
   const dim3 grid((unsigned)(t1 - t0)), block(64);
   hipStream_t s = (hipStream_t)stream;
-#define FIT_LAUNCH(p0, p1, p2, qc)                                                                    \
+#define FIT_LAUNCH(p0, p1, p2)                                                                        \
   do {                                                                                                \
-    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p0, p1, p2, qc>,          \
+    if (shm > 65536) IGAMT_HIP(hipFuncSetAttribute((const void *)fit_kernel<p0, p1, p2>,              \
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)); \
-    hipLaunchKernelGGL((fit_kernel<p0, p1, p2, qc>), grid, block, shm, s, a);                         \
+    hipLaunchKernelGGL((fit_kernel<p0, p1, p2>), grid, block, shm, s, a);                             \
   } while (0)
   // isotropic macro map and projection degree q <= 3 on q + 1 nodes: the compile-time shape
-  const int qc = (P->qd[0] == P->qd[1] && P->qd[0] == P->qd[2] && P->n_fit == P->qd[0] + 1 && P->qd[0] >= 1 &&
-                  P->qd[0] <= 3) ? P->qd[0] : 0;
+  // and the same 1-D operator in every direction
+  int qc = (P->qd[0] == P->qd[1] && P->qd[0] == P->qd[2] && P->n_fit == P->qd[0] + 1 && P->qd[0] >= 1 &&
+            P->qd[0] <= 3) ? P->qd[0] : 0;
+  if (qc) {
+    const size_t n1 = (size_t)(qc + 1) * (qc + 1);
+    if (std::memcmp(P->fit_P3.data(), P->fit_P3.data() + n1, n1 * sizeof(double)) != 0 ||
+        std::memcmp(P->fit_P3.data(), P->fit_P3.data() + 2 * n1, n1 * sizeof(double)) != 0)
+      qc = 0;
+  }
   switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
 #define FIT_ISO(p)                                                                                    \
   case IGAMT_DEGREE_KEY(p, p, p):                                                                     \
-    if (qc == 1) FIT_LAUNCH(p, p, p, 1);                                                              \
-    else if (qc == 2) FIT_LAUNCH(p, p, p, 2);                                                         \
-    else if (qc == 3) FIT_LAUNCH(p, p, p, 3);                                                         \
-    else FIT_LAUNCH(p, p, p, 0);                                                                      \
+    if (qc == 1) launch_fit_q<p, 1>(a, prec, grid, s);                                                \
+    else if (qc == 2) launch_fit_q<p, 2>(a, prec, grid, s);                                           \
+    else if (qc == 3) launch_fit_q<p, 3>(a, prec, grid, s);                                           \
+    else FIT_LAUNCH(p, p, p);                                                                         \
     break;
 #define FIT_CASE(p0, p1, p2)                                                                          \
-  case IGAMT_DEGREE_KEY(p0, p1, p2): FIT_LAUNCH(p0, p1, p2, 0); break;
+  case IGAMT_DEGREE_KEY(p0, p1, p2): FIT_LAUNCH(p0, p1, p2); break;
     FIT_ISO(1) FIT_ISO(2) FIT_ISO(3) FIT_ISO(4) FIT_ISO(5) FIT_ISO(6)
     IGAMT_FOR_ANISO_MACRO_DEGREES(FIT_CASE)
 #undef FIT_CASE

@@ -84,6 +84,23 @@ def test_fit_cfg1(cfg1, torch):
     assert err < 1e-13
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fit_coefficients_symmetric(torch, P, prec):
+    """A_ij,ab = A_ji,ba (eq. (37)); both fit kernels evaluate each such pair once, so the stored
+    coefficients at (9 C + 3 i + j, 3 a + b) and (9 C + 3 j + i, 3 b + a) agree bit for bit: the
+    compile-time-shape kernel (q = 2 on 3 nodes) and the general one (least squares on 4 nodes)."""
+    import dataclasses
+    w0 = W.make("cfg1")
+    for w in (w0, dataclasses.replace(w0, n_fit=w0.n_fit + 1)):
+        plan = P.Plan.from_workload(w)
+        c = plan.coef_view(plan.fit(w.E, w.nu, prec), prec).cpu().numpy()
+        plan.check()
+        c = c.reshape(w.n_tiles, -1, 3, 3, 3, 3)        # [t][C][i][j][a][b]
+        _say(f"fit symmetry {prec}, n_fit = {w.n_fit}: {c.shape[1]} coefficients per component")
+        assert np.abs(c).max() > 0
+        assert np.array_equal(c, c.transpose(0, 1, 3, 2, 5, 4))
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
 def test_blocks_cfg1(cfg1, torch, prec):
     w, oc, plan = cfg1
