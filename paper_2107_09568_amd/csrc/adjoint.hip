@@ -128,13 +128,23 @@ __global__ __launch_bounds__(kFitAdjThreads) void fit_adjoint_kernel(FitAdjArgs 
     SP[k][s] = sp;
     for (int r = 0; r <= PMX; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
   }
-  // F and D at the samples; zero the adjoint accumulators
+  __syncthreads();   // the basis tables are read by the sample loop
+  // F and D at the samples (from the shared 1-D bases: the values spline_jacobian3 computes); zero
+  // the adjoint accumulators
   for (int s = tid; s < ns; s += kFitAdjThreads) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian3<P0, P1, P2>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      span[k] = SP[k][si[k]];
+#pragma unroll
+      for (int r = 0; r <= PMX; ++r) {
+        N[k][r] = NB[k][si[k]][r];
+        dN[k][r] = DB[k][si[k]][r];
+      }
+    }
+    spline_jacobian_sum<P0, P1, P2>(a.nM, a.ctrl, a.wts, span, N, dN, J);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll

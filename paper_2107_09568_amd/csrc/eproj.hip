@@ -5,7 +5,8 @@
 // macro field of eq. (37) (Cartesian form, as the fit) and Pi_q A its projection onto the degree-q
 // Bernstein space from q + 1 Gauss-Legendre nodes per direction (the fit of eq. (42) at degree q).
 // The samples are a uniform tensor grid with both ends, x_k = k / (n_s - 1), in box coordinates.
-// Per tile one 256-thread workgroup: F = J^-1 and D = det J at the fit nodes and the samples (LDS);
+// Per tile one 256-thread workgroup: F = J^-1 and D = det J at the fit nodes and the samples (LDS;
+// the macro map's 1-D bases are evaluated once per direction and node and shared by the points);
 // for each (i, j) block of A, the nine components at the fit nodes, their coefficients by three 1-D
 // passes (one operator per direction), their values at the samples by three 1-D Bernstein passes;
 // per sample the squared Frobenius error and norm accumulate over the blocks.  The maxima are
@@ -44,14 +45,10 @@ __device__ inline double field_component(const double *FD, int i, int j, int aa,
   return FD[9] * (lam * Fi[aa] * Fj[bb] + (aa == bb ? mu * fij : 0.0) + mu * Fi[bb] * Fj[aa]);
 }
 
-template <int P0, int P1, int P2>
-__device__ inline void point_FD(const EprojArgs &a, const double (&ax)[3], const double (&hx)[3], const double (&x)[3],
-                                double *FD, int64_t t) {
-  constexpr int PMX = max3(P0, P1, P2);
-  const double xh[3] = {ax[0] + hx[0] * x[0], ax[1] + hx[1] * x[1], ax[2] + hx[2] * x[2]};
-  double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
-  int span[3];
-  spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+// J diag(h) from the macro map's parameter Jacobian J: F = (J diag(h))^-1 and D = det(J diag(h)) into
+// FD[0..9]; a tile whose map folds (D <= 0) is flagged.
+__device__ inline void point_FD_store(const EprojArgs &a, const double (&hx)[3], double (&J)[3][3], double *FD,
+                                      int64_t t) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -94,13 +91,49 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
     bernstein(a.q1[k] - 1, a.sx[m], B);
     for (int c = 0; c < a.q1[k]; ++c) Bs[k][m][c] = B[c];
   }
-  for (int s = tid; s < nfit; s += 256) {
-    const double x[3] = {a.fx[s % nf], a.fx[(s / nf) % nf], a.fx[s / (nf * nf)]};
-    point_FD<P0, P1, P2>(a, ax, hx, x, FDf + s * 10, t);
+  // the spans and 1-D B-spline values and derivatives of the macro map at the fit nodes and the
+  // samples of each direction, one thread each, shared by the points (the values spline_jacobian3
+  // would compute at every point)
+  constexpr int PMX = max3(P0, P1, P2);
+  __shared__ double NB[3][kMaxFit + kMaxSample][2][PMX + 1];
+  __shared__ int SP[3][kMaxFit + kMaxSample];
+  const int n1 = nf + ns1;
+  if (tid < 3 * n1) {
+    const int d = tid / n1, m = tid - d * n1;
+    const double x = (d == 0 ? ax[0] : d == 1 ? ax[1] : ax[2]) +
+                     (d == 0 ? hx[0] : d == 1 ? hx[1] : hx[2]) * (m < nf ? a.fx[m] : a.sx[m - nf]);
+    constexpr int PD[3] = {P0, P1, P2};
+    const int sp = find_span(a.knots[d], a.nM[d], d == 0 ? PD[0] : d == 1 ? PD[1] : PD[2], x);
+    double N[PMX + 1], dN[PMX + 1];
+    bspline_ders_dir<P0, P1, P2>(d, a.knots[d], sp, x, N, dN);
+    SP[d][m] = sp;
+#pragma unroll
+    for (int r = 0; r <= PMX; ++r) {
+      NB[d][m][0][r] = N[r];
+      NB[d][m][1][r] = dN[r];
+    }
   }
+  __syncthreads();
+  auto point = [&](int m0, int m1, int m2, double *FD) {
+    const int mi[3] = {m0, m1, m2};
+    int span[3];
+    double N[3][PMX + 1], dN[3][PMX + 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      span[k] = SP[k][mi[k]];
+#pragma unroll
+      for (int r = 0; r <= PMX; ++r) {
+        N[k][r] = NB[k][mi[k]][0][r];
+        dN[k][r] = NB[k][mi[k]][1][r];
+      }
+    }
+    double J[3][3];
+    spline_jacobian_sum<P0, P1, P2, true>(a.nM, a.ctrl, a.wts, span, N, dN, J);
+    point_FD_store(a, hx, J, FD, t);
+  };
+  for (int s = tid; s < nfit; s += 256) point(s % nf, (s / nf) % nf, s / (nf * nf), FDf + s * 10);
   for (int k = tid; k < nsmp; k += 256) {
-    const double x[3] = {a.sx[k % ns1], a.sx[(k / ns1) % ns1], a.sx[k / (ns1 * ns1)]};
-    point_FD<P0, P1, P2>(a, ax, hx, x, FDs + k * 10, t);
+    point(nf + k % ns1, nf + (k / ns1) % ns1, nf + k / (ns1 * ns1), FDs + k * 10);
     err2[k] = 0.0;
     nrm2[k] = 0.0;
   }

@@ -142,14 +142,39 @@ __global__ __launch_bounds__(64) void load_fit_kernel(LoadFitArgs a) {
   const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
   const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
   double *co = a.coef + t * (int64_t)kLoadSlots * 3 * npi;
-  // body samples
+  // body samples: the spans and 1-D B-spline values and derivatives at the nodes of each direction,
+  // one thread each, shared by the samples (the values spline_jacobian3 would compute per sample)
+  __shared__ double NB[3][kMaxFit][2][PMX + 1];
+  __shared__ int SP[3][kMaxFit];
+  if (tid < 3 * nf) {
+    const int d = tid / nf, m = tid - d * nf;
+    const double x = (d == 0 ? ax[0] : d == 1 ? ax[1] : ax[2]) + (d == 0 ? hx[0] : d == 1 ? hx[1] : hx[2]) * a.fx[m];
+    const int sp = find_span(a.knots[d], a.nM[d], d == 0 ? PD[0] : d == 1 ? PD[1] : PD[2], x);
+    double N[PMX + 1], dN[PMX + 1];
+    bspline_ders_dir<P0, P1, P2>(d, a.knots[d], sp, x, N, dN);
+    SP[d][m] = sp;
+#pragma unroll
+    for (int r = 0; r <= PMX; ++r) {
+      NB[d][m][0][r] = N[r];
+      NB[d][m][1][r] = dN[r];
+    }
+  }
+  __syncthreads();
   const int ns = nf * nf * nf;
   for (int s = tid; s < ns; s += 64) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian3<P0, P1, P2, true>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      span[k] = SP[k][si[k]];
+#pragma unroll
+      for (int r = 0; r <= PMX; ++r) {
+        N[k][r] = NB[k][si[k]][0][r];
+        dN[k][r] = NB[k][si[k]][1][r];
+      }
+    }
+    spline_jacobian_sum<P0, P1, P2, true>(a.nM, a.ctrl, a.wts, span, N, dN, J);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll

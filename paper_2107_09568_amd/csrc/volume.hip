@@ -103,24 +103,31 @@ __global__ __launch_bounds__(64) void volume_tile_kernel(VolumeTileArgs a) {
   const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
   const bool grad = a.local_grad != nullptr;
   double *WQ = GS + ns * 9;   // NURBS: 1 / W and sum_n GS[c][n] d_n W / W^2 per sample
-  if (grad)
-    for (int e = tid; e < 3 * nf; e += 64) {
-      const int k = e / nf, s = e % nf;
-      const double x = ax[k] + hx[k] * a.fx[s];
-      const int sp = find_span(a.knots[k], a.nM[k], PD[k], x);
-      double N[PMX + 1], dN[PMX + 1];
-      bspline_ders_dir<P0, P1, P2>(k, a.knots[k], sp, x, N, dN);
-      SP[k][s] = sp;
-      for (int r = 0; r <= PMX; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
-    }
-  __syncthreads();   // the basis tables are read by the sample loop (NURBS) and the local gradients
+  for (int e = tid; e < 3 * nf; e += 64) {   // 1-D macro bases at the tile's sample abscissae
+    const int k = e / nf, s = e % nf;
+    const double x = ax[k] + hx[k] * a.fx[s];
+    const int sp = find_span(a.knots[k], a.nM[k], PD[k], x);
+    double N[PMX + 1], dN[PMX + 1];
+    bspline_ders_dir<P0, P1, P2>(k, a.knots[k], sp, x, N, dN);
+    SP[k][s] = sp;
+    for (int r = 0; r <= PMX; ++r) { NB[k][s][r] = N[r]; DB[k][s][r] = dN[r]; }
+  }
+  __syncthreads();   // the basis tables are read by the sample loop and the local gradients
   double vol = 0.0;
   for (int s = tid; s < ns; s += 64) {
     const int si[3] = {s % nf, (s / nf) % nf, s / (nf * nf)};
-    const double xh[3] = {ax[0] + hx[0] * a.fx[si[0]], ax[1] + hx[1] * a.fx[si[1]], ax[2] + hx[2] * a.fx[si[2]]};
     double J[3][3], N[3][PMX + 1], dN[3][PMX + 1];
     int span[3];
-    spline_jacobian3<P0, P1, P2>(a.knots, a.nM, a.ctrl, a.wts, xh, J, span, N, dN);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {   // the shared 1-D bases (the values spline_jacobian3 computes)
+      span[k] = SP[k][si[k]];
+#pragma unroll
+      for (int r = 0; r <= PMX; ++r) {
+        N[k][r] = NB[k][si[k]][r];
+        dN[k][r] = DB[k][si[k]][r];
+      }
+    }
+    spline_jacobian_sum<P0, P1, P2>(a.nM, a.ctrl, a.wts, span, N, dN, J);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
