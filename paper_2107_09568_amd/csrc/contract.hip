@@ -660,6 +660,253 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void contract_split_kernel(Spl
   }
 }
 
+// ---- split modes with the table resident in registers ---------------------------------------
+// The LDS-resident variant above shares every coefficient column among the 112 table rows one CU
+// holds, so each column crosses that CU's L1 once per 112 rows, and that stream bounds it.  Here
+// each of the workgroup's 8 waves keeps 32 table rows (hi and lo planes, all k: 128 registers per
+// lane for K = 256) in registers for its whole life, 256 rows per CU, and the columns pass through
+// LDS once per workgroup: chunks of 32 columns (both planes, all k; 16 KB per plane, contiguous in
+// the tiled layout) are loaded by the whole workgroup one chunk ahead into alternating LDS buffers,
+// one barrier per chunk, and every wave reads each B fragment from LDS once for its 2 x 3 MFMAs
+// (two row tiles, three products).  A chunk's epilogue runs during the next chunk's first k-steps
+// (its accumulators are kept aside), so its stage traffic and stores overlap that chunk's MFMAs.
+// Workgroups of one XCD take every row block of their column splits, so each column is fetched
+// into that XCD's L2 once.
+#ifndef IGAMT_SPLIT_REG
+#define IGAMT_SPLIT_REG 1
+#endif
+constexpr int kRegWaves = 8;                             // waves per workgroup
+constexpr int kRegRT = 2;                                // 16-row tiles per wave
+constexpr int kRegRows = 16 * kRegRT * kRegWaves;        // 256 table rows per workgroup
+constexpr int kRegCols = 32;                             // columns per chunk (two column blocks)
+constexpr int kRegStageCol = 36;                         // words per column of a wave's stage (32 rows + pad)
+
+// two B chunk buffers (two planes each), one epilogue stage of 32 columns x 32 rows per wave, then
+// each wave's 32 inverse row scales (F16X3)
+__host__ __device__ inline int64_t split_reg_lds_bytes(int64_t Kp) {
+  return 2 * 2 * kRegCols * Kp * 2 + 4 * kRegWaves * 32 * kRegStageCol + 4 * kRegWaves * 32;
+}
+
+template <int MODE, int KS, int PROD>
+__global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(SplitArgs a) {
+  using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int64_t Kp = 32 * KS;
+  constexpr int CHUNK = kRegCols * (int)Kp * 2;          // bytes of one plane of one chunk
+  const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+  const int rb = slot % a.n_rblk, s = (slot / a.n_rblk) * 8 + xcd;
+  if (s >= a.n_split) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
+  const int64_t row0 = (int64_t)rb * kRegRows + 32 * wave;   // this wave's first row
+  const int64_t units = (a.c_hi - a.c_lo + 15) / 16;
+  const int64_t c0 = a.c_lo + 16 * (units * s / a.n_split);
+  const int64_t c1 = min(a.c_hi, a.c_lo + 16 * (units * (s + 1) / a.n_split));
+  if (c1 <= c0) return;
+  const int n_chunk = (int)((c1 - c0 + kRegCols - 1) / kRegCols);
+  float *stage = (float *)(lds + 4 * CHUNK) + wave * 32 * kRegStageCol;   // [32 columns][32 rows + pad]
+
+  // the chunk's two planes: 2 column blocks x KS k-steps x 512 elements, contiguous per block
+  constexpr int PIECES = CHUNK / 16;                     // 16-byte pieces per plane
+  constexpr int NPRE = 2 * PIECES / (64 * kRegWaves);    // pieces per thread, both planes
+  static_assert(2 * PIECES % (64 * kRegWaves) == 0, "chunk pieces must divide over the workgroup");
+  u32x4 pre[NPRE];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = tid + i * 64 * kRegWaves, pl = e / PIECES, j = e - pl * PIECES;
+      const int cb = j / (KS * 64), jj = j - cb * KS * 64;   // column block, piece within it
+      int64_t col = c0 + (int64_t)c * kRegCols + 16 * cb;
+      col = min(col, a.ncol_pad - 16);   // past the range: a valid block, its result is not stored
+      pre[i] = *(const u32x4 *)((pl ? a.Bl : a.Bh) + (col >> 4) * KS * 512 + 8 * jj);
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = tid + i * 64 * kRegWaves, pl = e / PIECES, j = e - pl * PIECES;
+      *(u32x4 *)(lds + (2 * buf + pl) * CHUNK + 16 * j) = pre[i];
+    }
+  };
+
+  // this wave's table rows: lane (l16, kq) holds row 16 rt + l16, k 32 ks + 8 kq .. + 7
+  V8 ah[kRegRT][KS], al[kRegRT][KS];
+#pragma unroll
+  for (int rt = 0; rt < kRegRT; ++rt) {
+    const int64_t r = row0 + 16 * rt + l16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int64_t off = r * Kp + 32 * ks + 8 * kq;
+      if (r < a.Mp) {
+        ah[rt][ks] = *(const V8 *)(a.Ah + off);
+        al[rt][ks] = *(const V8 *)(a.Al + off);
+      } else {
+        ah[rt][ks] = V8{};
+        al[rt][ks] = V8{};
+      }
+    }
+  }
+  // F16X3: the inverse row scales of the wave's 32 rows, in LDS after the stage
+  float *rsl = (float *)(lds + 4 * CHUNK) + kRegWaves * 32 * kRegStageCol + 32 * wave;
+  if constexpr (MODE == IGAMT_F16X3)
+    if (lane < 32) rsl[lane] = row0 + lane < a.Mp ? a.Ascale[row0 + lane] : 0.0f;
+  auto mma = [&](const V8 &x, const V8 &y, f4 &c) {
+    if constexpr (MODE == IGAMT_BF16X3)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+    else
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+  };
+
+  // Epilogue map: the 32 x 16 values of a chunk's row tile in block-array address order -- tile
+  // part, row, ab, where a tile part is the run of the chunk's columns that belong to one tile -- so
+  // that consecutive lanes store consecutive words.  It depends on the chunk only through the ab of
+  // its first column (ab0).  Element e = lane + 64 i of map ab0: espk = its stage index (column cl,
+  // row rr) | rr << 11, egoff = its offset in the block array from the chunk's first tile at the
+  // wave's first row; each lane's eight entries are contiguous.
+  __shared__ __attribute__((aligned(16))) uint16_t espk[9][64][8];
+  __shared__ __attribute__((aligned(16))) int egoff[9][64][8];
+  for (int idx = tid; idx < 9 * 512; idx += 64 * kRegWaves) {
+    const int ab0 = idx >> 9, e = idx & 511;
+    int base = 0, colo = 0, abs = ab0, k = min(9 - ab0, 32), t = 0;
+    for (int j = 0; j < 4; ++j) {   // at most five parts (1 + 9 + 9 + 9 + 4 columns)
+      if (e >= base + 16 * k) {
+        base += 16 * k;
+        colo += k;
+        abs = 0;
+        ++t;
+        k = min(9, 32 - colo);
+      }
+    }
+    const int local = e - base, rr = local / k, ab = abs + local - rr * k, cl = colo + ab - abs;
+    espk[ab0][e & 63][e >> 6] = (uint16_t)((cl * kRegStageCol + rr) | rr << 11);
+    egoff[ab0][e & 63][e >> 6] = (int)(((int64_t)t * a.M + rr) * 9 + ab);
+  }
+
+  // The previous chunk's epilogue, in three steps: (1) its accumulators (scaled) into the stage and
+  // its map entries into registers, (2) the stage read back in map order, (3) the stores.
+  f4 pacc[kRegRT][2];
+  float pcs[2] = {1.0f, 1.0f};
+  int64_t pcw = 0;
+  int spk[8], goff[8];
+  float v[kRegRT][8];
+  auto epi1 = [&]() {
+#pragma unroll
+    for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        f4 x = pacc[rt][q];
+        if constexpr (MODE == IGAMT_F16X3) {
+          const f4 rs = *(const f4 *)(rsl + 16 * rt + 4 * kq);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = x[j] * (rs[j] * pcs[q]);
+        }
+        *(f4 *)(stage + (16 * q + l16) * kRegStageCol + 16 * rt + 4 * kq) = x;
+      }
+    const int ab0 = (int)(pcw - 9 * (pcw / 9));
+    const u32x4 sp = *(const u32x4 *)&espk[ab0][lane][0];
+    const u32x4 g0 = *(const u32x4 *)&egoff[ab0][lane][0], g1 = *(const u32x4 *)&egoff[ab0][lane][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      spk[2 * i] = (int)(sp[i] & 0xffffu);
+      spk[2 * i + 1] = (int)(sp[i] >> 16);
+      goff[i] = (int)g0[i];
+      goff[4 + i] = (int)g1[i];
+    }
+  };
+  auto epi2 = [&]() {
+#pragma unroll
+    for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[rt][i] = stage[(spk[i] & 2047) + 16 * rt];
+  };
+  // part p of 4 (PARTS = 4: a quarter of the stores each), or all of them (p < 0); a chunk past the
+  // column range or a row block past M takes the checked stores at once
+  auto epi3 = [&](int p) {
+    float *obase = a.out + ((pcw / 9) * a.M + row0) * 9;
+    if (pcw + kRegCols <= c1 && row0 + 16 * kRegRT <= a.M) {
+#pragma unroll
+      for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (p < 0 || p == rt * 2 + i / 4) obase[goff[i] + 144 * rt] = v[rt][i];
+    } else if (p <= 0) {
+      const int ncl = (int)min((int64_t)kRegCols, c1 - pcw);   // columns of the chunk in range
+#pragma unroll
+      for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int rr = spk[i] >> 11, cl = (spk[i] & 2047) / kRegStageCol;
+          if (cl < ncl && row0 + 16 * rt + rr < a.M) obase[goff[i] + 144 * rt] = v[rt][i];
+        }
+    }
+  };
+
+  // Chunk c + 1 is loaded into registers during chunk c - 1 and written to LDS at the end of chunk
+  // c, before the loads of chunk c + 2 are issued.
+  load_chunk(0);
+  store_chunk(0);
+  if (n_chunk > 1) load_chunk(1);
+  for (int c = 0; c < n_chunk; ++c) {
+    __syncthreads();   // chunk c is in its buffer; every wave is done with the other one
+    const char *bh_base = lds + (2 * (c & 1)) * CHUNK + 16 * lane;
+    const char *bl_base = bh_base + CHUNK;
+    const int64_t cw = c0 + (int64_t)c * kRegCols;
+    float cs[2] = {1.0f, 1.0f};
+    if constexpr (MODE == IGAMT_F16X3)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) cs[q] = cw + 16 * q + l16 < c1 ? a.Bscale[cw + 16 * q + l16] : 0.0f;
+    f4 acc[kRegRT][2];
+#pragma unroll
+    for (int rt = 0; rt < kRegRT; ++rt) acc[rt][0] = acc[rt][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      V8 bh[2], bl[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        bh[cb] = *(const V8 *)(bh_base + (cb * KS + ks) * 1024);
+        if constexpr (PROD != 2) bl[cb] = *(const V8 *)(bl_base + (cb * KS + ks) * 1024);
+      }
+      if constexpr (PROD == 4)
+#pragma unroll
+        for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) mma(al[rt][ks], bl[cb], acc[rt][cb]);
+#pragma unroll
+      for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) mma(al[rt][ks], bh[cb], acc[rt][cb]);
+      if constexpr (PROD != 2)
+#pragma unroll
+        for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) mma(ah[rt][ks], bl[cb], acc[rt][cb]);
+#pragma unroll
+      for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) mma(ah[rt][ks], bh[cb], acc[rt][cb]);
+      // the previous chunk's epilogue, one step per k-step, between this chunk's MFMAs
+      if (c > 0) {
+        if (ks == 0) epi1();
+        if (ks == (KS > 2 ? 1 : 0)) epi2();
+        if constexpr (KS >= 6) {
+          if (ks >= 2 && ks < 6) epi3(ks - 2);
+        } else if (ks == KS - 1) {
+          epi3(-1);
+        }
+      }
+    }
+    if (c + 1 < n_chunk) store_chunk((c + 1) & 1);   // the other buffer: read by no wave since the barrier
+    if (c + 2 < n_chunk) load_chunk(c + 2);
+#pragma unroll
+    for (int rt = 0; rt < kRegRT; ++rt) pacc[rt][0] = acc[rt][0], pacc[rt][1] = acc[rt][1];
+    pcs[0] = cs[0];
+    pcs[1] = cs[1];
+    pcw = cw;
+  }
+  epi1();
+  epi2();
+  epi3(-1);
+}
+
 static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, int prod, const void *d_coef,
                                           void *d_blocks, hipStream_t s, int64_t g0, int64_t g1) {
   SplitArgs a;
@@ -679,16 +926,22 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
   a.c_lo = g0 * BN;
   a.c_hi = std::min(g1 * BN, 9 * P->n_tiles);
   a.ncol_pad = 9 * P->n_tiles_pad;
-  a.n_rblk = (int)((P->Mp + kSplitRows - 1) / kSplitRows);
+  const int rows = IGAMT_SPLIT_REG ? kRegRows : kSplitRows;
+  a.n_rblk = (int)((P->Mp + rows - 1) / rows);
   a.n_split = 8 * std::max(1, 32 / a.n_rblk);
   a.row_bytes = (int)(2 * P->Kp + 16);
-  const size_t shm = (size_t)split_lds_bytes(P->Kp);
-  const dim3 grid((unsigned)(a.n_rblk * a.n_split)), block(64 * kSplitWaves);
+  const size_t shm = (size_t)(IGAMT_SPLIT_REG ? split_reg_lds_bytes(P->Kp) : split_lds_bytes(P->Kp));
+  const dim3 grid((unsigned)(a.n_rblk * a.n_split)), block(64 * (IGAMT_SPLIT_REG ? kRegWaves : kSplitWaves));
+#if IGAMT_SPLIT_REG
+#define SPLIT_KERNEL contract_split_reg_kernel
+#else
+#define SPLIT_KERNEL contract_split_kernel
+#endif
 #define SPLIT_LAUNCH(M_, KS_, PR_)                                                                       \
   do {                                                                                                 \
-    IGAMT_HIP(hipFuncSetAttribute((const void *)contract_split_kernel<M_, KS_, PR_>,                   \
+    IGAMT_HIP(hipFuncSetAttribute((const void *)SPLIT_KERNEL<M_, KS_, PR_>,                            \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));              \
-    hipLaunchKernelGGL((contract_split_kernel<M_, KS_, PR_>), grid, block, shm, s, a);                 \
+    hipLaunchKernelGGL((SPLIT_KERNEL<M_, KS_, PR_>), grid, block, shm, s, a);                          \
   } while (0)
   const int ks = (int)(P->Kp / 32);
   if (bf) {
@@ -706,6 +959,7 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
     else SPLIT_LAUNCH(IGAMT_F16X3, 4, 3);
   }
 #undef SPLIT_LAUNCH
+#undef SPLIT_KERNEL
   IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
