@@ -173,6 +173,22 @@ __device__ inline double f16_scale_for(double bound) {
   return ldexp(1.0, 14 - e);  // bound * scale < 2^14
 }
 
+// A_ij,ab at one sample from the rows F_i, F_j of F = J^-1 and D = det J (the Cartesian form of
+// eq. (37)).  The elasticity tensor's symmetry gives A_ij,ab = A_ji,ba; callers pass (i, a) and
+// (j, b) ordered so that 3 i + a <= 3 j + b, and the two entries come out bit-identical.
+__device__ inline double elastic_density(const double *Fi, const double *Fj, double D, int aa, int bb, double lam,
+                                         double mu) {
+  const double fij = Fi[0] * Fj[0] + Fi[1] * Fj[1] + Fi[2] * Fj[2];
+  return D * (lam * Fi[aa] * Fj[bb] + (aa == bb ? mu * fij : 0.0) + mu * Fi[bb] * Fj[aa]);
+}
+
+// a wave-uniform double moved to scalar registers
+__device__ inline double uniform_f64(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 
 // Values and first derivatives of the B-splines of degree PD[k] non-zero on span `span` of direction

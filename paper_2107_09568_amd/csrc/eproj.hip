@@ -215,6 +215,179 @@ __global__ __launch_bounds__(256) void eproj_kernel(EprojArgs a) {
   if (tid == 0) a.tile_e[t] = red[0];
 }
 
+// Isotropic macro map of degree PM and projection degree Q on Q + 1 nodes (the interpolating
+// case), with the shape known at compile time.  One 128-thread workgroup per tile.  After F and D at
+// the fit nodes and the samples (1-D bases shared as above), lane l < 45 takes one of the 45 index
+// pairs (u, v) = (3 i + a, 3 j + b), u <= v: it evaluates A_ij,ab (= A_ji,ba) at the fit nodes and
+// projects it with three 1-D passes in registers (as the fit does), into LDS.  Then one thread per
+// sample: the tensor Bernstein weights of its sample in registers, and over the 45 pairs the exact
+// value, the projected one and their squared difference, counted twice for u < v (the (j, i) block
+// holds the same entries).
+constexpr int kEprojQThreads = 128;
+
+template <int PM, int Q>
+__global__ __launch_bounds__(kEprojQThreads) void eproj_q_kernel(EprojArgs a) {
+  constexpr int NF = Q + 1, NFIT = NF * NF * NF;
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, ns1 = a.n_s, nsmp = ns1 * ns1 * ns1;
+  double *FDf = smem;               // [NFIT][10]
+  double *FDs = FDf + NFIT * 10;    // [nsmp][10]
+  double *cf = FDs + nsmp * 10;     // [45][NFIT] coefficients of the 45 pairs
+  __shared__ double NB[3][kMaxFit + kMaxSample][2][PM + 1];
+  __shared__ int SP[3][kMaxFit + kMaxSample];
+  __shared__ double Bs[3][kMaxSample][Q + 1];
+  __shared__ double red[kEprojQThreads / 64];
+  const int64_t t = blockIdx.x;
+  const int tt[3] = {(int)(t % a.tiles[0]), (int)((t / a.tiles[0]) % a.tiles[1]),
+                     (int)(t / ((int64_t)a.tiles[0] * a.tiles[1]))};
+  const double ax[3] = {a.box_a[0][tt[0]], a.box_a[1][tt[1]], a.box_a[2][tt[2]]};
+  const double hx[3] = {a.box_h[0][tt[0]], a.box_h[1][tt[1]], a.box_h[2][tt[2]]};
+  const int n1 = NF + ns1;
+  for (int e = tid; e < 3 * n1; e += kEprojQThreads) {
+    const int d = e / n1, m = e - d * n1;
+    const double x = (d == 0 ? ax[0] : d == 1 ? ax[1] : ax[2]) +
+                     (d == 0 ? hx[0] : d == 1 ? hx[1] : hx[2]) * (m < NF ? a.fx[m] : a.sx[m - NF]);
+    const int sp = find_span(a.knots[d], a.nM[d], PM, x);
+    double N[PM + 1], dN[PM + 1];
+    bspline_ders<PM>(a.knots[d], sp, x, N, dN);
+    SP[d][m] = sp;
+#pragma unroll
+    for (int r = 0; r <= PM; ++r) {
+      NB[d][m][0][r] = N[r];
+      NB[d][m][1][r] = dN[r];
+    }
+  }
+  for (int e = tid; e < 3 * ns1; e += kEprojQThreads) {
+    const int k = e / ns1, m = e % ns1;
+    double B[kMaxQ + 1];
+    bernstein(Q, a.sx[m], B);
+#pragma unroll
+    for (int c = 0; c <= Q; ++c) Bs[k][m][c] = B[c];
+  }
+  __syncthreads();
+  for (int e = tid; e < NFIT + nsmp; e += kEprojQThreads) {
+    int mi[3];
+    double *FD;
+    if (e < NFIT) {
+      mi[0] = e % NF, mi[1] = (e / NF) % NF, mi[2] = e / (NF * NF);
+      FD = FDf + e * 10;
+    } else {
+      const int k = e - NFIT;
+      mi[0] = NF + k % ns1, mi[1] = NF + (k / ns1) % ns1, mi[2] = NF + k / (ns1 * ns1);
+      FD = FDs + k * 10;
+    }
+    int span[3];
+    double N[3][PM + 1], dN[3][PM + 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      span[k] = SP[k][mi[k]];
+#pragma unroll
+      for (int r = 0; r <= PM; ++r) {
+        N[k][r] = NB[k][mi[k]][0][r];
+        dN[k][r] = NB[k][mi[k]][1][r];
+      }
+    }
+    double J[3][3];
+    spline_jacobian_sum<PM, PM, PM, true>(a.nM, a.ctrl, a.wts, span, N, dN, J);
+    point_FD_store(a, hx, J, FD, t);
+  }
+  __syncthreads();
+
+  // the 45 pairs' projection coefficients
+  if (tid < 45) {
+    int u = 0, rem = tid;
+    while (rem >= 9 - u) { rem -= 9 - u; ++u; }
+    const int v = u + rem;
+    const int i = u / 3, aa = u % 3, j = v / 3, bb = v % 3;
+    double P[NF][NF];   // the 1-D operator, the same in every direction here (checked by the launcher)
+#pragma unroll
+    for (int c = 0; c < NF; ++c)
+#pragma unroll
+      for (int q = 0; q < NF; ++q) P[c][q] = uniform_f64(a.fP[c * NF + q]);
+    double val[NFIT];
+#pragma unroll
+    for (int q = 0; q < NFIT; ++q)
+      val[q] = elastic_density(FDf + q * 10 + 3 * i, FDf + q * 10 + 3 * j, FDf[q * 10 + 9], aa, bb, a.lam, a.mu);
+#pragma unroll
+    for (int l = 0; l < NF * NF; ++l) {   // x
+      double o[NF];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        double w = 0.0;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) w += P[c][q] * val[l * NF + q];
+        o[c] = w;
+      }
+#pragma unroll
+      for (int c = 0; c < NF; ++c) val[l * NF + c] = o[c];
+    }
+#pragma unroll
+    for (int s3 = 0; s3 < NF; ++s3)   // y
+#pragma unroll
+      for (int c1 = 0; c1 < NF; ++c1) {
+        double o[NF];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) {
+          double w = 0.0;
+#pragma unroll
+          for (int q = 0; q < NF; ++q) w += P[c][q] * val[(s3 * NF + q) * NF + c1];
+          o[c] = w;
+        }
+#pragma unroll
+        for (int c = 0; c < NF; ++c) val[(s3 * NF + c) * NF + c1] = o[c];
+      }
+#pragma unroll
+    for (int l = 0; l < NF * NF; ++l) {   // z
+      double o[NF];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        double w = 0.0;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) w += P[c][q] * val[q * NF * NF + l];
+        o[c] = w;
+      }
+#pragma unroll
+      for (int c = 0; c < NF; ++c) val[c * NF * NF + l] = o[c];
+    }
+#pragma unroll
+    for (int C = 0; C < NFIT; ++C) cf[tid * NFIT + C] = val[C];
+  }
+  __syncthreads();
+
+  // one thread per sample
+  double m = 0.0;
+  for (int k = tid; k < nsmp; k += kEprojQThreads) {
+    const int k0 = k % ns1, k1 = (k / ns1) % ns1, k2 = k / (ns1 * ns1);
+    double W[NFIT];
+#pragma unroll
+    for (int C = 0; C < NFIT; ++C) W[C] = Bs[0][k0][C % NF] * Bs[1][k1][(C / NF) % NF] * Bs[2][k2][C / (NF * NF)];
+    const double *F = FDs + k * 10;
+    double e2 = 0.0, n2 = 0.0;
+    int u = 0, v = 0;   // the pair of index l, row-major over u <= v
+#pragma unroll 1
+    for (int l = 0; l < 45; ++l) {
+      const double ex = elastic_density(F + 3 * (u / 3), F + 3 * (v / 3), F[9], u % 3, v % 3, a.lam, a.mu);
+      double pr = 0.0;
+#pragma unroll
+      for (int C = 0; C < NFIT; ++C) pr += cf[l * NFIT + C] * W[C];
+      const double d = ex - pr, w = u == v ? 1.0 : 2.0;
+      e2 += w * d * d;
+      n2 += w * ex * ex;
+      if (++v == 9) v = ++u;
+    }
+    m = fmax(m, sqrt(e2 / n2));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double r = red[0];
+    for (int w = 1; w < kEprojQThreads / 64; ++w) r = fmax(r, red[w]);
+    a.tile_e[t] = r;
+  }
+}
+
 __global__ __launch_bounds__(256) void max_kernel(const double *x, int64_t n, double *out) {
   __shared__ double red[256];
   double m = 0.0;
@@ -274,6 +447,31 @@ static igamt_status eproj_run(igamt_plan *P, double E, double nu, const int (&q)
   a.tile_e = d_tile_e ? d_tile_e : buf;
   a.flag = P->dev.flag;
   const int nfit = nf * nf * nf, nsmp = n_s * n_s * n_s;
+  // isotropic macro map and degree q <= 3: the compile-time shape
+  if (P->pM[0] == P->pM[1] && P->pM[0] == P->pM[2] && q[0] == q[1] && q[0] == q[2] && q[0] >= 1 && q[0] <= 3) {
+    const size_t shmq = (size_t)(10 * nfit + 10 * nsmp + 45 * nfit) * sizeof(double);
+    const dim3 gq((unsigned)P->n_tiles), bq(kEprojQThreads);
+    switch (P->pM[0] * 8 + q[0]) {
+#define EPQ_CASE(pm, qq)                                                                                  \
+  case pm * 8 + qq:                                                                                       \
+    if (shmq > 65536)                                                                                     \
+      IGAMT_HIP(hipFuncSetAttribute((const void *)eproj_q_kernel<pm, qq>,                                 \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmq));              \
+    hipLaunchKernelGGL((eproj_q_kernel<pm, qq>), gq, bq, shmq, s, a);                                     \
+    break;
+#define EPQ_DEG(pm) EPQ_CASE(pm, 1) EPQ_CASE(pm, 2) EPQ_CASE(pm, 3)
+      EPQ_DEG(1) EPQ_DEG(2) EPQ_DEG(3) EPQ_DEG(4) EPQ_DEG(5) EPQ_DEG(6)
+#undef EPQ_DEG
+#undef EPQ_CASE
+      default: set_error("unsupported macro degree"); return IGAMT_EUNSUPPORTED;
+    }
+    IGAMT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, a.tile_e, P->n_tiles, d_res);
+    IGAMT_LAUNCH_CHECK();
+    IGAMT_HIP(hipMemcpyAsync(e_out, d_res, sizeof(double), hipMemcpyDeviceToHost, s));
+    IGAMT_HIP(hipStreamSynchronize(s));   // the host vectors above and *e_out are used until here
+    return IGAMT_OK;
+  }
   const size_t shm = (size_t)(10 * nfit + 10 * nsmp + 2 * nsmp + 2 * 9 * std::max(nfit, nsmp)) * sizeof(double);
   const dim3 grid((unsigned)P->n_tiles), block(256);
   switch (IGAMT_DEGREE_KEY(P->pM[0], P->pM[1], P->pM[2])) {
