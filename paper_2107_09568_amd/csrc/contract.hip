@@ -24,6 +24,7 @@
 // last-level cache.
 #include <algorithm>
 #include <atomic>
+#include <numeric>
 
 #include "device_common.h"
 
@@ -463,7 +464,7 @@ struct SplitArgs {
   int64_t M, Mp, Kp;
   int64_t c_lo, c_hi;        // columns of this launch (tile groups of a slab, or all)
   int64_t ncol_pad;          // coefficient columns in memory (9 n_tiles_pad, a multiple of 16)
-  int n_rblk, n_split;       // row blocks of 112 rows; column splits (a multiple of 8)
+  int n_rblk, n_split;       // row blocks; column splits (a multiple of 8)
   int row_bytes;             // LDS bytes of one table row of one plane (2 Kp + 16)
 };
 
@@ -693,16 +694,14 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int64_t Kp = 32 * KS;
   constexpr int CHUNK = kRegCols * (int)Kp * 2;          // bytes of one plane of one chunk
-  const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
-  const int rb = slot % a.n_rblk, s = (slot / a.n_rblk) * 8 + xcd;
-  if (s >= a.n_split) return;
+  // Persistent: the workgroups of one XCD (blockIdx.x mod 8) take the units (row block rb, column
+  // split s = 8 j + xcd) of their XCD in turn, rb fastest, so that the row blocks of a column split
+  // run at about the same time on one L2 and read its coefficients once.
+  const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3, per_xcd = (int)(gridDim.x >> 3);
+  const int n_unit = a.n_rblk * (a.n_split / 8);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
-  const int64_t row0 = (int64_t)rb * kRegRows + 32 * wave;   // this wave's first row
-  const int64_t units = (a.c_hi - a.c_lo + 15) / 16;
-  const int64_t c0 = a.c_lo + 16 * (units * s / a.n_split);
-  const int64_t c1 = min(a.c_hi, a.c_lo + 16 * (units * (s + 1) / a.n_split));
-  if (c1 <= c0) return;
-  const int n_chunk = (int)((c1 - c0 + kRegCols - 1) / kRegCols);
+  const int64_t n16 = (a.c_hi - a.c_lo + 15) / 16;   // 16-column blocks of the launch
+  int64_t row0 = 0, c0 = 0, c1 = 0;                  // this wave's first row; the unit's columns
   float *stage = (float *)(lds + 4 * CHUNK) + wave * 32 * kRegStageCol;   // [32 columns][32 rows + pad]
 
   // the chunk's two planes: 2 column blocks x KS k-steps x 512 elements, contiguous per block
@@ -728,27 +727,10 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
     }
   };
 
-  // this wave's table rows: lane (l16, kq) holds row 16 rt + l16, k 32 ks + 8 kq .. + 7
+  // this wave's table rows (loaded per unit): lane (l16, kq) holds row 16 rt + l16, k 32 ks + 8 kq .. + 7
   V8 ah[kRegRT][KS], al[kRegRT][KS];
-#pragma unroll
-  for (int rt = 0; rt < kRegRT; ++rt) {
-    const int64_t r = row0 + 16 * rt + l16;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int64_t off = r * Kp + 32 * ks + 8 * kq;
-      if (r < a.Mp) {
-        ah[rt][ks] = *(const V8 *)(a.Ah + off);
-        al[rt][ks] = *(const V8 *)(a.Al + off);
-      } else {
-        ah[rt][ks] = V8{};
-        al[rt][ks] = V8{};
-      }
-    }
-  }
   // F16X3: the inverse row scales of the wave's 32 rows, in LDS after the stage
   float *rsl = (float *)(lds + 4 * CHUNK) + kRegWaves * 32 * kRegStageCol + 32 * wave;
-  if constexpr (MODE == IGAMT_F16X3)
-    if (lane < 32) rsl[lane] = row0 + lane < a.Mp ? a.Ascale[row0 + lane] : 0.0f;
   auto mma = [&](const V8 &x, const V8 &y, f4 &c) {
     if constexpr (MODE == IGAMT_BF16X3)
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
@@ -840,9 +822,37 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
     }
   };
 
+  for (int u = slot; u < n_unit; u += per_xcd) {
+  const int rb = u % a.n_rblk, s = (u / a.n_rblk) * 8 + xcd;
+  row0 = (int64_t)rb * kRegRows + 32 * wave;
+  c0 = a.c_lo + 16 * (n16 * s / a.n_split);
+  c1 = min(a.c_hi, a.c_lo + 16 * (n16 * (s + 1) / a.n_split));
+  if (c1 <= c0) continue;   // the same for every wave of the workgroup
+  const int n_chunk = (int)((c1 - c0 + kRegCols - 1) / kRegCols);
+#pragma unroll
+  for (int rt = 0; rt < kRegRT; ++rt) {
+    const int64_t r = row0 + 16 * rt + l16;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int64_t off = r * Kp + 32 * ks + 8 * kq;
+      if (r < a.Mp) {
+        ah[rt][ks] = *(const V8 *)(a.Ah + off);
+        al[rt][ks] = *(const V8 *)(a.Al + off);
+      } else {
+        ah[rt][ks] = V8{};
+        al[rt][ks] = V8{};
+      }
+    }
+  }
+  // (the wave's last epilogue of the previous unit has read its scales: LDS accesses of one wave
+  // complete in order)
+  if constexpr (MODE == IGAMT_F16X3)
+    if (lane < 32) rsl[lane] = row0 + lane < a.Mp ? a.Ascale[row0 + lane] : 0.0f;
+
   // Chunk c + 1 is loaded into registers during chunk c - 1 and written to LDS at the end of chunk
   // c, before the loads of chunk c + 2 are issued.
   load_chunk(0);
+  __syncthreads();   // every wave is done with the previous unit's chunk buffers
   store_chunk(0);
   if (n_chunk > 1) load_chunk(1);
   for (int c = 0; c < n_chunk; ++c) {
@@ -905,6 +915,20 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
   epi1();
   epi2();
   epi3(-1);
+  }
+}
+
+// compute units of the current device, queried once per device
+static int device_cus() {
+  static std::atomic<int> cus[64];   // 0: not yet queried
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int n = cus[dev & 63].load(std::memory_order_relaxed);
+  if (n == 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev & 63].store(n, std::memory_order_relaxed);
+  }
+  return n;
 }
 
 static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, int prod, const void *d_coef,
@@ -928,10 +952,24 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
   a.ncol_pad = 9 * P->n_tiles_pad;
   const int rows = IGAMT_SPLIT_REG ? kRegRows : kSplitRows;
   a.n_rblk = (int)((P->Mp + rows - 1) / rows);
-  a.n_split = 8 * std::max(1, 32 / a.n_rblk);
   a.row_bytes = (int)(2 * P->Kp + 16);
+  unsigned n_wg;
+  if (IGAMT_SPLIT_REG) {
+    // one workgroup per CU; per XCD, n_rblk x R units over its G workgroups with R = G / gcd(n_rblk, G)
+    // (every workgroup takes the same number of units), fewer splits where units would fall below
+    // 8 chunks of columns
+    const int G = std::max(1, device_cus() / 8);
+    int R = G / std::gcd(a.n_rblk, G);
+    const int64_t cols = a.c_hi - a.c_lo;
+    while (R > 1 && cols / (8 * R) < 8 * kRegCols) R /= 2;
+    a.n_split = 8 * R;
+    n_wg = (unsigned)(8 * std::min<int64_t>(G, (int64_t)a.n_rblk * R));
+  } else {
+    a.n_split = 8 * std::max(1, 32 / a.n_rblk);
+    n_wg = (unsigned)(a.n_rblk * a.n_split);
+  }
   const size_t shm = (size_t)(IGAMT_SPLIT_REG ? split_reg_lds_bytes(P->Kp) : split_lds_bytes(P->Kp));
-  const dim3 grid((unsigned)(a.n_rblk * a.n_split)), block(64 * (IGAMT_SPLIT_REG ? kRegWaves : kSplitWaves));
+  const dim3 grid(n_wg), block(64 * (IGAMT_SPLIT_REG ? kRegWaves : kSplitWaves));
 #if IGAMT_SPLIT_REG
 #define SPLIT_KERNEL contract_split_reg_kernel
 #else
@@ -969,17 +1007,8 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
 static unsigned contract_grid(igamt_precision prec, const ContractArgs &a) {
   const int64_t items_x = (int64_t)(a.n_groups + 7) / 8 * a.n_mblk;
   int64_t slots = items_x;
-  if (prec == IGAMT_F64 && kPersist<IGAMT_F64> && a.Kp / Mode<IGAMT_F64>::KCH >= 2) {   // two chunks per item
-    static std::atomic<int> cus[64];   // CU count per device, queried once (0: not yet)
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    int n = cus[dev & 63].load(std::memory_order_relaxed);
-    if (n == 0) {
-      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-      cus[dev & 63].store(n, std::memory_order_relaxed);
-    }
-    slots = std::min<int64_t>(items_x, std::max(1, n / 8));
-  }
+  if (prec == IGAMT_F64 && kPersist<IGAMT_F64> && a.Kp / Mode<IGAMT_F64>::KCH >= 2)   // two chunks per item
+    slots = std::min<int64_t>(items_x, std::max(1, device_cus() / 8));
   return (unsigned)(8 * slots);
 }
 
