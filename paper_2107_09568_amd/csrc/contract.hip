@@ -160,8 +160,8 @@ template <int MODE, bool SPLIT = (MODE == IGAMT_BF16X3 || MODE == IGAMT_F16X3)>
 struct Frag;
 template <int MODE>
 struct Frag<MODE, false> {
-  // A is prefetched a k-step ahead; B fragments are read from LDS inside mma, one k-slice ahead:
-  // two whole fragment sets do not fit the register file next to the accumulators.
+  // A is prefetched a k-step ahead; B fragments are read from LDS inside mma (FP64 one k-slice
+  // ahead): two whole fragment sets do not fit the register file next to the accumulators.
   using E = typename Mode<MODE>::E;
   static constexpr int WM = Mode<MODE>::WM;
   E av[WM][4];
@@ -173,27 +173,43 @@ struct Frag<MODE, false> {
       for (int s = 0; s < 4; ++s) av[mi][s] = src[s];
     }
   }
-  // consecutive MFMAs update different accumulators (18 apart)
+  // consecutive MFMAs update different accumulators (9 or 18 apart)
   __device__ inline void mma(typename Mode<MODE>::Acc (&acc)[WM][9], const char *buf, int l16, int kq, int kk) const {
-    E b[2][9];
+    if constexpr (MODE == IGAMT_F64) {
+      // one 8-byte read per column block and k-slice, the next slice's reads issued before this
+      // slice's MFMAs (16-byte reads of two slices at once avoid the bank conflicts of these reads,
+      // 4 lanes on each bank pair, but lose the look-ahead: 9.05-9.15 against 8.95 ms)
+      E b[2][9];
 #pragma unroll
-    for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq);
+      for (int ni = 0; ni < 9; ++ni) b[0][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (s + 1 < 4) {
+      for (int s = 0; s < 4; ++s) {
+        if (s + 1 < 4) {
 #pragma unroll
-        for (int ni = 0; ni < 9; ++ni)
-          b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq + s + 1);
-      }
-#pragma unroll
-      for (int mi = 0; mi < WM; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 9; ++ni) {
-          if constexpr (MODE == IGAMT_F64)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
-          else
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+          for (int ni = 0; ni < 9; ++ni)
+            b[(s + 1) & 1][ni] = *((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq + s + 1);
         }
+#pragma unroll
+        for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 9; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mi][s], b[s & 1][ni], acc[mi][ni], 0, 0, 0);
+      }
+    } else {
+      // FP32: lane (l16, kq) takes the four k = kk + 4 kq + s in one 16-byte read per column block;
+      // with the 16-byte row padding a quarter wave (l16 = 0..15) reads 16 different 4-bank groups,
+      // so the reads are free of bank conflicts (4-byte reads put 4 lanes on each bank)
+      typedef float f4v __attribute__((ext_vector_type(4)));
+      f4v b[9];
+#pragma unroll
+      for (int ni = 0; ni < 9; ++ni) b[ni] = *(const f4v *)((const E *)(buf + (ni * 16 + l16) * kLdsRow<MODE>) + kk + 4 * kq);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 9; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mi][s], b[ni][s], acc[mi][ni], 0, 0, 0);
     }
   }
 };
