@@ -472,6 +472,7 @@ constexpr int kSplitWC = 16 * kSplitNCB;               // columns per wave and p
 constexpr int kStageCol = 20;                          // words per column of a wave's epilogue stage
 
 struct SplitArgs {
+  const float *Af, *Bf;      // FP32: table [Mp][Kp] and coefficients [9 n_tiles_pad][Kp]
   const uint16_t *Ah, *Al;   // table planes [Mp][Kp]
   const float *Ascale;       // F16X3 inverse row scales [Mp]
   const uint16_t *Bh, *Bl;   // coefficient planes, tiled (split_coef_index)
@@ -692,24 +693,37 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void contract_split_kernel(Spl
 #ifndef IGAMT_SPLIT_REG
 #define IGAMT_SPLIT_REG 1
 #endif
+#ifndef IGAMT_F32_REG
+#define IGAMT_F32_REG 1   // FP32 (K = 128 or 256) on this kernel too, the table as FP32 in registers
+#endif
 constexpr int kRegWaves = 8;                             // waves per workgroup
 constexpr int kRegRT = 2;                                // 16-row tiles per wave
 constexpr int kRegRows = 16 * kRegRT * kRegWaves;        // 256 table rows per workgroup
 constexpr int kRegCols = 32;                             // columns per chunk (two column blocks)
 constexpr int kRegStageCol = 36;                         // words per column of a wave's stage (32 rows + pad)
 
-// two B chunk buffers (two planes each), one epilogue stage of 32 columns x 32 rows per wave, then
-// each wave's 32 inverse row scales (F16X3)
-__host__ __device__ inline int64_t split_reg_lds_bytes(int64_t Kp) {
-  return 2 * 2 * kRegCols * Kp * 2 + 4 * kRegWaves * 32 * kRegStageCol + 4 * kRegWaves * 32;
+// bytes of one B chunk buffer: the split modes' two planes (2 bytes per element, the tiled layout),
+// or FP32 columns of Kp floats padded by 16 bytes (so that the 16-byte fragment reads of a quarter
+// wave fall on 16 different 4-bank groups)
+__host__ __device__ constexpr int64_t reg_chunk_buf_bytes(bool f32, int64_t Kp) {
+  return f32 ? kRegCols * (4 * Kp + 16) : 2 * kRegCols * Kp * 2;
+}
+// two B chunk buffers, one epilogue stage of 32 columns x 32 rows per wave, then each wave's 32
+// inverse row scales (F16X3)
+__host__ __device__ inline int64_t split_reg_lds_bytes(bool f32, int64_t Kp) {
+  return 2 * reg_chunk_buf_bytes(f32, Kp) + 4 * kRegWaves * 32 * kRegStageCol + 4 * kRegWaves * 32;
 }
 
 template <int MODE, int KS, int PROD>
 __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(SplitArgs a) {
   using V8 = typename std::conditional<MODE == IGAMT_BF16X3, bf16x8, f16x8>::type;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  constexpr bool F32 = MODE == IGAMT_F32;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int64_t Kp = 32 * KS;
-  constexpr int CHUNK = kRegCols * (int)Kp * 2;          // bytes of one plane of one chunk
+  constexpr int CHUNK = kRegCols * (int)Kp * 2;          // bytes of one plane of one chunk (split modes)
+  constexpr int BUFB = (int)reg_chunk_buf_bytes(F32, Kp);   // bytes of one chunk buffer
+  constexpr int COLB = 4 * (int)Kp + 16;                 // FP32: bytes of one padded column in LDS
   // Persistent: the workgroups of one XCD (blockIdx.x mod 8) take the units (row block rb, column
   // split s = 8 j + xcd) of their XCD in turn, rb fastest, so that the row blocks of a column split
   // run at about the same time on one L2 and read its coefficients once.
@@ -718,35 +732,51 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, kq = lane >> 4;
   const int64_t n16 = (a.c_hi - a.c_lo + 15) / 16;   // 16-column blocks of the launch
   int64_t row0 = 0, c0 = 0, c1 = 0;                  // this wave's first row; the unit's columns
-  float *stage = (float *)(lds + 4 * CHUNK) + wave * 32 * kRegStageCol;   // [32 columns][32 rows + pad]
+  float *stage = (float *)(lds + 2 * BUFB) + wave * 32 * kRegStageCol;   // [32 columns][32 rows + pad]
 
   // the chunk's two planes: 2 column blocks x KS k-steps x 512 elements, contiguous per block
   constexpr int PIECES = CHUNK / 16;                     // 16-byte pieces per plane
   constexpr int NPRE = 2 * PIECES / (64 * kRegWaves);    // pieces per thread, both planes
   static_assert(2 * PIECES % (64 * kRegWaves) == 0, "chunk pieces must divide over the workgroup");
   u32x4 pre[NPRE];
+  // (FP32: the same number of 16-byte pieces, Kp / 4 per column; thread tid takes column tid / 16,
+  // pieces tid % 16 + 16 i, so that its pieces share one base address)
+  static_assert(!F32 || Kp / 4 == 16 * NPRE, "FP32 chunk pieces per thread");
   auto load_chunk = [&](int c) {
 #pragma unroll
     for (int i = 0; i < NPRE; ++i) {
-      const int e = tid + i * 64 * kRegWaves, pl = e / PIECES, j = e - pl * PIECES;
-      const int cb = j / (KS * 64), jj = j - cb * KS * 64;   // column block, piece within it
-      int64_t col = c0 + (int64_t)c * kRegCols + 16 * cb;
-      col = min(col, a.ncol_pad - 16);   // past the range: a valid block, its result is not stored
-      pre[i] = *(const u32x4 *)((pl ? a.Bl : a.Bh) + (col >> 4) * KS * 512 + 8 * jj);
+      const int e = tid + i * 64 * kRegWaves;
+      if constexpr (F32) {
+        const int64_t col = min(c0 + (int64_t)c * kRegCols + (tid >> 4), a.ncol_pad - 1);   // past the range: not stored
+        pre[i] = *(const u32x4 *)(a.Bf + col * Kp + 4 * (tid & 15) + 64 * i);
+      } else {
+        const int pl = e / PIECES, j = e - pl * PIECES;
+        const int cb = j / (KS * 64), jj = j - cb * KS * 64;   // column block, piece within it
+        int64_t col = c0 + (int64_t)c * kRegCols + 16 * cb;
+        col = min(col, a.ncol_pad - 16);   // past the range: a valid block, its result is not stored
+        pre[i] = *(const u32x4 *)((pl ? a.Bl : a.Bh) + (col >> 4) * KS * 512 + 8 * jj);
+      }
     }
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < NPRE; ++i) {
-      const int e = tid + i * 64 * kRegWaves, pl = e / PIECES, j = e - pl * PIECES;
-      *(u32x4 *)(lds + (2 * buf + pl) * CHUNK + 16 * j) = pre[i];
+      const int e = tid + i * 64 * kRegWaves;
+      if constexpr (F32) {
+        *(u32x4 *)(lds + buf * BUFB + (tid >> 4) * COLB + 16 * (tid & 15) + 256 * i) = pre[i];
+      } else {
+        const int pl = e / PIECES, j = e - pl * PIECES;
+        *(u32x4 *)(lds + buf * BUFB + pl * CHUNK + 16 * j) = pre[i];
+      }
     }
   };
 
   // this wave's table rows (loaded per unit): lane (l16, kq) holds row 16 rt + l16, k 32 ks + 8 kq .. + 7
+  // (FP32: af, k 16 s + 4 kq .. + 3 of each 16-k block s; the unused set takes no registers)
   V8 ah[kRegRT][KS], al[kRegRT][KS];
+  f4v af[kRegRT][2 * KS];
   // F16X3: the inverse row scales of the wave's 32 rows, in LDS after the stage
-  float *rsl = (float *)(lds + 4 * CHUNK) + kRegWaves * 32 * kRegStageCol + 32 * wave;
+  float *rsl = (float *)(lds + 2 * BUFB) + kRegWaves * 32 * kRegStageCol + 32 * wave;
   auto mma = [&](const V8 &x, const V8 &y, f4 &c) {
     if constexpr (MODE == IGAMT_BF16X3)
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
@@ -850,13 +880,19 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
     const int64_t r = row0 + 16 * rt + l16;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int64_t off = r * Kp + 32 * ks + 8 * kq;
-      if (r < a.Mp) {
-        ah[rt][ks] = *(const V8 *)(a.Ah + off);
-        al[rt][ks] = *(const V8 *)(a.Al + off);
+      if constexpr (F32) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          af[rt][2 * ks + h] = r < a.Mp ? *(const f4v *)(a.Af + r * Kp + 32 * ks + 16 * h + 4 * kq) : f4v{};
       } else {
-        ah[rt][ks] = V8{};
-        al[rt][ks] = V8{};
+        const int64_t off = r * Kp + 32 * ks + 8 * kq;
+        if (r < a.Mp) {
+          ah[rt][ks] = *(const V8 *)(a.Ah + off);
+          al[rt][ks] = *(const V8 *)(a.Al + off);
+        } else {
+          ah[rt][ks] = V8{};
+          al[rt][ks] = V8{};
+        }
       }
     }
   }
@@ -873,8 +909,9 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
   if (n_chunk > 1) load_chunk(1);
   for (int c = 0; c < n_chunk; ++c) {
     __syncthreads();   // chunk c is in its buffer; every wave is done with the other one
-    const char *bh_base = lds + (2 * (c & 1)) * CHUNK + 16 * lane;
+    const char *bh_base = lds + (c & 1) * BUFB + 16 * lane;
     const char *bl_base = bh_base + CHUNK;
+    const char *bf_base = lds + (c & 1) * BUFB + l16 * COLB + 16 * kq;   // FP32: column l16, k 4 kq
     const int64_t cw = c0 + (int64_t)c * kRegCols;
     float cs[2] = {1.0f, 1.0f};
     if constexpr (MODE == IGAMT_F16X3)
@@ -885,6 +922,23 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
     for (int rt = 0; rt < kRegRT; ++rt) acc[rt][0] = acc[rt][1] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
+      if constexpr (F32) {
+        // two 16-k blocks; lane (l16, kq) holds k = 16 s + 4 kq + t of column l16, the t-th MFMA
+        // of a block takes k-slice {16 s + 4 kq + t : kq} (A holds the same k)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          f4v b[2];
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) b[cb] = *(const f4v *)(bf_base + cb * 16 * COLB + (32 * ks + 16 * h) * 4);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int rt = 0; rt < kRegRT; ++rt)
+#pragma unroll
+              for (int cb = 0; cb < 2; ++cb)
+                acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rt][2 * ks + h][t], b[cb][t], acc[rt][cb], 0, 0, 0);
+        }
+      } else {
       V8 bh[2], bl[2];
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
@@ -909,6 +963,7 @@ __global__ __launch_bounds__(64 * kRegWaves, 1) void contract_split_reg_kernel(S
       for (int rt = 0; rt < kRegRT; ++rt)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) mma(ah[rt][ks], bh[cb], acc[rt][cb]);
+      }
       // the previous chunk's epilogue, one step per k-step, between this chunk's MFMAs
       if (c > 0) {
         if (ks == 0) epi1();
@@ -953,12 +1008,15 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
   const int64_t MK = P->Mp * P->Kp;
   const int64_t plane = P->n_tiles_pad * 9 * P->Kp;
   const bool bf = prec == IGAMT_BF16X3;
-  a.Ah = bf ? P->dev.table_bf : P->dev.table_h;
-  a.Al = a.Ah + MK;
-  a.Ascale = bf ? nullptr : P->dev.table_h_scale;
-  a.Bh = (const uint16_t *)d_coef;
-  a.Bl = a.Bh + plane;
-  a.Bscale = bf ? nullptr : (const float *)(a.Bh + 2 * plane);
+  const bool f32 = prec == IGAMT_F32;   // FP32 with the table in registers (not split)
+  a.Af = f32 ? P->dev.table_f32 : nullptr;
+  a.Bf = f32 ? (const float *)d_coef : nullptr;
+  a.Ah = f32 ? nullptr : bf ? P->dev.table_bf : P->dev.table_h;
+  a.Al = f32 ? nullptr : a.Ah + MK;
+  a.Ascale = f32 || bf ? nullptr : P->dev.table_h_scale;
+  a.Bh = f32 ? nullptr : (const uint16_t *)d_coef;
+  a.Bl = f32 ? nullptr : a.Bh + plane;
+  a.Bscale = f32 || bf ? nullptr : (const float *)(a.Bh + 2 * plane);
   a.out = (float *)d_blocks;
   a.M = P->n_pairs;
   a.Mp = P->Mp;
@@ -984,7 +1042,7 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
     a.n_split = 8 * std::max(1, 32 / a.n_rblk);
     n_wg = (unsigned)(a.n_rblk * a.n_split);
   }
-  const size_t shm = (size_t)(IGAMT_SPLIT_REG ? split_reg_lds_bytes(P->Kp) : split_lds_bytes(P->Kp));
+  const size_t shm = (size_t)(IGAMT_SPLIT_REG ? split_reg_lds_bytes(f32, P->Kp) : split_lds_bytes(P->Kp));
   const dim3 grid(n_wg), block(64 * (IGAMT_SPLIT_REG ? kRegWaves : kSplitWaves));
 #if IGAMT_SPLIT_REG
 #define SPLIT_KERNEL contract_split_reg_kernel
@@ -998,6 +1056,12 @@ static igamt_status launch_contract_split(igamt_plan *P, igamt_precision prec, i
     hipLaunchKernelGGL((SPLIT_KERNEL<M_, KS_, PR_>), grid, block, shm, s, a);                          \
   } while (0)
   const int ks = (int)(P->Kp / 32);
+#if IGAMT_SPLIT_REG
+  if (f32) {
+    if (ks == 8) SPLIT_LAUNCH(IGAMT_F32, 8, 3);
+    else SPLIT_LAUNCH(IGAMT_F32, 4, 3);
+  } else
+#endif
   if (bf) {
     if (ks == 8) {
       if (prod == 3) SPLIT_LAUNCH(IGAMT_BF16X3, 8, 3);
@@ -1064,7 +1128,8 @@ igamt_status launch_contract(igamt_plan *P, igamt_precision prec, const void *d_
       break;
     default: set_error("unknown precision"); return IGAMT_EINVAL;
   }
-  if ((prec == IGAMT_BF16X3 || prec == IGAMT_F16X3) && split_tiled(P->Kp))
+  if ((prec == IGAMT_BF16X3 || prec == IGAMT_F16X3 || (prec == IGAMT_F32 && IGAMT_SPLIT_REG && IGAMT_F32_REG)) &&
+      split_tiled(P->Kp))
     return launch_contract_split(P, prec, 3, d_coef, d_blocks, (hipStream_t)stream, g0, g1);
   const int bm = prec == IGAMT_F64 ? kBM<IGAMT_F64> : prec == IGAMT_F32 ? kBM<IGAMT_F32> : kBM<IGAMT_BF16X3>;
   if (P->Mp % bm != 0) { set_error("padded table rows are not a multiple of the row block"); return IGAMT_EINVAL; }
