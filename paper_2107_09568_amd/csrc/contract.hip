@@ -678,7 +678,7 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void contract_split_kernel(Spl
   }
 }
 
-// ---- split modes with the table resident in registers ---------------------------------------
+// ---- split modes (and FP32) with the table resident in registers -----------------------------
 // The LDS-resident variant above shares every coefficient column among the 112 table rows one CU
 // holds, so each column crosses that CU's L1 once per 112 rows, and that stream bounds it.  Here
 // each of the workgroup's 8 waves keeps 32 table rows (hi and lo planes, all k: 128 registers per
@@ -689,7 +689,9 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void contract_split_kernel(Spl
 // (two row tiles, three products).  A chunk's epilogue runs during the next chunk's first k-steps
 // (its accumulators are kept aside), so its stage traffic and stores overlap that chunk's MFMAs.
 // Workgroups of one XCD take every row block of their column splits, so each column is fetched
-// into that XCD's L2 once.
+// into that XCD's L2 once.  FP32 (K = 128 or 256) runs the same kernel: its table rows are FP32 (the
+// same 128 registers per lane), its coefficient chunks plain columns padded in LDS, and each k-step
+// of 32 issues 32 v_mfma_f32_16x16x4f32 per wave, so the epilogue hides under far more MFMA time.
 #ifndef IGAMT_SPLIT_REG
 #define IGAMT_SPLIT_REG 1
 #endif
