@@ -497,7 +497,7 @@ def bench_learned(torch, W, P, n_designs=32):
     hist = tn.train(p_train, steps=8000)
     ctrls = [W.tile_family(p).ctrl for p in p_test]
     ctrls_d = [torch.from_numpy(np.ascontiguousarray(c).ravel()).cuda() for c in ctrls]
-    t_exact, t_learn, t_est, errs, fallbacks = [], [], [], [], 0
+    t_exact, t_learn, t_est, t_dev, errs, fallbacks = [], [], [], [], [], 0
     for p, c, cd in zip(p_test, ctrls, ctrls_d):
         # exact table build (device-resident design, as the learned path gets it)
         torch.cuda.synchronize()
@@ -522,6 +522,13 @@ def bench_learned(torch, W, P, n_designs=32):
         torch.cuda.synchronize()
         t_est.append(time.perf_counter() - t0)
         fallbacks += int(gate_t.item())
+        # the same with the design already on the device, as the exact build above gets it
+        xd = tn.scale_inputs(np.atleast_2d(p))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tn.table_for_device(xd, cd)
+        torch.cuda.synchronize()
+        t_dev.append(time.perf_counter() - t0)
     # the same per-design path replayed from a HIP graph (captured on the first call)
     tn.table_for_graph(p_test[0], ctrls[0])
     torch.cuda.synchronize()
@@ -558,6 +565,8 @@ def bench_learned(torch, W, P, n_designs=32):
                         "512 training / held-out designs, POD r=64, MLP 4-128-128-64 GELU",
             "designs_timed": len(p_test), "exact_table_ms": med(t_exact), "learned_table_ms": med(t_learn),
             "learned_with_estimate_ms": med(t_est), "speedup_learned_vs_exact": med(t_exact) / med(t_learn),
+            "learned_with_estimate_device_design_ms": med(t_dev),
+            "speedup_with_estimate_device_design_vs_exact": med(t_exact) / med(t_dev),
             "speedup_with_estimate_vs_exact": med(t_exact) / med(t_est),
             "learned_with_estimate_graph_ms": med(t_graph),
             "speedup_with_estimate_graph_vs_exact": med(t_exact) / med(t_graph),

@@ -13,6 +13,7 @@
 //    Adam kernels, all FP32.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <numeric>
 #include <vector>
 
@@ -272,21 +273,29 @@ __global__ __launch_bounds__(kRowsErrThreads) void rows_error_kernel(const doubl
   __shared__ double num[T], den[T];
   table += blockIdx.x * table_dstride;
   exact += (int64_t)blockIdx.x * n_rows * K;
-  const int64_t n = (int64_t)n_rows * K;
+  const int n = n_rows * K;   // the host checks that it fits an int
+  // element i0 + u T goes to partial sum u mod 4, in ascending i0; 16 elements' loads are issued
+  // together (the table row of an element is known only after its row index has arrived)
   double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 4 * T) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += 16 * T) {
+    double x[16], y[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t i = i0 + (int64_t)u * T;
+    for (int u = 0; u < 16; ++u) {
+      const int i = i0 + u * T;
+      x[u] = y[u] = 0.0;
       if (i < n) {
-        const int64_t rr = i / K, c = i - rr * K;
+        const int rr = (int)((unsigned)i / (unsigned)K), c = i - rr * K;
         const int64_t p = rows[rr];
-        const double x = exact[i];
-        const double y = (p >= 0 && p < n_pairs) ? table[p * Kp + c] : __builtin_nan("");
-        a[u] += (y - x) * (y - x);
-        b[u] += x * x;
+        x[u] = exact[i];
+        y[u] = (p >= 0 && p < n_pairs) ? table[p * Kp + c] : __builtin_nan("");
       }
     }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (i0 + u * T < n) {
+        a[u & 3] += (y[u] - x[u]) * (y[u] - x[u]);
+        b[u & 3] += x[u] * x[u];
+      }
   }
   num[threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
   den[threadIdx.x] = (b[0] + b[1]) + (b[2] + b[3]);
@@ -312,21 +321,46 @@ __device__ inline float gelu_grad(float z) {
 // per batch row and block of outputs: the row's inputs (through GELU) are computed once into LDS,
 // then every thread sums its output in ascending i.
 constexpr int kMlpMaxWidth = 4096;
-__global__ __launch_bounds__(256) void mlp_layer_fwd(const float *__restrict__ in, int in_gelu, int batch, int fi,
-                                                     int fo, const float *__restrict__ W, const float *__restrict__ bias,
-                                                     float *__restrict__ Z, float *__restrict__ Y) {
-  __shared__ float hs[kMlpMaxWidth];
+// Forward pass of all layers, one workgroup per batch row; a layer's inputs (x, then GELU of the
+// previous layer's pre-activations) sit in LDS.  Output o of layer l is bias[o] + sum_i h[i] W[i][o],
+// summed over i in order (unrolled so that the weight loads are in flight together); Z_l is stored
+// for the backward pass, and the last layer's Z is also y.
+struct MlpLayout {
+  int n_layers, widths[9];
+  int64_t w_off[8], z_off[8];   // offsets of W_l in the parameters and of Z_l in the activations
+};
+__global__ __launch_bounds__(256) void mlp_forward_kernel(MlpLayout m, const float *__restrict__ params,
+                                                          const float *__restrict__ x, float *__restrict__ act,
+                                                          float *__restrict__ y) {
+  __shared__ float hs[2][kMlpMaxWidth];
   const int b = blockIdx.x;
-  const float *h = in + (int64_t)b * fi;
-  for (int i = threadIdx.x; i < fi; i += blockDim.x) hs[i] = in_gelu ? gelu(h[i]) : h[i];
+  for (int i = threadIdx.x; i < m.widths[0]; i += blockDim.x) hs[0][i] = x[(int64_t)b * m.widths[0] + i];
   __syncthreads();
-  const int o = blockIdx.y * blockDim.x + threadIdx.x;
-  if (o >= fo) return;
-  float z = bias[o];
-  for (int i = 0; i < fi; ++i) z += hs[i] * W[(int64_t)i * fo + o];
-  const int64_t id = (int64_t)b * fo + o;
-  Z[id] = z;
-  if (Y) Y[id] = z;
+  int cur = 0;
+  for (int l = 0; l < m.n_layers; ++l) {
+    const int fi = m.widths[l], fo = m.widths[l + 1];
+    const float *W = params + m.w_off[l], *bias = W + (int64_t)fi * fo;
+    float *Z = act + m.z_off[l] + (int64_t)b * fo;
+    const float *h = hs[cur];
+    for (int o = threadIdx.x; o < fo; o += blockDim.x) {
+      float z = bias[o];
+      const float *w = W + o;
+      int i = 0;
+      for (; i + 16 <= fi; i += 16) {
+        float wv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) wv[u] = w[(int64_t)(i + u) * fo];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) z += h[i + u] * wv[u];
+      }
+      for (; i < fi; ++i) z += h[i] * w[(int64_t)i * fo];
+      Z[o] = z;
+      if (l == m.n_layers - 1) y[(int64_t)b * fo + o] = z;
+      hs[cur ^ 1][o] = gelu(z);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
 }
 
 // dZ = dH * GELU'(Z) (or dY unchanged for the output layer)
@@ -499,6 +533,7 @@ extern "C" igamt_status igamt_table_from_pod(igamt_plan *P, const float *d_mean,
 extern "C" igamt_status igamt_table_rows_error(const igamt_plan *P, const int32_t *d_rows, int32_t n_rows,
                                                const double *d_exact, double *d_err, void *stream) {
   if (!P || !d_rows || !d_exact || !d_err || n_rows < 1) { set_error("invalid argument"); return IGAMT_EINVAL; }
+  if ((int64_t)n_rows * P->K > INT32_MAX) { set_error("too many check rows"); return IGAMT_EINVAL; }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
   hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(kRowsErrThreads), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
                      P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, 0.0, nullptr, 0);
@@ -513,6 +548,7 @@ extern "C" igamt_status igamt_table_rows_check(const igamt_plan *P, const int32_
     set_error("invalid argument");
     return IGAMT_EINVAL;
   }
+  if ((int64_t)n_rows * P->K > INT32_MAX) { set_error("too many check rows"); return IGAMT_EINVAL; }
   if (!P->dev.ready || !P->tables_ready) { set_error("tables not built"); return IGAMT_ESTATE; }
   hipLaunchKernelGGL(rows_error_kernel, dim3(1), dim3(kRowsErrThreads), 0, (hipStream_t)stream, P->dev.table, (int64_t)P->Kp,
                      P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate, 0);
@@ -528,18 +564,16 @@ extern "C" int64_t igamt_mlp_n_params(const igamt_mlp_desc *d) {
 extern "C" igamt_status igamt_mlp_forward(const igamt_mlp_desc *d, const float *d_params, const float *d_x,
                                           float *d_act, float *d_y, void *stream) {
   if (!mlp_ok(d) || !d_params || !d_x || !d_act || !d_y) { set_error("invalid MLP arguments"); return IGAMT_EINVAL; }
-  hipStream_t s = (hipStream_t)stream;
+  MlpLayout m;
+  m.n_layers = d->n_layers;
+  for (int l = 0; l <= d->n_layers; ++l) m.widths[l] = d->widths[l];
   for (int l = 0; l < d->n_layers; ++l) {
-    const int fi = d->widths[l], fo = d->widths[l + 1];
-    const float *W = d_params + param_offset(d, l);
-    const float *b = W + (int64_t)fi * fo;
-    const float *in = l == 0 ? d_x : d_act + act_offset(d, l - 1);
-    float *Z = d_act + act_offset(d, l);
-    const int block = fo <= 64 ? 64 : fo <= 128 ? 128 : 256;
-    hipLaunchKernelGGL(mlp_layer_fwd, dim3((unsigned)d->batch, (unsigned)((fo + block - 1) / block)), dim3(block), 0, s,
-                       in, l > 0 ? 1 : 0, d->batch, fi, fo, W, b, Z, l == d->n_layers - 1 ? d_y : nullptr);
-    IGAMT_LAUNCH_CHECK();
+    m.w_off[l] = param_offset(d, l);
+    m.z_off[l] = act_offset(d, l);
   }
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)d->batch), dim3(256), 0, (hipStream_t)stream, m, d_params, d_x,
+                     d_act, d_y);
+  IGAMT_LAUNCH_CHECK();
   return IGAMT_OK;
 }
 
@@ -659,6 +693,7 @@ extern "C" igamt_status igamt_tables_rows_check_batch(const igamt_plan *P, const
     set_error("invalid argument");
     return IGAMT_EINVAL;
   }
+  if ((int64_t)n_rows * P->K > INT32_MAX) { set_error("too many check rows"); return IGAMT_EINVAL; }
   hipLaunchKernelGGL(rows_error_kernel, dim3((unsigned)n_design), dim3(kRowsErrThreads), 0, (hipStream_t)stream, d_tables,
                      (int64_t)P->K, P->K, d_rows, n_rows, P->n_pairs, d_exact, d_err, tol, d_gate,
                      P->n_pairs * P->K);

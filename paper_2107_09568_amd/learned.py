@@ -256,6 +256,18 @@ class TableNet:
         b = self._buffers()
         return b["err"], b["gate"]
 
+    def table_for_device(self, x, tile_ctrl):
+        """table_for_async for a design already on the device: x its parameters scaled by
+        scale_inputs (float32 [1, 4]), tile_ctrl its tile control points (float64, n_tile_ctrl x 3
+        values).  Returns the same device tensors."""
+        torch = _torch()
+        if not (x.is_cuda and tile_ctrl.is_cuda and x.dtype == torch.float32 and tile_ctrl.dtype == torch.float64
+                and x.numel() == 4 and tile_ctrl.numel() == 3 * self.plan.n_tile_ctrl):
+            raise ValueError("x must be float32 [1, 4] and tile_ctrl float64 [n_tile_ctrl x 3], both on the device")
+        self._enqueue_learned(x.contiguous(), tile_ctrl.contiguous())
+        b = self._buffers()
+        return b["err"], b["gate"]
+
     def tables_for_batch(self, params, tile_ctrls):
         """Tables of a batch of designs (params [B, 4], tile control points as a device float64
         tensor [B, n_tile_ctrl, 3]) into a dense [B, n_pairs, n_cols] tensor: one MLP forward over
@@ -283,11 +295,14 @@ class TableNet:
                                                _ptr(err), _ptr(gate), _ptr(work), _ptr(tables), _stream()))
         return tables, err, gate
 
-    def _enqueue_learned(self):
+    def _enqueue_learned(self, x=None, ctrl=None):
         """Queue the per-design learned path on the current stream, reading the design from the
-        device buffers x and ctrl (no host work, no allocation): the MLP runs with a batch-1
-        descriptor and activation buffers of its own, which no later call reallocates."""
+        device buffers x and ctrl, or from the given device tensors (no host work, no allocation):
+        the MLP runs with a batch-1 descriptor and activation buffers of its own, which no later
+        call reallocates."""
         b = self._buffers()
+        x = b["x"] if x is None else x
+        ctrl = b["ctrl"] if ctrl is None else ctrl
         if "desc1" not in b:
             torch = _torch()
             b["desc1"] = _lib.MlpDesc()
@@ -297,8 +312,8 @@ class TableNet:
             b["desc1"].batch = 1
             b["act1"] = torch.empty(sum(self.mlp.widths[1:]), dtype=torch.float32, device="cuda")
             b["y1"] = torch.empty((1, self.mlp.widths[-1]), dtype=torch.float32, device="cuda")
-        self.plan.set_tile_ctrl(b["ctrl"])
-        check(lib().igamt_table_learned(self.plan._h, C.byref(b["desc1"]), _ptr(self.mlp.params), _ptr(b["x"]),
+        self.plan.set_tile_ctrl(ctrl)
+        check(lib().igamt_table_learned(self.plan._h, C.byref(b["desc1"]), _ptr(self.mlp.params), _ptr(x),
                                         _ptr(b["act1"]), _ptr(b["y1"]), _ptr(self.mean), _ptr(self.basis),
                                         float(self.coeff_scale), _ptr(b["rows"]), int(b["rows"].numel()),
                                         _ptr(b["exact_rows"]), float(self.tol), _ptr(b["err"]), _ptr(b["gate"]),

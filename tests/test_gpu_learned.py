@@ -281,6 +281,29 @@ def test_learned_batch_matches_per_design(family):
          f"estimated err max over learned {err_b[gate_b == 0].max().item():.2e}")
 
 
+def test_learned_device_resident_design(family):
+    """table_for_device (design already on the device) gives table_for_async's table, error
+    estimate and fallback flag bit for bit, a design that falls back included; malformed device
+    inputs are refused."""
+    torch, P, L, w, plan, tn, p_test = family
+    for i, p in enumerate(list(p_test[:3]) + [np.array([0.6, 0.6, 0.1, 0.55])]):
+        ctrl = W.tile_family(p).ctrl
+        err_a, gate_a = tn.table_for_async(p, ctrl)
+        ref, ref_err, ref_gate = plan.tables_get().clone(), err_a.clone(), gate_a.clone()
+        x = tn.scale_inputs(np.atleast_2d(p))
+        cd = torch.from_numpy(np.ascontiguousarray(ctrl, dtype=np.float64).ravel()).cuda()
+        err_d, gate_d = tn.table_for_device(x, cd)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.tables_get(), ref), i
+        assert torch.equal(err_d, ref_err) and torch.equal(gate_d, ref_gate), i
+    assert int(ref_gate.item()) == 1
+    with pytest.raises(ValueError):
+        tn.table_for_device(x.double(), cd)
+    with pytest.raises(ValueError):
+        tn.table_for_device(x, cd[:-3])
+    plan.check()
+
+
 def test_learned_graph_replay_matches_eager(family):
     """The per-design learned path replayed from a HIP graph gives, design after design, the
     eager path's table, error estimate and fallback flag bit for bit, with eager work and
