@@ -30,7 +30,9 @@ def _aniso(q, name="cfg1", **kw):
     return dataclasses.replace(w, q=q, n_fit=max(q) + 1)
 
 
-@pytest.mark.parametrize("q", [(1, 2, 3), (3, 1, 2), (0, 2, 1)])
+# (1, 1, 1) and (1, 1, 2): 72 and 108 table columns, padded to 128 (the register-table contraction's
+# 128-column shape in FP32, BF16x3 and FP16x3); (1, 2, 3), (3, 1, 2): 256; (0, 2, 1): 64
+@pytest.mark.parametrize("q", [(1, 2, 3), (3, 1, 2), (0, 2, 1), (1, 1, 1), (1, 1, 2)])
 def test_table_and_blocks_vs_oracle(env, q):
     torch, P = env
     w = _aniso(q)
